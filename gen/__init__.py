@@ -1,0 +1,14 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This package only builds matrices and right-hand sides (index arithmetic and
+random draws); it contains none of the solver's arithmetic.
+"""
+from .stencils import (  # noqa: F401
+    Problem,
+    grid_laplacian,
+    random_spd,
+    random_pattern,
+    make_config,
+    rhs,
+    CONFIG_NAMES,
+)

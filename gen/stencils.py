@@ -1,0 +1,168 @@
+"""Synthetic sparse matrices shaped like the paper's workloads.
+
+The paper measures on matrices of the University of Florida collection
+(Table 1: 0.5-1.6 million unknowns, SPD / symmetric-indefinite /
+unsymmetric).  Those matrices are not available, so structured stencil
+matrices of the same order of size stand in for them.
+
+Storage convention: compressed sparse column (CSC), 0-based, row indices
+sorted ascending inside every column, no duplicates, the FULL symmetric
+pattern (both triangles).  ``colptr`` is int64, ``rowind`` int32, values
+float64.  Grid nodes are numbered lexicographically with x fastest:
+idx = x + nx * (y + ny * z).  Out-of-grid neighbours are dropped
+(Dirichlet boundary).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+CONFIG_NAMES = {
+    1: "laplace2d_5pt_64x64",
+    2: "laplace3d_7pt_100^3_shift1e-3",
+}
+
+
+@dataclass
+class Problem:
+    n: int
+    colptr: np.ndarray  # int64 [n+1]
+    rowind: np.ndarray  # int32 [nnz]
+    values: np.ndarray  # float64 [nnz]
+    b: np.ndarray | None = None  # float64 [n, nrhs], column-major per RHS
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colptr[-1])
+
+
+def _coo_to_csc(n: int, rows: np.ndarray, cols: np.ndarray, vals: np.ndarray):
+    """Sort COO triplets into CSC (rows ascending within a column).
+
+    Duplicate (row, col) pairs are summed.
+    """
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    key = cols * n + rows
+    order = np.argsort(key, kind="stable")
+    key = key[order]
+    vals = vals[order]
+    uniq, start = np.unique(key, return_index=True)
+    summed = np.add.reduceat(vals, start) if len(vals) else vals
+    ucols = uniq // n
+    urows = uniq - ucols * n
+    colptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(colptr, ucols + 1, 1)
+    colptr = np.cumsum(colptr)
+    return colptr.astype(np.int64), urows.astype(np.int32), summed.astype(np.float64)
+
+
+def grid_laplacian(dims, diag: float | None = None, shift: float = 0.0, offdiag: float = -1.0) -> Problem:
+    """Constant-coefficient 5-point (2-D) or 7-point (3-D) Laplacian.
+
+    a_ii = 2*d + shift (d = number of dimensions) unless ``diag`` is given,
+    a_ij = ``offdiag`` for grid neighbours.  A 1-D tuple gives tridiag(-1,2,-1).
+    """
+    dims = tuple(int(d) for d in dims)
+    nd = len(dims)
+    n = int(np.prod(dims))
+    if diag is None:
+        diag = 2.0 * nd
+    diag = diag + shift
+    coords = np.indices(dims[::-1]).reshape(nd, -1)[::-1]  # coords[0] = x (fastest)
+    idx = np.arange(n, dtype=np.int64)
+    rows = [idx]
+    cols = [idx]
+    vals = [np.full(n, diag)]
+    stride = 1
+    for d in range(nd):
+        ok = coords[d] < dims[d] - 1
+        a = idx[ok]
+        bnb = a + stride
+        rows += [a, bnb]
+        cols += [bnb, a]
+        vals += [np.full(len(a), offdiag), np.full(len(a), offdiag)]
+        stride *= dims[d]
+    colptr, rowind, values = _coo_to_csc(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+    return Problem(n, colptr, rowind, values, name="laplace%dd_%s" % (nd, "x".join(map(str, dims))),
+                   meta={"dims": dims, "diag": diag, "offdiag": offdiag, "shift": shift})
+
+
+def random_pattern(n: int, density: float, seed: int):
+    """Random symmetric pattern (with the full diagonal) as CSC index arrays."""
+    rng = np.random.default_rng(seed)
+    m = max(0, int(round(density * n * (n - 1) / 2)))
+    i = rng.integers(0, n, size=m)
+    j = rng.integers(0, n, size=m)
+    keep = i != j
+    i, j = i[keep], j[keep]
+    rows = np.concatenate([i, j, np.arange(n)])
+    cols = np.concatenate([j, i, np.arange(n)])
+    colptr, rowind, _ = _coo_to_csc(n, rows, cols, np.ones(len(rows)))
+    return colptr, rowind
+
+
+def random_spd(n: int, density: float, seed: int) -> Problem:
+    """Random sparse symmetric, strictly diagonally dominant matrix (SPD).
+
+    Off-diagonal values uniform in [-1, 1]; a_ii = 1 + sum_j |a_ij|.
+    """
+    rng = np.random.default_rng(seed)
+    colptr, rowind = random_pattern(n, density, seed)
+    cols = np.repeat(np.arange(n), np.diff(colptr))
+    rows = rowind.astype(np.int64)
+    upper = rows < cols
+    vals = np.zeros(len(rows))
+    # draw one value per unordered pair (stored at the upper entry), mirror it
+    vu = rng.uniform(-1.0, 1.0, size=int(upper.sum()))
+    vals[upper] = vu
+    # mirror: entry (r, c) lower gets value of (c, r) upper
+    key_up = cols[upper] * n + rows[upper]          # key of (row=c', col=...) ordering
+    lower = rows > cols
+    key_lo = rows[lower] * n + cols[lower]          # transpose key matches upper's (col, row)
+    order = np.argsort(key_up)
+    pos = np.searchsorted(key_up[order], key_lo)
+    vals[lower] = vu[order][pos]
+    offsum = np.zeros(n)
+    np.add.at(offsum, cols[rows != cols], np.abs(vals[rows != cols]))
+    diag = rows == cols
+    vals[diag] = 1.0 + offsum[cols[diag]]
+    return Problem(n, colptr, rowind, vals, name="random_spd_n%d_s%d" % (n, seed),
+                   meta={"density": density, "seed": seed})
+
+
+def rhs(n: int, nrhs: int, seed: int) -> np.ndarray:
+    """Right-hand sides uniform in [-1, 1], drawn as (nrhs, n) then transposed.
+
+    Returned as a Fortran-ordered (n, nrhs) array: column r is RHS r.
+    """
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.uniform(-1.0, 1.0, size=(nrhs, n)).T)
+
+
+def make_config(i: int, seed: int | None = None) -> Problem:
+    """The benchmark workloads.
+
+    1: 2-D 5-point Laplacian on a 64x64 grid, a_ii = 4, a_ij = -1, one RHS.
+    2: 3-D 7-point Laplacian on a 100^3 grid plus a diagonal shift 1e-3, one RHS.
+    The right-hand side seed is 1000 + i unless ``seed`` is given.
+    """
+    if seed is None:
+        seed = 1000 + i
+    if i == 1:
+        p = grid_laplacian((64, 64))
+        nrhs = 1
+    elif i == 2:
+        p = grid_laplacian((100, 100, 100), shift=1e-3)
+        nrhs = 1
+    else:
+        raise ValueError("unknown config %r" % (i,))
+    p.b = rhs(p.n, nrhs, seed)
+    p.name = CONFIG_NAMES[i]
+    p.meta["config"] = i
+    p.meta["seed"] = seed
+    return p
