@@ -1,0 +1,178 @@
+/*
+ * spx.h - C ABI of an MI355X (gfx950) supernodal sparse Cholesky solver.
+ *
+ * The operation is the one of "Taking advantage of hybrid systems for sparse
+ * direct solvers via task-based runtimes" (Lacoste et al.), Section III:
+ * solve A x = b for a sparse symmetric positive definite A by
+ *   1. an ordering by nested dissection and a symbolic analysis (elimination
+ *      tree, predicted nonzero pattern of the factor grouped into column
+ *      blocks, amalgamation allowing extra fill, vertical splitting of wide
+ *      supernodes)                                   -> spx_analyze
+ *   2. the numerical supernodal factorization P A P^T = L L^T: per column
+ *      block, dense factorization of the diagonal block, triangular solve of
+ *      the off-diagonal rows, and right-looking updates of the facing column
+ *      blocks (Section III, the "1D task" and its split into one task per
+ *      panel and one per couple of panels)          -> spx_factorize
+ *   3. forward and backward triangular solves with the factor, followed by
+ *      iterative refinement with an FP64 residual   -> spx_solve
+ * Static pivoting (no dynamic pivoting, Section III) makes the structure
+ * depend on the pattern only, so one analysis serves many factorizations and
+ * one factorization many solves.
+ *
+ * Conventions.  Indices are 0-based.  A matrix pattern is given in compressed
+ * sparse column form: colptr[n+1] (int64, non-decreasing, colptr[0] = 0) and
+ * rowind[colptr[n]] (int32, strictly increasing inside a column, in [0, n)).
+ * Either the full symmetric pattern or only its lower triangle may be given;
+ * the pattern is symmetrized internally.  Values passed to spx_factorize are
+ * aligned with that pattern; only entries with row >= column are read.
+ *
+ * Errors.  Every function returns SPX_OK (0) or a negative code; the text of
+ * the last error of a handle is available from spx_last_error.  No function
+ * throws.  A handle must not be used by two threads at once.  Calls that take
+ * a hip_stream (a hipStream_t, or NULL for the default stream) enqueue their
+ * device work on that stream and return when it has finished.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum spx_status {
+    SPX_OK = 0,
+    SPX_EINVAL = -1,   /* bad argument, bad pattern (unsorted, out of range, duplicate) */
+    SPX_ENOMEM = -2,   /* host or device allocation failed */
+    SPX_EDEVICE = -3,  /* a HIP runtime call failed, or the device scheduler stopped early */
+    SPX_ESTATE = -4,   /* call out of order (e.g. solve before factorize) */
+    SPX_ENOTPD = -5,   /* a pivot was not > 0 (or NaN): matrix not positive definite */
+    SPX_ENOCONV = -6   /* refinement did not reach the tolerance; x is still returned */
+};
+
+enum spx_method { SPX_LLT = 0 };
+
+enum spx_precision {
+    SPX_FP64 = 0      /* factor stored and computed in FP64 */
+};
+
+typedef struct spx_options {
+    int32_t method;           /* SPX_LLT */
+    int32_t leaf_size;        /* nested dissection stops at components of this size (64) */
+    int32_t amalg_pct;        /* extra fill allowed by amalgamation, percent of nnz(L) (12) */
+    int32_t split_width;      /* column blocks wider than this are split (256, at most 256) */
+    const int32_t* user_perm; /* optional ordering (new -> old) replacing nested dissection */
+    int32_t precision;        /* enum spx_precision */
+    int32_t ir_max_iter;      /* refinement steps after the first solve (2) */
+    double ir_tol;            /* componentwise backward error target (1e-14) */
+} spx_options;
+
+typedef struct spx_info {
+    int32_t n;
+    int32_t ncblk;            /* column blocks after splitting */
+    int32_t nblok;            /* blocks, diagonal blocks included */
+    int32_t nsnode;           /* supernodes after amalgamation */
+    int64_t nnz_a;            /* entries of the input pattern */
+    int64_t nnz_l;            /* exact nonzeros of L (column counts summed) */
+    int64_t nnz_l_stored;     /* nonzeros of the block structure (after amalgamation) */
+    int64_t panel_entries;    /* size of the panel storage (diagonal blocks stored square) */
+    double flops_alg;         /* sum of squared exact column counts */
+    double flops_exec;        /* the same on the amalgamated structure */
+    int64_t ntasks;           /* device scheduler work items per factorization */
+    int32_t fail_col;         /* after SPX_ENOTPD: failing column, original numbering */
+    int32_t factorized;       /* 1 once a factorization succeeded */
+    double logdet;            /* log det A after a factorization */
+    double factor_kernel_ms;  /* last factorization: scheduler kernel time (HIP events) */
+    double assemble_ms;       /* last factorization: assembly kernel time */
+} spx_info;
+
+typedef struct spx_solve_info {
+    int32_t ir_iters;         /* refinement steps taken */
+    int32_t converged;        /* omega <= ir_tol */
+    double omega;             /* componentwise backward error max_i |b-Ax|_i / (|A||x|+|b|)_i */
+    double eta;               /* normwise backward error */
+} spx_solve_info;
+
+/* Read-only views of the symbolic structure, valid until spx_destroy.
+ * Column blocks ("cblk") are ranges of consecutive columns in the new
+ * numbering; each owns a dense column-major panel with leading dimension
+ * stride[k]: the w x w diagonal block first, then its off-diagonal blocks. */
+typedef struct spx_symbolic_view {
+    int32_t n, ncblk, nblok, nsnode, nupd;
+    const int32_t* perm;      /* [n] new -> old */
+    const int32_t* iperm;     /* [n] old -> new */
+    const int32_t* etree;     /* [n] column elimination tree, new numbering, -1 = root */
+    const int32_t* snptr;     /* [nsnode+1] first column of every supernode */
+    const int32_t* fcol;      /* [ncblk] first column */
+    const int32_t* lcol;      /* [ncblk] last column (inclusive) */
+    const int32_t* stride;    /* [ncblk] rows of the panel */
+    const int64_t* panel_off; /* [ncblk+1] offset of the panel in the factor storage */
+    const int32_t* bptr;      /* [ncblk+1] first block of each cblk (its diagonal block) */
+    const int32_t* cparent;   /* [ncblk] first facing cblk, -1 if none */
+    const int32_t* frow;      /* [nblok] first row */
+    const int32_t* lrow;      /* [nblok] last row (inclusive) */
+    const int32_t* fcblk;     /* [nblok] facing cblk (whose columns hold these rows) */
+    const int32_t* coefind;   /* [nblok] row offset inside the owning panel */
+    const int32_t* uptr;      /* [ncblk+1] update targets of cblk k: utgt[uptr[k]..uptr[k+1]) */
+    const int32_t* utgt;      /* [nupd] facing cblks, ascending */
+    const int32_t* dep;       /* [ncblk] number of cblks updating each cblk */
+} spx_symbolic_view;
+
+/* Opaque problem handle: symbolic plan, device task tables, factor. */
+typedef struct spx_handle spx_handle;
+
+/* Fill *opt with the defaults listed above. */
+void spx_default_options(spx_options* opt);
+
+/* Ordering and symbolic analysis on the host (Section III).  Inputs are host
+ * pointers, copied and not retained.  opt may be NULL (defaults).  On success
+ * *out owns all host and device memory of the problem (the plan is uploaded
+ * to the current HIP device).  Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE. */
+int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind,
+                const spx_options* opt, spx_handle** out);
+
+/* Numerical factorization (Section III and V: diagonal factorization,
+ * panel triangular solve, sparse-GEMM updates scattered into the facing
+ * panels), scheduled on the GPU by a device-side ready queue.
+ * values: colptr[n] doubles aligned with the analysed pattern; a device
+ * pointer if values_on_device, else a host pointer; not retained.
+ * Errors: SPX_ESTATE (no analysis), SPX_ENOTPD (fail_col in spx_info),
+ * SPX_EDEVICE.  May be called again with new values. */
+int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device, void* hip_stream);
+
+/* Solve A X = B for nrhs right-hand sides stored column-major with leading
+ * dimension ldb >= n; B is overwritten with X.  b is a device pointer if
+ * b_on_device, else a host pointer.  Runs the forward and backward sweeps,
+ * then FP64 refinement until omega <= ir_tol or ir_max_iter steps.
+ * info may be NULL.  Errors: SPX_ESTATE, SPX_EINVAL, SPX_ENOCONV, SPX_EDEVICE. */
+int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_device,
+              spx_solve_info* info, void* hip_stream);
+
+/* Statistics of the analysis and of the last factorization. */
+int spx_get_info(const spx_handle* h, spx_info* info);
+
+/* Views of the symbolic arrays (bit-exact comparison with an independent
+ * analysis). */
+int spx_export_symbolic(const spx_handle* h, spx_symbolic_view* view);
+
+/* Copy the factor panels (panel_entries doubles, layout of the symbolic
+ * view; the strict upper triangle of diagonal blocks is zero) to dst, a host
+ * or device pointer.  Errors: SPX_ESTATE before a factorization. */
+int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip_stream);
+
+/* Free everything owned by the handle.  NULL is allowed. */
+void spx_destroy(spx_handle* h);
+
+/* Static description of a status code. */
+const char* spx_strerror(int status);
+
+/* Text of the last error raised on h ("" if none); valid until the next call.
+ * With h == NULL: the message of the last failed spx_analyze of this thread. */
+const char* spx_last_error(const spx_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPX_H */

@@ -67,6 +67,8 @@ def _load():
     L.orc_assemble.argtypes = [vp, vp, vp, vp, vp]
     L.orc_factor.restype = C.c_int
     L.orc_factor.argtypes = [vp, vp, C.POINTER(i32)]
+    L.orc_factor_upto.restype = C.c_int
+    L.orc_factor_upto.argtypes = [vp, vp, i32, C.POINTER(i32)]
     L.orc_solve.restype = C.c_int
     L.orc_solve.argtypes = [vp, vp, i32, vp, i64, vp, i64]
     L.orc_residual.restype = None
@@ -146,7 +148,7 @@ _ARRAYS = [
     ("stride", np.int32, "ncblk"), ("panel_off", np.int64, "ncblk+1"), ("bptr", np.int32, "ncblk+1"),
     ("cparent", np.int32, "ncblk"), ("frow", np.int32, "nblok"), ("lrow", np.int32, "nblok"),
     ("fcblk", np.int32, "nblok"), ("coefind", np.int32, "nblok"), ("uptr", np.int32, "ncblk+1"),
-    ("utgt", np.int32, "nupd"), ("dep", np.int32, "ncblk"),
+    ("utgt", np.int32, "nupd"), ("dep", np.int32, "ncblk"), ("colcount", np.int64, "n"),
 ]
 
 
@@ -229,6 +231,20 @@ def factor(sym: Symbolic, colptr, rowind, values):
         raise NotPositiveDefinite(fc.value, int(sym.perm[fc.value]))
     if rc != 0:
         raise RuntimeError("orc_factor failed %d" % rc)
+    return P
+
+
+def factor_upto(sym: Symbolic, colptr, rowind, values, kend):
+    """Assemble, then process column blocks 0..kend-1 only; those panels hold
+    their final values afterwards (each block is updated by smaller ones)."""
+    L = _load()
+    P = assemble(sym, colptr, rowind, values)
+    fc = C.c_int32(-1)
+    rc = L.orc_factor_upto(C.c_void_p(sym.handle), _p(P), int(kend), C.byref(fc))
+    if rc == ENOTPD:
+        raise NotPositiveDefinite(fc.value, int(sym.perm[fc.value]))
+    if rc != 0:
+        raise RuntimeError("orc_factor_upto failed %d" % rc)
     return P
 
 

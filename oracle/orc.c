@@ -382,6 +382,7 @@ typedef struct {
     i64 nupd;
     i64 nnz_exact, nnz_amalg, zeros_used, budget, panel_size;
     double flops_alg, flops_exec;
+    i64* colcount; /* exact column counts (diagonal included), final numbering */
 } orc_sym;
 
 void orc_free(orc_sym* s)
@@ -390,7 +391,7 @@ void orc_free(orc_sym* s)
     free(s->perm); free(s->iperm); free(s->etree); free(s->snptr);
     free(s->fcol); free(s->lcol); free(s->stride); free(s->panel_off); free(s->bptr); free(s->cparent);
     free(s->frow); free(s->lrow); free(s->fcblk); free(s->coefind);
-    free(s->uptr); free(s->utgt); free(s->dep);
+    free(s->uptr); free(s->utgt); free(s->dep); free(s->colcount);
     free(s);
 }
 
@@ -606,6 +607,8 @@ int orc_analyze(i32 n, const i64* colptr, const i32* rowind, i32 leaf, i32 amalg
     s->snptr[nsn] = col;
     for (i32 k = 0; k < n; k++) s->iperm[s->perm[k]] = k;
     s->etree = (i32*)malloc(sizeof(i32) * ((size_t)n + 1));
+    s->colcount = (i64*)malloc(sizeof(i64) * ((size_t)n + 1));
+    for (i32 j = 0; j < n; j++) s->colcount[lab3to4[j]] = eta[j];
     for (i32 j = 0; j < n; j++) {
         i32 pj = par1[j];
         s->etree[lab3to4[j]] = pj < 0 ? -1 : lab3to4[pj];
@@ -771,6 +774,7 @@ int orc_sym_copy(const orc_sym* s, int what, void* dst)
     case 14: memcpy(dst, s->uptr, 4 * (nc + 1)); break;
     case 15: memcpy(dst, s->utgt, 4 * (size_t)s->nupd); break;
     case 16: memcpy(dst, s->dep, 4 * nc); break;
+    case 17: memcpy(dst, s->colcount, 8 * n); break;
     default: return ORC_EINVAL;
     }
     return ORC_OK;
@@ -827,15 +831,22 @@ int orc_assemble(const orc_sym* s, const i64* colptr, const i32* rowind, const d
  *      triangle of j's diagonal block is touched.
  * Returns ORC_ENOTPD and the failing column (final numbering) on breakdown.
  */
-int orc_factor(const orc_sym* s, double* P, i32* fail_col)
+int orc_factor_upto(const orc_sym* s, double* P, i32 kend, i32* fail_col);
+
+int orc_factor(const orc_sym* s, double* P, i32* fail_col) { return orc_factor_upto(s, P, s->ncblk, fail_col); }
+
+/* Column blocks 0..kend-1 only: after it they hold their final values (every
+ * update into them comes from a smaller block). */
+int orc_factor_upto(const orc_sym* s, double* P, i32 kend, i32* fail_col)
 {
     *fail_col = -1;
+    if (kend > s->ncblk) kend = s->ncblk;
     i32 maxs = 0;
     for (i32 k = 0; k < s->ncblk; k++) if (s->stride[k] > maxs) maxs = s->stride[k];
     double* W = (double*)malloc(sizeof(double) * (size_t)maxs * (size_t)maxs + 8);
     i32* grow = (i32*)malloc(sizeof(i32) * ((size_t)maxs + 1));
     if (!W || !grow) return ORC_ENOMEM;
-    for (i32 k = 0; k < s->ncblk; k++) {
+    for (i32 k = 0; k < kend; k++) {
         i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k];
         double* L = P + s->panel_off[k];
         /* global row of each panel row */

@@ -1,0 +1,680 @@
+// C ABI of the solver (declared in include/spx.h): handle life cycle, upload
+// of the symbolic plan, construction of the device task tables and level
+// lists, and the host drivers of factorization, solve and refinement.
+#include "../../include/spx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "plan.hpp"
+
+namespace spx {
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_assemble(double* panels, const int64_t* amap, const double* values, int64_t nnz, hipStream_t s);
+hipError_t launch_sched_init(int32_t* queue, int32_t total, const int32_t* ready, int32_t nready, int32_t* fact_dep,
+                             const int32_t* fact_dep0, int32_t* trsm_left, const int32_t* trsm_count, int32_t ncblk,
+                             int32_t* qhead, int32_t* qtail, int32_t* status, hipStream_t s);
+int sched_blocks_per_cu();
+hipError_t launch_sched(const SchedArgs& a, int grid, hipStream_t s);
+hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
+hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
+hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
+hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
+hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,
+                             hipStream_t s);
+hipError_t launch_permute_out(double* x, int64_t ldx, const double* y, const int32_t* perm, int32_t n, int32_t nrhs,
+                              hipStream_t s);
+hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s);
+hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const int64_t* rval, const double* vals,
+                           const double* x, const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
+                           unsigned long long* stats, hipStream_t s);
+
+struct DeviceError : std::runtime_error {
+    explicit DeviceError(const std::string& s) : std::runtime_error(s) {}
+};
+struct StatusError : std::runtime_error {
+    int code;
+    StatusError(int c, const std::string& s) : std::runtime_error(s), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                                    \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) throw DeviceError(std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// Owned device allocation.
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count)
+    {
+        if (count <= n && p) return;
+        release();
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (hipMalloc(reinterpret_cast<void**>(&p), bytes) != hipSuccess) {
+            p = nullptr;
+            throw std::bad_alloc();
+        }
+        n = count;
+    }
+    void upload(const std::vector<T>& v)
+    {
+        alloc(v.size());
+        if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+};
+
+struct Level {
+    std::vector<int32_t> cptr;   // cblks of level l: cblk[cptr[l]..cptr[l+1])
+    std::vector<int32_t> cblk;
+    std::vector<int32_t> kptr;   // chunks of level l
+    std::vector<int2> chunk;
+};
+
+}  // namespace spx
+
+using namespace spx;
+
+struct spx_handle {
+    Plan plan;
+    spx_options opt{};
+    std::string err;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    // device plan
+    DevBuf<int32_t> fcol, lcol, stride, bptr, frow, lrow, coefind, perm;
+    DevBuf<int64_t> panel_off, dinv_off;
+    DevBuf<int64_t> amap, rptr, rval;
+    DevBuf<int32_t> rcol;
+    DevBuf<int32_t> rowg;
+    DevBuf<int64_t> rowg_off;
+    // scheduler tables
+    int32_t total = 0, nready = 0;
+    DevBuf<int4> desc;
+    DevBuf<int32_t> trsm_first, trsm_count, upd_first, upd_count, fact_dep0, fact_dep, trsm_left, queue, ready, qctr,
+        status;
+    // levels for the sweeps
+    Level lv;
+    DevBuf<int32_t> lv_cblk;
+    DevBuf<int2> lv_chunk;
+    // numeric
+    DevBuf<double> panels, dinv, vals;
+    int64_t dinv_size = 0;
+    bool factorized = false;
+    int32_t fail_col = -1;
+    bool logdet_valid = false;
+    double logdet = 0.0;
+    double factor_ms = 0.0, assemble_ms = 0.0;
+    // solve work
+    DevBuf<double> y, tacc, xw, rw, bw;
+    DevBuf<unsigned long long> stats;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int device = 0;
+    int grid = 0;
+    int64_t timeout_ticks = 0;
+    bool uploaded = false;
+
+    ~spx_handle()
+    {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+
+    DevPlan devplan() const
+    {
+        DevPlan d;
+        d.ncblk = plan.ncblk;
+        d.fcol = fcol.p;
+        d.lcol = lcol.p;
+        d.stride = stride.p;
+        d.panel_off = panel_off.p;
+        d.bptr = bptr.p;
+        d.frow = frow.p;
+        d.lrow = lrow.p;
+        d.coefind = coefind.p;
+        d.dinv_off = dinv_off.p;
+        return d;
+    }
+};
+
+namespace {
+
+thread_local std::string g_analyze_err;   // message of the last failed spx_analyze in this thread
+
+int fail(spx_handle* h, int code, const std::string& msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+template <class F>
+int guarded(spx_handle* h, F&& f)
+{
+    try {
+        return f();
+    } catch (const InvalidArgument& e) {
+        return fail(h, SPX_EINVAL, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(h, SPX_ENOMEM, "out of memory");
+    } catch (const StatusError& e) {
+        return fail(h, e.code, e.what());
+    } catch (const DeviceError& e) {
+        return fail(h, SPX_EDEVICE, e.what());
+    } catch (const std::exception& e) {
+        return fail(h, SPX_EDEVICE, e.what());
+    } catch (...) {
+        return fail(h, SPX_EDEVICE, "unknown error");
+    }
+}
+
+// Work items of the device scheduler, in queue-id order: FACT(k) = k, then
+// per cblk its TRSM row tiles, then per cblk its UPDATE tiles (targets
+// ascending, then row tiles, then column tiles).  Tiles that lie entirely in
+// the strict upper triangle of a target's diagonal block are not generated.
+void build_tasks(spx_handle* h)
+{
+    const Plan& P = h->plan;
+    const int32_t nc = P.ncblk;
+    constexpr int kTrsmRows = 128;
+    std::vector<int4> desc;
+    desc.reserve(static_cast<size_t>(nc) * 2);
+    std::vector<int32_t> tf(nc), tc(nc), uf(nc), uc(nc), dep(nc, 0);
+    for (int32_t k = 0; k < nc; ++k) {
+        desc.push_back(int4{kFact, k, 0, 0});
+        desc.push_back(int4{0, 0, 0, 0});
+    }
+    int32_t id = nc;
+    for (int32_t k = 0; k < nc; ++k) {
+        const int32_t w = P.lcol[k] - P.fcol[k] + 1, ld = P.stride[k];
+        tf[k] = id;
+        for (int32_t r = w; r < ld; r += kTrsmRows) {
+            desc.push_back(int4{kTrsm, k, r, std::min(kTrsmRows, ld - r)});
+            desc.push_back(int4{0, 0, 0, 0});
+            ++id;
+        }
+        tc[k] = id - tf[k];
+    }
+    for (int32_t k = 0; k < nc; ++k) {
+        const int32_t ld = P.stride[k];
+        uf[k] = id;
+        for (int32_t b = P.bptr[k] + 1; b < P.bptr[k + 1];) {
+            const int32_t j = P.fcblk[b];
+            int32_t b2 = b;
+            while (b2 < P.bptr[k + 1] && P.fcblk[b2] == j) ++b2;
+            const int32_t rs = P.coefind[b];
+            const int32_t re = P.coefind[b2 - 1] + (P.lrow[b2 - 1] - P.frow[b2 - 1] + 1);
+            for (int32_t r0 = rs; r0 < ld; r0 += kTile) {
+                const int32_t mr = std::min(kTile, ld - r0);
+                for (int32_t c0 = rs; c0 < re; c0 += kTile) {
+                    if (r0 + mr - 1 < c0) continue;   // strictly above the diagonal of j
+                    const int32_t ncl = std::min(kTile, re - c0);
+                    desc.push_back(int4{kUpdate, k, j, r0});
+                    desc.push_back(int4{c0, ncl, mr, 0});
+                    ++dep[j];
+                    ++id;
+                }
+            }
+            b = b2;
+        }
+        uc[k] = id - uf[k];
+    }
+    h->total = id;
+    std::vector<int32_t> ready;
+    for (int32_t k = 0; k < nc; ++k)
+        if (dep[k] == 0) ready.push_back(k);
+    h->nready = static_cast<int32_t>(ready.size());
+    h->desc.upload(desc);
+    h->trsm_first.upload(tf);
+    h->trsm_count.upload(tc);
+    h->upd_first.upload(uf);
+    h->upd_count.upload(uc);
+    h->fact_dep0.upload(dep);
+    h->fact_dep.alloc(nc);
+    h->trsm_left.alloc(nc);
+    h->queue.alloc(static_cast<size_t>(h->total));
+    h->ready.upload(ready);
+    h->qctr.alloc(2);
+    h->status.alloc(4);
+}
+
+// Dependency levels for the sweeps: level(k) = 1 + max level of the cblks
+// updating k.  Off-diagonal rows are cut into chunks of 256 rows.
+void build_levels(spx_handle* h)
+{
+    const Plan& P = h->plan;
+    const int32_t nc = P.ncblk;
+    std::vector<int32_t> lvl(nc, 0);
+    int32_t nl = nc > 0 ? 1 : 0;
+    for (int32_t k = 0; k < nc; ++k) {
+        for (int32_t q = P.uptr[k]; q < P.uptr[k + 1]; ++q) {
+            const int32_t j = P.utgt[q];
+            lvl[j] = std::max(lvl[j], lvl[k] + 1);
+        }
+        nl = std::max(nl, lvl[k] + 1);
+    }
+    Level& L = h->lv;
+    L = Level();
+    L.cptr.assign(nl + 1, 0);
+    for (int32_t k = 0; k < nc; ++k) ++L.cptr[lvl[k] + 1];
+    for (int32_t l = 0; l < nl; ++l) L.cptr[l + 1] += L.cptr[l];
+    L.cblk.resize(nc);
+    std::vector<int32_t> pos(L.cptr.begin(), L.cptr.end() - 1);
+    for (int32_t k = 0; k < nc; ++k) L.cblk[pos[lvl[k]]++] = k;
+    L.kptr.assign(nl + 1, 0);
+    for (int32_t l = 0; l < nl; ++l) {
+        for (int32_t q = L.cptr[l]; q < L.cptr[l + 1]; ++q) {
+            const int32_t k = L.cblk[q];
+            const int32_t w = P.lcol[k] - P.fcol[k] + 1;
+            for (int32_t r = w; r < P.stride[k]; r += 256) L.chunk.push_back(int2{k, r});
+        }
+        L.kptr[l + 1] = static_cast<int32_t>(L.chunk.size());
+    }
+    h->lv_cblk.upload(L.cblk);
+    h->lv_chunk.upload(L.chunk);
+}
+
+void upload_plan(spx_handle* h)
+{
+    const Plan& P = h->plan;
+    h->uploaded = true;
+    HIPCHK(hipGetDevice(&h->device));
+    h->fcol.upload(P.fcol);
+    h->lcol.upload(P.lcol);
+    h->stride.upload(P.stride);
+    h->bptr.upload(P.bptr);
+    h->frow.upload(P.frow);
+    h->lrow.upload(P.lrow);
+    h->coefind.upload(P.coefind);
+    h->perm.upload(P.perm);
+    h->panel_off.upload(P.panel_off);
+    std::vector<int64_t> doff(static_cast<size_t>(P.ncblk) + 1, 0);
+    for (int32_t k = 0; k < P.ncblk; ++k) {
+        const int64_t w = P.lcol[k] - P.fcol[k] + 1;
+        doff[k + 1] = doff[k] + ((w + kNB - 1) / kNB) * kNB * kNB;
+    }
+    h->dinv_size = doff[P.ncblk];
+    h->dinv_off.upload(doff);
+    h->amap.upload(P.amap);
+    h->rptr.upload(P.rptr);
+    h->rcol.upload(P.rcol);
+    h->rval.upload(P.rval);
+    // global rows of the off-diagonal panel rows
+    std::vector<int32_t> rg;
+    std::vector<int64_t> rgo(static_cast<size_t>(P.ncblk) + 1, 0);
+    for (int32_t k = 0; k < P.ncblk; ++k) {
+        rgo[k] = static_cast<int64_t>(rg.size());
+        for (int32_t b = P.bptr[k] + 1; b < P.bptr[k + 1]; ++b)
+            for (int32_t r = P.frow[b]; r <= P.lrow[b]; ++r) rg.push_back(r);
+    }
+    rgo[P.ncblk] = static_cast<int64_t>(rg.size());
+    h->rowg.upload(rg);
+    h->rowg_off.upload(rgo);
+    build_tasks(h);
+    build_levels(h);
+    for (auto& e : h->ev)
+        if (!e) HIPCHK(hipEventCreate(&e));
+    int ncu = 0, clk_khz = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+    if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess || clk_khz <= 0)
+        clk_khz = 100000;
+    h->grid = std::max(1, ncu * sched_blocks_per_cu());
+    h->timeout_ticks = static_cast<int64_t>(clk_khz) * 1000 * 20;   // 20 s per wait
+}
+
+void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
+{
+    SweepArgs a;
+    a.pl = h->devplan();
+    a.panels = h->panels.p;
+    a.dinv = h->dinv.p;
+    a.rowg = h->rowg.p;
+    a.rowg_off = h->rowg_off.p;
+    a.y = y;
+    a.tacc = h->tacc.p;
+    a.n = h->n;
+    a.nrhs = nrhs;
+    const Level& L = h->lv;
+    const int nl = static_cast<int>(L.cptr.size()) - 1;
+    for (int l = 0; l < nl; ++l) {
+        HIPCHK(launch_fwd_diag(a, h->lv_cblk.p + L.cptr[l], L.cptr[l + 1] - L.cptr[l], s));
+        HIPCHK(launch_fwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
+    }
+    HIPCHK(launch_fill_f64(h->tacc.p, static_cast<int64_t>(h->n) * nrhs, 0.0, s));
+    for (int l = nl - 1; l >= 0; --l) {
+        HIPCHK(launch_bwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
+        HIPCHK(launch_bwd_diag(a, h->lv_cblk.p + L.cptr[l], L.cptr[l + 1] - L.cptr[l], s));
+    }
+}
+
+double pairwise_sum(const double* v, int64_t n)
+{
+    if (n <= 8) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += v[i];
+        return s;
+    }
+    const int64_t m = n / 2;
+    return pairwise_sum(v, m) + pairwise_sum(v + m, n - m);
+}
+
+}  // namespace
+
+extern "C" {
+
+void spx_default_options(spx_options* o)
+{
+    if (!o) return;
+    o->method = SPX_LLT;
+    o->leaf_size = 64;
+    o->amalg_pct = 12;
+    o->split_width = 256;
+    o->user_perm = nullptr;
+    o->precision = SPX_FP64;
+    o->ir_max_iter = 2;
+    o->ir_tol = 1e-14;
+}
+
+int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const spx_options* opt, spx_handle** out)
+{
+    if (!out) return SPX_EINVAL;
+    *out = nullptr;
+    if (n < 0 || (n > 0 && (!colptr || !rowind))) return SPX_EINVAL;
+    spx_handle* h = nullptr;
+    try {
+        h = new spx_handle();
+    } catch (...) {
+        return SPX_ENOMEM;
+    }
+    if (opt) h->opt = *opt; else spx_default_options(&h->opt);
+    int rc = guarded(h, [&]() -> int {
+        if (h->opt.method != SPX_LLT) throw InvalidArgument("only SPX_LLT is supported");
+        if (h->opt.precision != SPX_FP64) throw InvalidArgument("unsupported precision");
+        if (h->opt.ir_max_iter < 0) throw InvalidArgument("ir_max_iter must be >= 0");
+        Options o;
+        o.leaf_size = h->opt.leaf_size;
+        o.amalg_pct = h->opt.amalg_pct;
+        o.split_width = h->opt.split_width;
+        o.user_perm = h->opt.user_perm;
+        analyze_pattern(n, colptr, rowind, o, h->plan);
+        h->n = n;
+        h->nnz = n > 0 ? colptr[n] : 0;
+        h->opt.user_perm = nullptr;
+        // upload now when a device is present; a host-only process (symbolic
+        // work only) defers it to the first factorization
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) upload_plan(h);
+        return SPX_OK;
+    });
+    if (rc != SPX_OK) {
+        g_analyze_err = h->err;
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return SPX_OK;
+}
+
+int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device, void* hip_stream)
+{
+    if (!h) return SPX_EINVAL;
+    return guarded(h, [&]() -> int {
+        if (h->nnz > 0 && !values) throw InvalidArgument("values is NULL");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        const Plan& P = h->plan;
+        if (!h->uploaded) upload_plan(h);
+        h->factorized = false;
+        h->logdet_valid = false;
+        h->fail_col = -1;
+        h->vals.alloc(static_cast<size_t>(h->nnz));
+        if (h->nnz > 0)
+            HIPCHK(hipMemcpyAsync(h->vals.p, values, h->nnz * sizeof(double),
+                                  values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        h->panels.alloc(static_cast<size_t>(P.panel_entries));
+        h->dinv.alloc(static_cast<size_t>(h->dinv_size));
+        HIPCHK(hipEventRecord(h->ev[0], s));
+        HIPCHK(launch_fill_f64(h->panels.p, P.panel_entries, 0.0, s));
+        HIPCHK(launch_assemble(h->panels.p, h->amap.p, h->vals.p, h->nnz, s));
+        HIPCHK(launch_sched_init(h->queue.p, h->total, h->ready.p, h->nready, h->fact_dep.p, h->fact_dep0.p,
+                                 h->trsm_left.p, h->trsm_count.p, P.ncblk, h->qctr.p, h->qctr.p + 1, h->status.p, s));
+        HIPCHK(hipEventRecord(h->ev[1], s));
+        if (h->total > 0) {
+            SchedArgs a;
+            a.pl = h->devplan();
+            a.panels = h->panels.p;
+            a.dinv = h->dinv.p;
+            a.desc = h->desc.p;
+            a.total = h->total;
+            a.trsm_first = h->trsm_first.p;
+            a.trsm_count = h->trsm_count.p;
+            a.upd_first = h->upd_first.p;
+            a.upd_count = h->upd_count.p;
+            a.fact_dep = h->fact_dep.p;
+            a.trsm_left = h->trsm_left.p;
+            a.queue = h->queue.p;
+            a.qhead = h->qctr.p;
+            a.qtail = h->qctr.p + 1;
+            a.status = h->status.p;
+            a.timeout_ticks = h->timeout_ticks;
+            HIPCHK(launch_sched(a, h->grid, s));
+        }
+        HIPCHK(hipEventRecord(h->ev[2], s));
+        int32_t st[4] = {INT_MAX, 0, 0, 0};
+        HIPCHK(hipMemcpyAsync(st, h->status.p, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        float ms0 = 0.f, ms1 = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms0, h->ev[0], h->ev[1]));
+        HIPCHK(hipEventElapsedTime(&ms1, h->ev[1], h->ev[2]));
+        h->assemble_ms = ms0;
+        h->factor_ms = ms1;
+        if (h->total > 0 && (st[1] != 0 || st[2] != h->total)) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "device scheduler stopped early (%d of %d items, abort=%d)", st[2], h->total,
+                          st[1]);
+            throw DeviceError(buf);
+        }
+        if (st[0] != INT_MAX) {
+            h->fail_col = (st[0] >= 0 && st[0] < h->n) ? P.perm[st[0]] : st[0];
+            throw StatusError(SPX_ENOTPD, "pivot not positive at column " + std::to_string(h->fail_col));
+        }
+        h->factorized = true;
+        return SPX_OK;
+    });
+}
+
+int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_device, spx_solve_info* info,
+              void* hip_stream)
+{
+    if (!h) return SPX_EINVAL;
+    return guarded(h, [&]() -> int {
+        if (!h->factorized) throw StatusError(SPX_ESTATE, "solve called without a successful factorization");
+        if (nrhs < 0 || ldb < h->n || (nrhs > 0 && h->n > 0 && !b)) throw InvalidArgument("bad right-hand side");
+        if (info) *info = spx_solve_info{0, 1, 0.0, 0.0};
+        if (nrhs == 0 || h->n == 0) return SPX_OK;
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        const int32_t n = h->n;
+        const size_t tot = static_cast<size_t>(n) * nrhs;
+        h->y.alloc(tot);
+        h->tacc.alloc(tot);
+        h->xw.alloc(tot);
+        h->rw.alloc(tot);
+        h->stats.alloc(5);
+        const double* bd = b;
+        int64_t ldbd = ldb;
+        if (!b_on_device) {
+            h->bw.alloc(tot);
+            HIPCHK(hipMemcpy2DAsync(h->bw.p, n * sizeof(double), b, ldb * sizeof(double), n * sizeof(double), nrhs,
+                                    hipMemcpyHostToDevice, s));
+            bd = h->bw.p;
+            ldbd = n;
+        }
+        // x0 = A^{-1} b
+        HIPCHK(launch_permute_in(h->y.p, bd, ldbd, h->perm.p, n, nrhs, s));
+        sweeps(h, h->y.p, nrhs, s);
+        HIPCHK(launch_permute_out(h->xw.p, n, h->y.p, h->perm.p, n, nrhs, s));
+        int iters = 0;
+        double omega = 0.0, eta = 0.0;
+        const double tol = h->opt.ir_tol;
+        for (;;) {
+            HIPCHK(hipMemsetAsync(h->stats.p, 0, 5 * sizeof(unsigned long long), s));
+            HIPCHK(launch_residual(h->rptr.p, h->rcol.p, h->rval.p, h->vals.p, h->xw.p, bd, ldbd, h->rw.p, n, nrhs,
+                                   h->stats.p, s));
+            unsigned long long st[5];
+            HIPCHK(hipMemcpyAsync(st, h->stats.p, sizeof st, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            double v[5];
+            std::memcpy(v, st, sizeof v);
+            omega = v[0];
+            const double den = v[4] * v[2] + v[3];
+            eta = v[1] == 0.0 ? 0.0 : (den == 0.0 ? INFINITY : v[1] / den);
+            if (omega <= tol || iters >= h->opt.ir_max_iter) break;
+            // d = A^{-1} r ; x += d
+            HIPCHK(launch_permute_in(h->y.p, h->rw.p, n, h->perm.p, n, nrhs, s));
+            sweeps(h, h->y.p, nrhs, s);
+            HIPCHK(launch_permute_out(h->rw.p, n, h->y.p, h->perm.p, n, nrhs, s));
+            HIPCHK(launch_axpy(h->xw.p, h->rw.p, static_cast<int64_t>(tot), s));
+            ++iters;
+        }
+        if (b_on_device) {
+            HIPCHK(hipMemcpy2DAsync(b, ldb * sizeof(double), h->xw.p, n * sizeof(double), n * sizeof(double), nrhs,
+                                    hipMemcpyDeviceToDevice, s));
+        } else {
+            HIPCHK(hipMemcpy2DAsync(b, ldb * sizeof(double), h->xw.p, n * sizeof(double), n * sizeof(double), nrhs,
+                                    hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        const bool conv = omega <= tol;
+        if (info) *info = spx_solve_info{iters, conv ? 1 : 0, omega, eta};
+        if (!conv) throw StatusError(SPX_ENOCONV, "refinement stopped above the tolerance");
+        return SPX_OK;
+    });
+}
+
+int spx_get_info(const spx_handle* hc, spx_info* info)
+{
+    if (!hc || !info) return SPX_EINVAL;
+    spx_handle* h = const_cast<spx_handle*>(hc);
+    return guarded(h, [&]() -> int {
+        const Plan& P = h->plan;
+        if (h->factorized && !h->logdet_valid) {
+            // 2 * sum log l_jj with pairwise summation, from the diagonal of each panel
+            std::vector<double> diag(static_cast<size_t>(P.n));
+            for (int32_t k = 0; k < P.ncblk; ++k) {
+                const int32_t w = P.lcol[k] - P.fcol[k] + 1;
+                HIPCHK(hipMemcpy2D(diag.data() + P.fcol[k], sizeof(double), h->panels.p + P.panel_off[k],
+                                   (static_cast<size_t>(P.stride[k]) + 1) * sizeof(double), sizeof(double), w,
+                                   hipMemcpyDeviceToHost));
+            }
+            for (auto& d : diag) d = 2.0 * std::log(d);
+            h->logdet = pairwise_sum(diag.data(), P.n);
+            h->logdet_valid = true;
+        }
+        spx_info o;
+        std::memset(&o, 0, sizeof o);
+        o.n = P.n;
+        o.ncblk = P.ncblk;
+        o.nblok = P.nblok;
+        o.nsnode = P.nsnode;
+        o.nnz_a = P.nnz_a;
+        o.nnz_l = P.nnz_exact;
+        o.nnz_l_stored = P.nnz_stored;
+        o.panel_entries = P.panel_entries;
+        o.flops_alg = P.flops_alg;
+        o.flops_exec = P.flops_exec;
+        o.ntasks = h->total;
+        o.fail_col = h->fail_col;
+        o.factorized = h->factorized ? 1 : 0;
+        o.logdet = h->logdet_valid ? h->logdet : 0.0;
+        o.factor_kernel_ms = h->factor_ms;
+        o.assemble_ms = h->assemble_ms;
+        *info = o;
+        return SPX_OK;
+    });
+}
+
+int spx_export_symbolic(const spx_handle* h, spx_symbolic_view* v)
+{
+    if (!h || !v) return SPX_EINVAL;
+    const Plan& P = h->plan;
+    v->n = P.n;
+    v->ncblk = P.ncblk;
+    v->nblok = P.nblok;
+    v->nsnode = P.nsnode;
+    v->nupd = static_cast<int32_t>(P.utgt.size());
+    v->perm = P.perm.data();
+    v->iperm = P.iperm.data();
+    v->etree = P.etree.data();
+    v->snptr = P.snptr.data();
+    v->fcol = P.fcol.data();
+    v->lcol = P.lcol.data();
+    v->stride = P.stride.data();
+    v->panel_off = P.panel_off.data();
+    v->bptr = P.bptr.data();
+    v->cparent = P.cparent.data();
+    v->frow = P.frow.data();
+    v->lrow = P.lrow.data();
+    v->fcblk = P.fcblk.data();
+    v->coefind = P.coefind.data();
+    v->uptr = P.uptr.data();
+    v->utgt = P.utgt.data();
+    v->dep = P.dep.data();
+    return SPX_OK;
+}
+
+int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip_stream)
+{
+    if (!h) return SPX_EINVAL;
+    return guarded(h, [&]() -> int {
+        if (!h->factorized) throw StatusError(SPX_ESTATE, "no factorization");
+        if (!dst && h->plan.panel_entries > 0) throw InvalidArgument("dst is NULL");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (h->plan.panel_entries > 0)
+            HIPCHK(hipMemcpyAsync(dst, h->panels.p, h->plan.panel_entries * sizeof(double),
+                                  dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return SPX_OK;
+    });
+}
+
+void spx_destroy(spx_handle* h) { delete h; }
+
+const char* spx_strerror(int status)
+{
+    switch (status) {
+    case SPX_OK: return "success";
+    case SPX_EINVAL: return "invalid argument";
+    case SPX_ENOMEM: return "out of memory";
+    case SPX_EDEVICE: return "device error";
+    case SPX_ESTATE: return "call out of order";
+    case SPX_ENOTPD: return "matrix is not positive definite";
+    case SPX_ENOCONV: return "refinement did not converge";
+    default: return "unknown status";
+    }
+}
+
+const char* spx_last_error(const spx_handle* h) { return h ? h->err.c_str() : g_analyze_err.c_str(); }
+
+}  // extern "C"

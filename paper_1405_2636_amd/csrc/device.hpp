@@ -1,0 +1,67 @@
+// Device-side data of the factorization and solve (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace spx {
+
+// Column-block geometry on the device (all arrays indexed by cblk or block).
+struct DevPlan {
+    int32_t ncblk;
+    const int32_t* fcol;
+    const int32_t* lcol;
+    const int32_t* stride;
+    const int64_t* panel_off;
+    const int32_t* bptr;
+    const int32_t* frow;
+    const int32_t* lrow;
+    const int32_t* coefind;
+    const int64_t* dinv_off;   // offset of the inverted diagonal tiles of each cblk
+};
+
+// Work-item kinds of the device scheduler.
+enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2 };
+
+// Two int4 per item: {kind, k, a, b}, {c, d, e, f}
+//   kFact:   k
+//   kTrsm:   k, row0 = first panel row, nrows
+//   kUpdate: k (source), j (target), row0 (first source panel row),
+//            col0 (first facing panel row), ncols, mrows
+struct SchedArgs {
+    DevPlan pl;
+    double* panels;
+    double* dinv;
+    const int4* desc;
+    int32_t total;
+    const int32_t* trsm_first;
+    const int32_t* trsm_count;
+    const int32_t* upd_first;
+    const int32_t* upd_count;
+    int32_t* fact_dep;
+    int32_t* trsm_left;
+    int32_t* queue;
+    int32_t* qhead;
+    int32_t* qtail;
+    int32_t* status;        // [0] smallest failing column, [1] abort flag, [2] items done
+    int64_t timeout_ticks;  // wall-clock ticks a worker may wait for its queue slot
+};
+
+// Arguments of the triangular sweeps.
+struct SweepArgs {
+    DevPlan pl;
+    const double* panels;
+    const double* dinv;
+    const int32_t* rowg;      // global row of every off-diagonal panel row
+    const int64_t* rowg_off;  // [ncblk] start of cblk k's rows in rowg
+    double* y;                // permuted vectors, n x nrhs, leading dimension n
+    double* tacc;             // backward partial sums, n x nrhs
+    int32_t n;
+    int32_t nrhs;
+};
+
+constexpr int kThreads = 256;   // 4 waves of 64
+constexpr int kTile = 64;       // rows/cols of update, triangular-solve tiles
+constexpr int kNB = 32;         // diagonal tile (inverted explicitly)
+
+}  // namespace spx

@@ -1,0 +1,309 @@
+// Triangular solves with the supernodal factor, FP64 residual and the
+// refinement helpers (the solve phase of A x = b; the paper states the
+// problem, the sweeps are the standard supernodal ones).
+//
+// Forward sweep, column blocks in ascending dependency levels:
+//   y_k <- L_kk^{-1} y_k                  (one workgroup per block)
+//   y[rows of k] -= L_k,off y_k           (row chunks, FP64 atomics)
+// Backward sweep, levels descending:
+//   t_k  = L_k,off^T x[rows of k]         (row chunks, wave reductions)
+//   x_k <- L_kk^{-T} (y_k - t_k)
+// Both use the 32x32 inverted diagonal tiles kept by the factorization.
+// The sweeps stream the panels once each: they are bound by HBM bandwidth.
+#include "device.hpp"
+
+namespace spx {
+
+constexpr int kChunk = 256;   // off-diagonal rows per workgroup
+
+// ---- forward, diagonal block: y_k <- L_kk^{-1} y_k
+__global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblks)
+{
+    __shared__ double ys[256];
+    __shared__ double part[8][32];
+    __shared__ double zs[32];
+    const int k = cblks[blockIdx.x];
+    const DevPlan& pl = a.pl;
+    const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
+    const int64_t ld = pl.stride[k];
+    const double* L = a.panels + pl.panel_off[k];
+    const double* D = a.dinv + pl.dinv_off[k];
+    const int tid = threadIdx.x;
+    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
+        double* y = a.y + (int64_t)rhs * a.n + f;
+        if (tid < w) ys[tid] = y[tid];
+        __syncthreads();
+        for (int J = 0; J < w; J += kNB) {
+            const int jb = min(kNB, w - J);
+            const int r = tid & 31, q = tid >> 5;
+            double s = 0.0;
+            if (r < jb)
+                for (int p = q; p < J; p += 8) s += L[(J + r) + p * ld] * ys[p];
+            part[q][r] = s;
+            __syncthreads();
+            if (tid < 32) {
+                double t = 0.0;
+                for (int u = 0; u < 8; ++u) t += part[u][tid];
+                zs[tid] = tid < jb ? ys[J + tid] - t : 0.0;
+            }
+            __syncthreads();
+            if (tid < jb) {
+                const double* Ti = D + (J / kNB) * kNB * kNB;
+                double v = 0.0;
+                for (int p = 0; p <= tid; ++p) v += Ti[tid + p * kNB] * zs[p];
+                ys[J + tid] = v;
+            }
+            __syncthreads();
+        }
+        if (tid < w) y[tid] = ys[tid];
+        __syncthreads();
+    }
+}
+
+// ---- forward, off-diagonal rows: y[g(r)] -= sum_c L[r, c] y_k[c]
+__global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
+{
+    __shared__ double yk[256];
+    const int2 it = chunks[blockIdx.x];
+    const int k = it.x, row0 = it.y;
+    const DevPlan& pl = a.pl;
+    const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
+    const int64_t ld = pl.stride[k];
+    const int nr = min(kChunk, (int)ld - row0);
+    const double* L = a.panels + pl.panel_off[k] + row0;
+    const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
+    const int tid = threadIdx.x;
+    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
+        double* y = a.y + (int64_t)rhs * a.n;
+        if (tid < w) yk[tid] = y[f + tid];
+        __syncthreads();
+        if (tid < nr) {
+            double s = 0.0;
+            for (int c = 0; c < w; ++c) s += L[tid + c * ld] * yk[c];
+            unsafeAtomicAdd(y + g[tid], -s);
+        }
+        __syncthreads();
+    }
+}
+
+// ---- backward, off-diagonal rows: tacc[f + c] += sum_r L[r, c] x[g(r)]
+__global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
+{
+    __shared__ double xr[kChunk];
+    const int2 it = chunks[blockIdx.x];
+    const int k = it.x, row0 = it.y;
+    const DevPlan& pl = a.pl;
+    const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
+    const int64_t ld = pl.stride[k];
+    const int nr = min(kChunk, (int)ld - row0);
+    const double* L = a.panels + pl.panel_off[k] + row0;
+    const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
+        const double* x = a.y + (int64_t)rhs * a.n;
+        if (tid < nr) xr[tid] = x[g[tid]];
+        __syncthreads();
+        for (int c = wave; c < w; c += 4) {
+            double s = 0.0;
+            for (int r = lane; r < nr; r += 64) s += L[r + c * ld] * xr[r];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if (lane == 0) unsafeAtomicAdd(a.tacc + (int64_t)rhs * a.n + f + c, s);
+        }
+        __syncthreads();
+    }
+}
+
+// ---- backward, diagonal block: x_k <- L_kk^{-T} (y_k - t_k)
+__global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblks)
+{
+    __shared__ double xs[256];
+    __shared__ double part[8][32];
+    __shared__ double zs[32];
+    const int k = cblks[blockIdx.x];
+    const DevPlan& pl = a.pl;
+    const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
+    const int64_t ld = pl.stride[k];
+    const double* L = a.panels + pl.panel_off[k];
+    const double* D = a.dinv + pl.dinv_off[k];
+    const int tid = threadIdx.x;
+    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
+        double* y = a.y + (int64_t)rhs * a.n + f;
+        const double* t = a.tacc + (int64_t)rhs * a.n + f;
+        if (tid < w) xs[tid] = y[tid] - t[tid];
+        __syncthreads();
+        const int ntile = (w + kNB - 1) / kNB;
+        for (int tI = ntile - 1; tI >= 0; --tI) {
+            const int J = tI * kNB, jb = min(kNB, w - J);
+            // z_J = xs_J - L[J+jb:w, J:J+jb]^T x[J+jb:w]
+            const int r = tid & 31, q = tid >> 5;
+            double s = 0.0;
+            if (r < jb)
+                for (int p = J + jb + q; p < w; p += 8) s += L[p + (J + r) * ld] * xs[p];
+            part[q][r] = s;
+            __syncthreads();
+            if (tid < 32) {
+                double u = 0.0;
+                for (int v = 0; v < 8; ++v) u += part[v][tid];
+                zs[tid] = tid < jb ? xs[J + tid] - u : 0.0;
+            }
+            __syncthreads();
+            if (tid < jb) {
+                // x_J = Ti^T z_J: (Ti^T)[r][p] = Ti[p][r], nonzero for p >= r
+                const double* Ti = D + tI * kNB * kNB;
+                double v = 0.0;
+                for (int p = tid; p < jb; ++p) v += Ti[p + tid * kNB] * zs[p];
+                xs[J + tid] = v;
+            }
+            __syncthreads();
+        }
+        if (tid < w) y[tid] = xs[tid];
+        __syncthreads();
+    }
+}
+
+// ---- vector kernels
+__global__ void permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs)
+{
+    const int64_t tot = (int64_t)n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = t / n, i = t - c * n;
+        y[t] = b[c * ldb + perm[i]];
+    }
+}
+
+__global__ void permute_out(double* x, int64_t ldx, const double* y, const int32_t* perm, int32_t n, int32_t nrhs)
+{
+    const int64_t tot = (int64_t)n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = t / n, i = t - c * n;
+        x[c * ldx + perm[i]] = y[t];
+    }
+}
+
+__global__ void axpy_kernel(double* x, const double* d, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += d[i];
+}
+
+// order-preserving bits of a non-negative double (NaN is treated as +inf)
+__device__ __forceinline__ unsigned long long key_of(double v)
+{
+    if (v != v) v = __builtin_inf();
+    return (unsigned long long)__double_as_longlong(v);
+}
+
+__device__ __forceinline__ unsigned long long block_max(unsigned long long v)
+{
+    __shared__ unsigned long long sm[4];
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sm[wave] = v;
+    __syncthreads();
+    unsigned long long r = sm[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = sm[i] > r ? sm[i] : r;
+    __syncthreads();
+    return r;
+}
+
+// r = b - A x and componentwise / normwise error statistics, in FP64.
+// A is read through the symmetric row pattern (rptr, rcol) whose values are
+// the input entries rval[q] (lower triangle mirrored).
+// stats[0] = max_i |r_i| / (|A||x| + |b|)_i   (0/0 = 0, p/0 = inf)
+// stats[1] = max |r_i|, stats[2] = max |x_i|, stats[3] = max |b_i|, stats[4] = max_i sum_j |a_ij|
+__global__ void __launch_bounds__(256) residual_kernel(const int64_t* rptr, const int32_t* rcol, const int64_t* rval,
+                                                       const double* vals, const double* x, const double* b,
+                                                       int64_t ldb, double* r, int32_t n, int32_t nrhs,
+                                                       unsigned long long* stats)
+{
+    unsigned long long m0 = 0, m1 = 0, m2 = 0, m3 = 0, m4 = 0;
+    const int64_t tot = (int64_t)n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = t / n, i = t - c * n;
+        const double* xc = x + c * n;
+        const double bi = b[c * ldb + i];
+        double acc = bi, den = fabs(bi), arow = 0.0;
+        for (int64_t q = rptr[i]; q < rptr[i + 1]; ++q) {
+            const double av = vals[rval[q]];
+            const double xv = xc[rcol[q]];
+            acc -= av * xv;
+            den += fabs(av) * fabs(xv);
+            arow += fabs(av);
+        }
+        r[t] = acc;
+        const double ar = fabs(acc);
+        const double om = ar == 0.0 ? 0.0 : (den == 0.0 ? __builtin_inf() : ar / den);
+        unsigned long long k0 = key_of(om), k1 = key_of(ar), k2 = key_of(fabs(xc[i])), k3 = key_of(fabs(bi)),
+                           k4 = key_of(arow);
+        m0 = k0 > m0 ? k0 : m0;
+        m1 = k1 > m1 ? k1 : m1;
+        m2 = k2 > m2 ? k2 : m2;
+        m3 = k3 > m3 ? k3 : m3;
+        m4 = k4 > m4 ? k4 : m4;
+    }
+    m0 = block_max(m0);
+    m1 = block_max(m1);
+    m2 = block_max(m2);
+    m3 = block_max(m3);
+    m4 = block_max(m4);
+    if (threadIdx.x == 0) {
+        atomicMax(stats + 0, m0);
+        atomicMax(stats + 1, m1);
+        atomicMax(stats + 2, m2);
+        atomicMax(stats + 3, m3);
+        atomicMax(stats + 4, m4);
+    }
+}
+
+// ---- host launchers
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s)
+{
+    if (count > 0) fwd_diag<<<count, 256, 0, s>>>(a, cblks);
+    return hipGetLastError();
+}
+hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s)
+{
+    if (count > 0) fwd_off<<<count, 256, 0, s>>>(a, chunks);
+    return hipGetLastError();
+}
+hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s)
+{
+    if (count > 0) bwd_off<<<count, 256, 0, s>>>(a, chunks);
+    return hipGetLastError();
+}
+hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s)
+{
+    if (count > 0) bwd_diag<<<count, 256, 0, s>>>(a, cblks);
+    return hipGetLastError();
+}
+hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,
+                             hipStream_t s)
+{
+    permute_in<<<grid_for((int64_t)n * nrhs), 256, 0, s>>>(y, b, ldb, perm, n, nrhs);
+    return hipGetLastError();
+}
+hipError_t launch_permute_out(double* x, int64_t ldx, const double* y, const int32_t* perm, int32_t n, int32_t nrhs,
+                              hipStream_t s)
+{
+    permute_out<<<grid_for((int64_t)n * nrhs), 256, 0, s>>>(x, ldx, y, perm, n, nrhs);
+    return hipGetLastError();
+}
+hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s)
+{
+    axpy_kernel<<<grid_for(n), 256, 0, s>>>(x, d, n);
+    return hipGetLastError();
+}
+hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const int64_t* rval, const double* vals,
+                           const double* x, const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
+                           unsigned long long* stats, hipStream_t s)
+{
+    residual_kernel<<<grid_for((int64_t)n * nrhs), 256, 0, s>>>(rptr, rcol, rval, vals, x, b, ldb, r, n, nrhs, stats);
+    return hipGetLastError();
+}
+
+}  // namespace spx

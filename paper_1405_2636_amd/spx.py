@@ -1,0 +1,238 @@
+"""ctypes binding of the C ABI declared in include/spx.h.
+
+Argument marshalling only: device memory and streams come from torch
+tensors, every step of analysis, factorization and solve runs in the native
+library.  The library must be built (``python -m paper_1405_2636_amd._build``);
+loading fails loudly otherwise, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspx.so")
+
+SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ESTATE, SPX_ENOTPD, SPX_ENOCONV = 0, -1, -2, -3, -4, -5, -6
+
+
+class SpxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("spx error %d: %s" % (code, msg))
+        self.code = code
+
+
+class NotPositiveDefinite(SpxError):
+    def __init__(self, code, msg, col):
+        super().__init__(code, msg)
+        self.col = col
+
+
+class NotConverged(SpxError):
+    def __init__(self, code, msg, x, info):
+        super().__init__(code, msg)
+        self.x = x
+        self.info = info
+
+
+class Options(C.Structure):
+    _fields_ = [("method", C.c_int32), ("leaf_size", C.c_int32), ("amalg_pct", C.c_int32),
+                ("split_width", C.c_int32), ("user_perm", C.c_void_p), ("precision", C.c_int32),
+                ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int32), ("ncblk", C.c_int32), ("nblok", C.c_int32), ("nsnode", C.c_int32),
+                ("nnz_a", C.c_int64), ("nnz_l", C.c_int64), ("nnz_l_stored", C.c_int64),
+                ("panel_entries", C.c_int64), ("flops_alg", C.c_double), ("flops_exec", C.c_double),
+                ("ntasks", C.c_int64), ("fail_col", C.c_int32), ("factorized", C.c_int32),
+                ("logdet", C.c_double), ("factor_kernel_ms", C.c_double), ("assemble_ms", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("ir_iters", C.c_int32), ("converged", C.c_int32), ("omega", C.c_double), ("eta", C.c_double)]
+
+
+SYMBOLIC_FIELDS = [
+    ("perm", "n"), ("iperm", "n"), ("etree", "n"), ("snptr", "nsnode+1"), ("fcol", "ncblk"),
+    ("lcol", "ncblk"), ("stride", "ncblk"), ("panel_off", "ncblk+1"), ("bptr", "ncblk+1"),
+    ("cparent", "ncblk"), ("frow", "nblok"), ("lrow", "nblok"), ("fcblk", "nblok"),
+    ("coefind", "nblok"), ("uptr", "ncblk+1"), ("utgt", "nupd"), ("dep", "ncblk"),
+]
+
+
+class SymView(C.Structure):
+    _fields_ = ([("n", C.c_int32), ("ncblk", C.c_int32), ("nblok", C.c_int32), ("nsnode", C.c_int32),
+                 ("nupd", C.c_int32)] + [(name, C.c_void_p) for name, _ in SYMBOLIC_FIELDS])
+
+
+EXPORTED = ["spx_default_options", "spx_analyze", "spx_factorize", "spx_solve", "spx_get_info",
+            "spx_export_symbolic", "spx_copy_factor", "spx_destroy", "spx_strerror", "spx_last_error"]
+
+_lib = None
+
+
+def load_library():
+    """Load libspx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("%s is missing: build it with `python -m paper_1405_2636_amd._build`" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.spx_default_options.restype = None
+    L.spx_default_options.argtypes = [C.POINTER(Options)]
+    L.spx_analyze.restype = C.c_int
+    L.spx_analyze.argtypes = [C.c_int32, vp, vp, C.POINTER(Options), C.POINTER(vp)]
+    L.spx_factorize.restype = C.c_int
+    L.spx_factorize.argtypes = [vp, vp, C.c_int32, vp]
+    L.spx_solve.restype = C.c_int
+    L.spx_solve.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_int32, C.POINTER(SolveInfo), vp]
+    L.spx_get_info.restype = C.c_int
+    L.spx_get_info.argtypes = [vp, C.POINTER(Info)]
+    L.spx_export_symbolic.restype = C.c_int
+    L.spx_export_symbolic.argtypes = [vp, C.POINTER(SymView)]
+    L.spx_copy_factor.restype = C.c_int
+    L.spx_copy_factor.argtypes = [vp, vp, C.c_int32, vp]
+    L.spx_destroy.restype = None
+    L.spx_destroy.argtypes = [vp]
+    L.spx_strerror.restype = C.c_char_p
+    L.spx_strerror.argtypes = [C.c_int]
+    L.spx_last_error.restype = C.c_char_p
+    L.spx_last_error.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Solver:
+    """Sparse SPD solver: analyze at construction, then factorize(values), solve(b).
+
+    colptr/rowind: CSC pattern (host arrays, full symmetric pattern or its lower
+    triangle).  values passed to factorize are aligned with the pattern.
+    """
+
+    def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,
+                 ir_max_iter=2, ir_tol=1e-14):
+        L = load_library()
+        self._lib = L
+        self.n = int(n)
+        self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        self._rowind = np.ascontiguousarray(rowind, dtype=np.int32)
+        self.nnz = int(self._colptr[-1]) if len(self._colptr) else 0
+        opt = Options()
+        L.spx_default_options(C.byref(opt))
+        opt.leaf_size, opt.amalg_pct, opt.split_width = leaf_size, amalg_pct, split_width
+        opt.ir_max_iter, opt.ir_tol = ir_max_iter, ir_tol
+        up = None
+        if user_perm is not None:
+            up = np.ascontiguousarray(user_perm, dtype=np.int32)
+            opt.user_perm = up.ctypes.data
+        h = C.c_void_p()
+        rc = L.spx_analyze(self.n, self._colptr.ctypes.data, self._rowind.ctypes.data, C.byref(opt), C.byref(h))
+        if rc != SPX_OK:
+            raise SpxError(rc, "analyze failed: %s" % L.spx_last_error(None).decode())
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.spx_destroy(h)
+            self._h = None
+
+    def _check(self, rc, what):
+        if rc == SPX_OK:
+            return
+        msg = self._lib.spx_last_error(self._h).decode()
+        if rc == SPX_ENOTPD:
+            raise NotPositiveDefinite(rc, "%s: %s" % (what, msg), self.info()["fail_col"])
+        raise SpxError(rc, "%s: %s" % (what, msg))
+
+    # ---------------------------------------------------------------- calls
+    def factorize(self, values, stream=None):
+        """values: torch tensor on the GPU (float64) or a host numpy array."""
+        import torch
+        if isinstance(values, torch.Tensor):
+            if values.dtype != torch.float64 or values.numel() != self.nnz:
+                raise ValueError("values must be float64 with nnz entries")
+            values = values.contiguous()
+            on_dev = 1 if values.is_cuda else 0
+            ptr = values.data_ptr()
+            keep = values
+        else:
+            keep = np.ascontiguousarray(values, dtype=np.float64)
+            if keep.size != self.nnz:
+                raise ValueError("values must have nnz entries")
+            on_dev, ptr = 0, keep.ctypes.data
+        rc = self._lib.spx_factorize(self._h, C.c_void_p(ptr), on_dev, _stream_ptr(stream))
+        del keep
+        self._check(rc, "factorize")
+
+    def solve(self, b, stream=None, raise_on_noconv=True):
+        """Solve A x = b.  b: torch CUDA tensor of shape (n,) or (nrhs, n)
+        (each row one right-hand side), overwritten with x and returned with
+        the refinement statistics."""
+        import torch
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()):
+            raise ValueError("b must be a contiguous float64 CUDA tensor")
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        if b.shape[-1] != self.n:
+            raise ValueError("b has the wrong length")
+        si = SolveInfo()
+        rc = self._lib.spx_solve(self._h, nrhs, C.c_void_p(b.data_ptr()), self.n, 1, C.byref(si), _stream_ptr(stream))
+        info = {"ir_iters": si.ir_iters, "converged": bool(si.converged), "omega": si.omega, "eta": si.eta}
+        if rc == SPX_ENOCONV and not raise_on_noconv:
+            return b, info
+        if rc == SPX_ENOCONV:
+            raise NotConverged(rc, self._lib.spx_last_error(self._h).decode(), b, info)
+        self._check(rc, "solve")
+        return b, info
+
+    def info(self) -> dict:
+        inf = Info()
+        rc = self._lib.spx_get_info(self._h, C.byref(inf))
+        if rc != SPX_OK:
+            raise SpxError(rc, "get_info failed")
+        return {name: getattr(inf, name) for name, _ in Info._fields_}
+
+    def symbolic(self) -> dict:
+        """Copies of the exported symbolic arrays (numpy)."""
+        v = SymView()
+        rc = self._lib.spx_export_symbolic(self._h, C.byref(v))
+        if rc != SPX_OK:
+            raise SpxError(rc, "export_symbolic failed")
+        sizes = {"n": v.n, "ncblk": v.ncblk, "nblok": v.nblok, "nsnode": v.nsnode, "nupd": v.nupd}
+        out = {}
+        for name, sz in SYMBOLIC_FIELDS:
+            cnt = sizes[sz.split("+")[0]] + (1 if sz.endswith("+1") else 0)
+            dt = np.int64 if name == "panel_off" else np.int32
+            ptr = getattr(v, name)
+            if cnt == 0 or not ptr:
+                out[name] = np.zeros(0, dt)
+                continue
+            ct = C.c_int64 if dt == np.int64 else C.c_int32
+            buf = (ct * cnt).from_address(ptr)
+            out[name] = np.ctypeslib.as_array(buf).copy()
+        out.update(sizes)
+        return out
+
+    def factor_values(self, out=None, stream=None):
+        """The factor panels (panel_entries doubles) as a torch CUDA tensor."""
+        import torch
+        cnt = self.info()["panel_entries"]
+        if out is None:
+            out = torch.empty(max(cnt, 1), dtype=torch.float64, device="cuda")
+        rc = self._lib.spx_copy_factor(self._h, C.c_void_p(out.data_ptr()), 1, _stream_ptr(stream))
+        self._check(rc, "copy_factor")
+        return out[:cnt]
