@@ -227,6 +227,12 @@ void build_tasks(spx_handle* h)
             while (b2 < P.bptr[k + 1] && P.fcblk[b2] == j) ++b2;
             const int32_t rs = P.coefind[b];
             const int32_t re = P.coefind[b2 - 1] + (P.lrow[b2 - 1] - P.frow[b2 - 1] + 1);
+            // every source row from the facing block down must lie inside one block of j
+            for (int32_t q = b; q < P.bptr[k + 1]; ++q) {
+                const int32_t p0 = panel_row(P, j, P.frow[q]), p1 = panel_row(P, j, P.lrow[q]);
+                if (p0 < 0 || p1 < 0 || p1 - p0 != P.lrow[q] - P.frow[q])
+                    throw std::runtime_error("update rows outside the target structure");
+            }
             for (int32_t r0 = rs; r0 < ld; r0 += kTile) {
                 const int32_t mr = std::min(kTile, ld - r0);
                 for (int32_t c0 = rs; c0 < re; c0 += kTile) {

@@ -230,7 +230,7 @@ __device__ __forceinline__ int global_row(const DevPlan& pl, int k, int r)
 // position inside panel j of global row g (g belongs to j's structure)
 __device__ __forceinline__ int target_row(const DevPlan& pl, int j, int g)
 {
-    if (g <= pl.lcol[j]) return g - pl.fcol[j];
+    if (g <= pl.lcol[j] || pl.bptr[j + 1] - pl.bptr[j] < 2) return g - pl.fcol[j];
     int lo = pl.bptr[j] + 1, hi = pl.bptr[j + 1] - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -356,8 +356,12 @@ __global__ void __launch_bounds__(kThreads) sched_kernel(SchedArgs a)
         __syncthreads();
         if (s_count > 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            for (int i = tid; i < s_count; i += kThreads)
-                __hip_atomic_store(&a.queue[s_base + i], s_first + i, __ATOMIC_RELAXED, AGENT);
+            for (int i = tid; i < s_count; i += kThreads) {
+                if (s_base + i < a.total)
+                    __hip_atomic_store(&a.queue[s_base + i], s_first + i, __ATOMIC_RELAXED, AGENT);
+                else
+                    __hip_atomic_store(&a.status[1], 2, __ATOMIC_RELAXED, AGENT);   // more pushes than items
+            }
         }
         __syncthreads();
     }
