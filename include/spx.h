@@ -66,6 +66,7 @@ typedef struct spx_options {
     int32_t precision;        /* enum spx_precision */
     int32_t ir_max_iter;      /* refinement steps after the first solve (2) */
     double ir_tol;            /* componentwise backward error target (1e-14) */
+    int32_t trace;            /* 1: record a per-work-item trace of each factorization (0) */
 } spx_options;
 
 typedef struct spx_info {
@@ -160,6 +161,14 @@ int spx_export_symbolic(const spx_handle* h, spx_symbolic_view* view);
  * view; the strict upper triangle of diagonal blocks is zero) to dst, a host
  * or device pointer.  Errors: SPX_ESTATE before a factorization. */
 int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip_stream);
+
+/* Task trace of the last factorization (trace option on): 4 int64 per work
+ * item in dst {claimed, started, finished: device wall-clock ticks; hardware
+ * id register of the executing wave}, and, if kinds is not NULL, 4 int32 per
+ * item {kind 0 factor / 1 triangular solve / 2 update, source cblk, target
+ * cblk, rows*cols of an update tile or rows of a solve tile}.  cap = number
+ * of items dst can hold.  Returns the item count, or a negative status. */
+int64_t spx_get_trace(spx_handle* h, int64_t* dst, int64_t cap, int32_t* kinds);
 
 /* Free everything owned by the handle.  NULL is allowed. */
 void spx_destroy(spx_handle* h);

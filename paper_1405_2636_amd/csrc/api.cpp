@@ -23,9 +23,8 @@ namespace spx {
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_assemble(double* panels, const int64_t* amap, const double* values, int64_t nnz, hipStream_t s);
-hipError_t launch_sched_init(int32_t* queue, int32_t total, const int32_t* ready, int32_t nready, int32_t* fact_dep,
-                             const int32_t* fact_dep0, int32_t* trsm_left, const int32_t* trsm_count, int32_t ncblk,
-                             int32_t* qhead, int32_t* qtail, int32_t* status, hipStream_t s);
+hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, const int32_t* fact_dep0,
+                             int32_t ncblk, hipStream_t s);
 int sched_blocks_per_cu();
 hipError_t launch_sched(const SchedArgs& a, int grid, hipStream_t s);
 hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
@@ -113,10 +112,12 @@ struct spx_handle {
     DevBuf<int32_t> rowg;
     DevBuf<int64_t> rowg_off;
     // scheduler tables
-    int32_t total = 0, nready = 0;
+    int32_t total = 0, nready = 0, hp_total = 0, total_normal = 0;
     DevBuf<int4> desc;
-    DevBuf<int32_t> trsm_first, trsm_count, upd_first, upd_count, fact_dep0, fact_dep, trsm_left, queue, ready, qctr,
-        status;
+    DevBuf<int32_t> rmap;
+    DevBuf<int32_t> trsm_first, trsm_count, upd_first, upd_hp, upd_count, fact_dep0, fact_dep, trsm_left, queue,
+        hp_queue, ready, qctr, status;
+    DevBuf<int64_t> trace;   // per-item task trace, allocated when the trace option is on
     // levels for the sweeps
     Level lv;
     DevBuf<int32_t> lv_cblk;
@@ -191,23 +192,30 @@ int guarded(spx_handle* h, F&& f)
     }
 }
 
-// Work items of the device scheduler, in queue-id order: FACT(k) = k, then
-// per cblk its TRSM row tiles, then per cblk its UPDATE tiles (targets
-// ascending, then row tiles, then column tiles).  Tiles that lie entirely in
-// the strict upper triangle of a target's diagonal block are not generated.
+// Work items of the device scheduler, in id order: FACT(k) = k, then per cblk
+// its TRSM row tiles (64 rows), then per cblk its UPDATE tiles.  The update
+// tiles of a pair (k, j) are 256 rows by 64 facing columns (32 when at most
+// 32 rows of k face j); tiles entirely in the strict upper
+// triangle of j's diagonal block are not generated.  The tiles into the
+// first facing cblk (the next block of an elimination chain) come first and
+// go to the high-priority queue, like FACT and TRSM items.
+// rmap holds, per update pair, the row inside panel j of every panel row of
+// k from the first facing row on (checked against the target structure).
 void build_tasks(spx_handle* h)
 {
     const Plan& P = h->plan;
     const int32_t nc = P.ncblk;
-    constexpr int kTrsmRows = 128;
+    constexpr int kTrsmRows = 64;
     std::vector<int4> desc;
     desc.reserve(static_cast<size_t>(nc) * 2);
-    std::vector<int32_t> tf(nc), tc(nc), uf(nc), uc(nc), dep(nc, 0);
+    std::vector<int32_t> tf(nc), tc(nc), uf(nc), uh(nc), ucnt(nc), dep(nc, 0);
+    std::vector<int32_t> rmap;
     for (int32_t k = 0; k < nc; ++k) {
         desc.push_back(int4{kFact, k, 0, 0});
         desc.push_back(int4{0, 0, 0, 0});
     }
     int32_t id = nc;
+    int64_t ntrsm = 0;
     for (int32_t k = 0; k < nc; ++k) {
         const int32_t w = P.lcol[k] - P.fcol[k] + 1, ld = P.stride[k];
         tf[k] = id;
@@ -217,53 +225,76 @@ void build_tasks(spx_handle* h)
             ++id;
         }
         tc[k] = id - tf[k];
+        ntrsm += tc[k];
     }
+    int64_t nhp_upd = 0;
+    std::vector<int32_t> grow;
     for (int32_t k = 0; k < nc; ++k) {
-        const int32_t ld = P.stride[k];
+        const int32_t w = P.lcol[k] - P.fcol[k] + 1, ld = P.stride[k];
+        // global row of every panel row of k
+        grow.assign(static_cast<size_t>(ld), 0);
+        for (int32_t b = P.bptr[k]; b < P.bptr[k + 1]; ++b)
+            for (int32_t r = P.frow[b]; r <= P.lrow[b]; ++r) grow[P.coefind[b] + (r - P.frow[b])] = r;
+        (void)w;
         uf[k] = id;
+        uh[k] = 0;
+        bool first_pair = true;
         for (int32_t b = P.bptr[k] + 1; b < P.bptr[k + 1];) {
             const int32_t j = P.fcblk[b];
             int32_t b2 = b;
             while (b2 < P.bptr[k + 1] && P.fcblk[b2] == j) ++b2;
             const int32_t rs = P.coefind[b];
             const int32_t re = P.coefind[b2 - 1] + (P.lrow[b2 - 1] - P.frow[b2 - 1] + 1);
-            // every source row from the facing block down must lie inside one block of j
-            for (int32_t q = b; q < P.bptr[k + 1]; ++q) {
-                const int32_t p0 = panel_row(P, j, P.frow[q]), p1 = panel_row(P, j, P.lrow[q]);
-                if (p0 < 0 || p1 < 0 || p1 - p0 != P.lrow[q] - P.frow[q])
+            const int64_t moff = static_cast<int64_t>(rmap.size());
+            if (moff - rs > INT32_MAX - ld) throw std::runtime_error("row map exceeds 2^31 entries");
+            for (int32_t r = rs; r < ld; ++r) {
+                const int32_t pos = panel_row(P, j, grow[r]);
+                if (pos < 0 || (r < re && pos != grow[r] - P.fcol[j]))
                     throw std::runtime_error("update rows outside the target structure");
+                rmap.push_back(pos);
             }
-            for (int32_t r0 = rs; r0 < ld; r0 += kTile) {
-                const int32_t mr = std::min(kTile, ld - r0);
-                for (int32_t c0 = rs; c0 < re; c0 += kTile) {
+            const int32_t mbase = static_cast<int32_t>(moff - rs);
+            const int32_t nf = re - rs;
+            const int32_t tr = 256, tcl = nf > 32 ? 64 : 32;
+            for (int32_t r0 = rs; r0 < ld; r0 += tr) {
+                const int32_t mr = std::min(tr, ld - r0);
+                for (int32_t c0 = rs; c0 < re; c0 += tcl) {
                     if (r0 + mr - 1 < c0) continue;   // strictly above the diagonal of j
-                    const int32_t ncl = std::min(kTile, re - c0);
+                    const int32_t ncl = std::min(tcl, re - c0);
                     desc.push_back(int4{kUpdate, k, j, r0});
-                    desc.push_back(int4{c0, ncl, mr, 0});
+                    desc.push_back(int4{mr, c0, ncl, mbase});
                     ++dep[j];
                     ++id;
+                    if (first_pair) ++uh[k];
                 }
             }
+            first_pair = false;
             b = b2;
         }
-        uc[k] = id - uf[k];
+        ucnt[k] = id - uf[k];
+        nhp_upd += uh[k];
     }
     h->total = id;
+    h->hp_total = static_cast<int32_t>(nc + ntrsm + nhp_upd);
+    h->total_normal = h->total - h->hp_total;
     std::vector<int32_t> ready;
     for (int32_t k = 0; k < nc; ++k)
         if (dep[k] == 0) ready.push_back(k);
     h->nready = static_cast<int32_t>(ready.size());
     h->desc.upload(desc);
+    h->rmap.upload(rmap);
     h->trsm_first.upload(tf);
     h->trsm_count.upload(tc);
     h->upd_first.upload(uf);
-    h->upd_count.upload(uc);
+    h->upd_hp.upload(uh);
+    h->upd_count.upload(ucnt);
     h->fact_dep0.upload(dep);
     h->fact_dep.alloc(nc);
     h->trsm_left.alloc(nc);
-    h->queue.alloc(static_cast<size_t>(h->total));
+    h->queue.alloc(static_cast<size_t>(h->total_normal));
+    h->hp_queue.alloc(static_cast<size_t>(h->hp_total));
     h->ready.upload(ready);
-    h->qctr.alloc(2);
+    h->qctr.alloc(4);
     h->status.alloc(4);
 }
 
@@ -320,7 +351,7 @@ void upload_plan(spx_handle* h)
     std::vector<int64_t> doff(static_cast<size_t>(P.ncblk) + 1, 0);
     for (int32_t k = 0; k < P.ncblk; ++k) {
         const int64_t w = P.lcol[k] - P.fcol[k] + 1;
-        doff[k + 1] = doff[k] + ((w + kNB - 1) / kNB) * kNB * kNB;
+        doff[k + 1] = doff[k] + w * w;
     }
     h->dinv_size = doff[P.ncblk];
     h->dinv_off.upload(doff);
@@ -402,6 +433,7 @@ void spx_default_options(spx_options* o)
     o->precision = SPX_FP64;
     o->ir_max_iter = 2;
     o->ir_tol = 1e-14;
+    o->trace = 0;
 }
 
 int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const spx_options* opt, spx_handle** out)
@@ -460,33 +492,45 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
             HIPCHK(hipMemcpyAsync(h->vals.p, values, h->nnz * sizeof(double),
                                   values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         h->panels.alloc(static_cast<size_t>(P.panel_entries));
-        h->dinv.alloc(static_cast<size_t>(h->dinv_size));
+        if (!h->dinv.p) {
+            // blocks above the diagonal of each inverse are never written: zero them once
+            h->dinv.alloc(static_cast<size_t>(h->dinv_size));
+            HIPCHK(launch_fill_f64(h->dinv.p, h->dinv_size, 0.0, s));
+        }
         HIPCHK(hipEventRecord(h->ev[0], s));
         HIPCHK(launch_fill_f64(h->panels.p, P.panel_entries, 0.0, s));
         HIPCHK(launch_assemble(h->panels.p, h->amap.p, h->vals.p, h->nnz, s));
-        HIPCHK(launch_sched_init(h->queue.p, h->total, h->ready.p, h->nready, h->fact_dep.p, h->fact_dep0.p,
-                                 h->trsm_left.p, h->trsm_count.p, P.ncblk, h->qctr.p, h->qctr.p + 1, h->status.p, s));
-        HIPCHK(hipEventRecord(h->ev[1], s));
-        if (h->total > 0) {
-            SchedArgs a;
-            a.pl = h->devplan();
-            a.panels = h->panels.p;
-            a.dinv = h->dinv.p;
-            a.desc = h->desc.p;
-            a.total = h->total;
-            a.trsm_first = h->trsm_first.p;
-            a.trsm_count = h->trsm_count.p;
-            a.upd_first = h->upd_first.p;
-            a.upd_count = h->upd_count.p;
-            a.fact_dep = h->fact_dep.p;
-            a.trsm_left = h->trsm_left.p;
-            a.queue = h->queue.p;
-            a.qhead = h->qctr.p;
-            a.qtail = h->qctr.p + 1;
-            a.status = h->status.p;
-            a.timeout_ticks = h->timeout_ticks;
-            HIPCHK(launch_sched(a, h->grid, s));
+        SchedArgs a;
+        a.pl = h->devplan();
+        a.panels = h->panels.p;
+        a.dinv = h->dinv.p;
+        a.desc = h->desc.p;
+        a.rmap = h->rmap.p;
+        a.hp_total = h->hp_total;
+        a.total_normal = h->total_normal;
+        a.trsm_first = h->trsm_first.p;
+        a.trsm_count = h->trsm_count.p;
+        a.upd_first = h->upd_first.p;
+        a.upd_hp = h->upd_hp.p;
+        a.upd_count = h->upd_count.p;
+        a.fact_dep = h->fact_dep.p;
+        a.trsm_left = h->trsm_left.p;
+        a.queue = h->queue.p;
+        a.qhead = h->qctr.p;
+        a.qtail = h->qctr.p + 1;
+        a.hp_queue = h->hp_queue.p;
+        a.hp_head = h->qctr.p + 2;
+        a.hp_tail = h->qctr.p + 3;
+        a.status = h->status.p;
+        a.timeout_ticks = h->timeout_ticks;
+        a.trace = nullptr;
+        if (h->opt.trace) {
+            h->trace.alloc(static_cast<size_t>(h->total) * 4);
+            a.trace = h->trace.p;
         }
+        HIPCHK(launch_sched_init(a, h->ready.p, h->nready, h->fact_dep0.p, P.ncblk, s));
+        HIPCHK(hipEventRecord(h->ev[1], s));
+        if (h->total > 0) HIPCHK(launch_sched(a, h->grid, s));
         HIPCHK(hipEventRecord(h->ev[2], s));
         int32_t st[4] = {INT_MAX, 0, 0, 0};
         HIPCHK(hipMemcpyAsync(st, h->status.p, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -662,6 +706,27 @@ int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip
                                   dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         return SPX_OK;
+    });
+}
+
+int64_t spx_get_trace(spx_handle* h, int64_t* dst, int64_t cap, int32_t* kinds)
+{
+    if (!h) return SPX_EINVAL;
+    return guarded(h, [&]() -> int {
+        if (!h->opt.trace || !h->trace.p) throw StatusError(SPX_ESTATE, "trace option off or no factorization yet");
+        if (cap < h->total) throw InvalidArgument("trace buffer too small");
+        HIPCHK(hipMemcpy(dst, h->trace.p, static_cast<size_t>(h->total) * 4 * sizeof(int64_t), hipMemcpyDeviceToHost));
+        if (kinds) {
+            std::vector<int4> d(static_cast<size_t>(h->total) * 2);
+            HIPCHK(hipMemcpy(d.data(), h->desc.p, d.size() * sizeof(int4), hipMemcpyDeviceToHost));
+            for (int32_t i = 0; i < h->total; ++i) {
+                kinds[4 * i + 0] = d[2 * i].x;   // kind
+                kinds[4 * i + 1] = d[2 * i].y;   // source cblk
+                kinds[4 * i + 2] = d[2 * i].x == kUpdate ? d[2 * i].z : d[2 * i].y;   // target cblk
+                kinds[4 * i + 3] = d[2 * i].x == kUpdate ? d[2 * i + 1].y * d[2 * i + 1].z : d[2 * i].w;
+            }
+        }
+        return h->total;
     });
 }
 

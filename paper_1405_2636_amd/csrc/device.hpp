@@ -25,26 +25,33 @@ enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2 };
 
 // Two int4 per item: {kind, k, a, b}, {c, d, e, f}
 //   kFact:   k
-//   kTrsm:   k, row0 = first panel row, nrows
-//   kUpdate: k (source), j (target), row0 (first source panel row),
-//            col0 (first facing panel row), ncols, mrows
+//   kTrsm:   k, row0 = first panel row, nrows (<= 64)
+//   kUpdate: k (source), j (target), row0 (first source panel row);
+//            mrows, col0 (first facing panel row), ncols, mbase (row-map base)
 struct SchedArgs {
     DevPlan pl;
     double* panels;
     double* dinv;
     const int4* desc;
-    int32_t total;
+    const int32_t* rmap;     // panel row of k -> row inside panel j, per update pair
+    int32_t hp_total;        // items of the high-priority queue (FACT, TRSM, chain updates)
+    int32_t total_normal;    // items of the normal queue (other updates)
     const int32_t* trsm_first;
     const int32_t* trsm_count;
     const int32_t* upd_first;
+    const int32_t* upd_hp;   // leading update items of a cblk that go to the high-priority queue
     const int32_t* upd_count;
     int32_t* fact_dep;
     int32_t* trsm_left;
     int32_t* queue;
     int32_t* qhead;
     int32_t* qtail;
+    int32_t* hp_queue;
+    int32_t* hp_head;
+    int32_t* hp_tail;
     int32_t* status;        // [0] smallest failing column, [1] abort flag, [2] items done
-    int64_t timeout_ticks;  // wall-clock ticks a worker may wait for its queue slot
+    int64_t timeout_ticks;  // wall-clock ticks a worker may wait for work
+    int64_t* trace;         // optional: 4 words per item {claimed, started, finished, hw id}
 };
 
 // Arguments of the triangular sweeps.

@@ -8,7 +8,7 @@
 // Backward sweep, levels descending:
 //   t_k  = L_k,off^T x[rows of k]         (row chunks, wave reductions)
 //   x_k <- L_kk^{-T} (y_k - t_k)
-// Both use the 32x32 inverted diagonal tiles kept by the factorization.
+// Both use the inverse of each diagonal block kept by the factorization.
 // The sweeps stream the panels once each: they are bound by HBM bandwidth.
 #include "device.hpp"
 
@@ -16,51 +16,40 @@ namespace spx {
 
 constexpr int kChunk = 256;   // off-diagonal rows per workgroup
 
-// ---- forward, diagonal block: y_k <- L_kk^{-1} y_k
+// ---- forward, diagonal block: y_k <- D y_k with D = L_kk^{-1} (lower, w x w,
+// column-major, kept by the factorization).  Thread r owns row r; the loads
+// D[r + p*w] of one p are contiguous over the threads.
 __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblks)
 {
     __shared__ double ys[256];
-    __shared__ double part[8][32];
-    __shared__ double zs[32];
     const int k = cblks[blockIdx.x];
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
-    const int64_t ld = pl.stride[k];
-    const double* L = a.panels + pl.panel_off[k];
     const double* D = a.dinv + pl.dinv_off[k];
     const int tid = threadIdx.x;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
         double* y = a.y + (int64_t)rhs * a.n + f;
         if (tid < w) ys[tid] = y[tid];
         __syncthreads();
-        for (int J = 0; J < w; J += kNB) {
-            const int jb = min(kNB, w - J);
-            const int r = tid & 31, q = tid >> 5;
-            double s = 0.0;
-            if (r < jb)
-                for (int p = q; p < J; p += 8) s += L[(J + r) + p * ld] * ys[p];
-            part[q][r] = s;
-            __syncthreads();
-            if (tid < 32) {
-                double t = 0.0;
-                for (int u = 0; u < 8; ++u) t += part[u][tid];
-                zs[tid] = tid < jb ? ys[J + tid] - t : 0.0;
+        if (tid < w) {
+            const double* row = D + tid;
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+            int p = 0;
+            for (; p + 4 <= tid + 1; p += 4) {
+                v0 += row[(int64_t)p * w] * ys[p];
+                v1 += row[(int64_t)(p + 1) * w] * ys[p + 1];
+                v2 += row[(int64_t)(p + 2) * w] * ys[p + 2];
+                v3 += row[(int64_t)(p + 3) * w] * ys[p + 3];
             }
-            __syncthreads();
-            if (tid < jb) {
-                const double* Ti = D + (J / kNB) * kNB * kNB;
-                double v = 0.0;
-                for (int p = 0; p <= tid; ++p) v += Ti[tid + p * kNB] * zs[p];
-                ys[J + tid] = v;
-            }
-            __syncthreads();
+            for (; p <= tid; ++p) v0 += row[(int64_t)p * w] * ys[p];
+            y[tid] = (v0 + v1) + (v2 + v3);
         }
-        if (tid < w) y[tid] = ys[tid];
         __syncthreads();
     }
 }
 
-// ---- forward, off-diagonal rows: y[g(r)] -= sum_c L[r, c] y_k[c]
+// ---- forward, off-diagonal rows: y[g(r)] -= sum_c L[r, c] y_k[c]; thread per
+// row, loads contiguous over the threads
 __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
 {
     __shared__ double yk[256];
@@ -78,15 +67,24 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
         if (tid < w) yk[tid] = y[f + tid];
         __syncthreads();
         if (tid < nr) {
-            double s = 0.0;
-            for (int c = 0; c < w; ++c) s += L[tid + c * ld] * yk[c];
-            unsafeAtomicAdd(y + g[tid], -s);
+            const double* row = L + tid;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int c = 0;
+            for (; c + 4 <= w; c += 4) {
+                s0 += row[c * ld] * yk[c];
+                s1 += row[(c + 1) * ld] * yk[c + 1];
+                s2 += row[(c + 2) * ld] * yk[c + 2];
+                s3 += row[(c + 3) * ld] * yk[c + 3];
+            }
+            for (; c < w; ++c) s0 += row[c * ld] * yk[c];
+            unsafeAtomicAdd(y + g[tid], -((s0 + s1) + (s2 + s3)));
         }
         __syncthreads();
     }
 }
 
-// ---- backward, off-diagonal rows: tacc[f + c] += sum_r L[r, c] x[g(r)]
+// ---- backward, off-diagonal rows: tacc[f + c] += sum_r L[r, c] x[g(r)];
+// thread per column, each streaming down its own column of the chunk
 __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
 {
     __shared__ double xr[kChunk];
@@ -98,65 +96,56 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
     const int nr = min(kChunk, (int)ld - row0);
     const double* L = a.panels + pl.panel_off[k] + row0;
     const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
         const double* x = a.y + (int64_t)rhs * a.n;
         if (tid < nr) xr[tid] = x[g[tid]];
         __syncthreads();
-        for (int c = wave; c < w; c += 4) {
-            double s = 0.0;
-            for (int r = lane; r < nr; r += 64) s += L[r + c * ld] * xr[r];
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            if (lane == 0) unsafeAtomicAdd(a.tacc + (int64_t)rhs * a.n + f + c, s);
+        if (tid < w) {
+            const double* col = L + (int64_t)tid * ld;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int r = 0;
+            for (; r + 4 <= nr; r += 4) {
+                s0 += col[r] * xr[r];
+                s1 += col[r + 1] * xr[r + 1];
+                s2 += col[r + 2] * xr[r + 2];
+                s3 += col[r + 3] * xr[r + 3];
+            }
+            for (; r < nr; ++r) s0 += col[r] * xr[r];
+            unsafeAtomicAdd(a.tacc + (int64_t)rhs * a.n + f + tid, (s0 + s1) + (s2 + s3));
         }
         __syncthreads();
     }
 }
 
-// ---- backward, diagonal block: x_k <- L_kk^{-T} (y_k - t_k)
+// ---- backward, diagonal block: x_k <- D^T (y_k - t_k); thread c streams
+// down column c of D
 __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblks)
 {
-    __shared__ double xs[256];
-    __shared__ double part[8][32];
-    __shared__ double zs[32];
+    __shared__ double zs[256];
     const int k = cblks[blockIdx.x];
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
-    const int64_t ld = pl.stride[k];
-    const double* L = a.panels + pl.panel_off[k];
     const double* D = a.dinv + pl.dinv_off[k];
     const int tid = threadIdx.x;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
         double* y = a.y + (int64_t)rhs * a.n + f;
         const double* t = a.tacc + (int64_t)rhs * a.n + f;
-        if (tid < w) xs[tid] = y[tid] - t[tid];
+        if (tid < w) zs[tid] = y[tid] - t[tid];
         __syncthreads();
-        const int ntile = (w + kNB - 1) / kNB;
-        for (int tI = ntile - 1; tI >= 0; --tI) {
-            const int J = tI * kNB, jb = min(kNB, w - J);
-            // z_J = xs_J - L[J+jb:w, J:J+jb]^T x[J+jb:w]
-            const int r = tid & 31, q = tid >> 5;
-            double s = 0.0;
-            if (r < jb)
-                for (int p = J + jb + q; p < w; p += 8) s += L[p + (J + r) * ld] * xs[p];
-            part[q][r] = s;
-            __syncthreads();
-            if (tid < 32) {
-                double u = 0.0;
-                for (int v = 0; v < 8; ++v) u += part[v][tid];
-                zs[tid] = tid < jb ? xs[J + tid] - u : 0.0;
+        if (tid < w) {
+            const double* col = D + (int64_t)tid * w;
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+            int p = tid;
+            for (; p + 4 <= w; p += 4) {
+                v0 += col[p] * zs[p];
+                v1 += col[p + 1] * zs[p + 1];
+                v2 += col[p + 2] * zs[p + 2];
+                v3 += col[p + 3] * zs[p + 3];
             }
-            __syncthreads();
-            if (tid < jb) {
-                // x_J = Ti^T z_J: (Ti^T)[r][p] = Ti[p][r], nonzero for p >= r
-                const double* Ti = D + tI * kNB * kNB;
-                double v = 0.0;
-                for (int p = tid; p < jb; ++p) v += Ti[p + tid * kNB] * zs[p];
-                xs[J + tid] = v;
-            }
-            __syncthreads();
+            for (; p < w; ++p) v0 += col[p] * zs[p];
+            y[tid] = (v0 + v1) + (v2 + v3);
         }
-        if (tid < w) y[tid] = xs[tid];
         __syncthreads();
     }
 }

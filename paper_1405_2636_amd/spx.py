@@ -40,7 +40,7 @@ class NotConverged(SpxError):
 class Options(C.Structure):
     _fields_ = [("method", C.c_int32), ("leaf_size", C.c_int32), ("amalg_pct", C.c_int32),
                 ("split_width", C.c_int32), ("user_perm", C.c_void_p), ("precision", C.c_int32),
-                ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double)]
+                ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double), ("trace", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -69,7 +69,8 @@ class SymView(C.Structure):
 
 
 EXPORTED = ["spx_default_options", "spx_analyze", "spx_factorize", "spx_solve", "spx_get_info",
-            "spx_export_symbolic", "spx_copy_factor", "spx_destroy", "spx_strerror", "spx_last_error"]
+            "spx_export_symbolic", "spx_copy_factor", "spx_get_trace", "spx_destroy", "spx_strerror",
+            "spx_last_error"]
 
 _lib = None
 
@@ -97,6 +98,8 @@ def load_library():
     L.spx_export_symbolic.argtypes = [vp, C.POINTER(SymView)]
     L.spx_copy_factor.restype = C.c_int
     L.spx_copy_factor.argtypes = [vp, vp, C.c_int32, vp]
+    L.spx_get_trace.restype = C.c_int64
+    L.spx_get_trace.argtypes = [vp, vp, C.c_int64, vp]
     L.spx_destroy.restype = None
     L.spx_destroy.argtypes = [vp]
     L.spx_strerror.restype = C.c_char_p
@@ -124,7 +127,7 @@ class Solver:
     """
 
     def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,
-                 ir_max_iter=2, ir_tol=1e-14):
+                 ir_max_iter=2, ir_tol=1e-14, trace=False):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -135,6 +138,7 @@ class Solver:
         L.spx_default_options(C.byref(opt))
         opt.leaf_size, opt.amalg_pct, opt.split_width = leaf_size, amalg_pct, split_width
         opt.ir_max_iter, opt.ir_tol = ir_max_iter, ir_tol
+        opt.trace = 1 if trace else 0
         up = None
         if user_perm is not None:
             up = np.ascontiguousarray(user_perm, dtype=np.int32)
@@ -226,6 +230,16 @@ class Solver:
             out[name] = np.ctypeslib.as_array(buf).copy()
         out.update(sizes)
         return out
+
+    def trace(self):
+        """Per-item trace of the last factorization: (times int64 [items, 4], kinds int32 [items, 4])."""
+        cnt = self.info()["ntasks"]
+        t = np.zeros((max(cnt, 1), 4), np.int64)
+        k = np.zeros((max(cnt, 1), 4), np.int32)
+        rc = self._lib.spx_get_trace(self._h, t.ctypes.data, cnt, k.ctypes.data)
+        if rc < 0:
+            self._check(int(rc), "get_trace")
+        return t[:cnt], k[:cnt]
 
     def factor_values(self, out=None, stream=None):
         """The factor panels (panel_entries doubles) as a torch CUDA tensor."""
