@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 
 
-def cpu_baseline(p, budget_flops: float = 2.5e10):
+def cpu_baseline(p, budget_flops: float = 1.0e10):
     """The oracle (plain serial C, one core) on a bounded sample of the same
     workload: its own analysis of the full matrix, then the factorization of
     the leading column blocks in elimination order up to a flop budget."""

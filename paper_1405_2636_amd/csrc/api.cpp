@@ -23,8 +23,8 @@ namespace spx {
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_assemble(double* panels, const int64_t* amap, const double* values, int64_t nnz, hipStream_t s);
-hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, const int32_t* fact_dep0,
-                             int32_t ncblk, hipStream_t s);
+hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, int32_t nready_hp,
+                             const int32_t* fact_dep0, int32_t ncblk, hipStream_t s);
 int sched_blocks_per_cu();
 hipError_t launch_sched(const SchedArgs& a, int grid, hipStream_t s);
 hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
@@ -112,11 +112,11 @@ struct spx_handle {
     DevBuf<int32_t> rowg;
     DevBuf<int64_t> rowg_off;
     // scheduler tables
-    int32_t total = 0, nready = 0, hp_total = 0, total_normal = 0;
+    int32_t total = 0, nready = 0, nready_hp = 0, hp_total = 0, total_normal = 0;
     DevBuf<int4> desc;
     DevBuf<int32_t> rmap;
-    DevBuf<int32_t> trsm_first, trsm_count, upd_first, upd_hp, upd_count, fact_dep0, fact_dep, trsm_left, queue,
-        hp_queue, ready, qctr, status;
+    DevBuf<int32_t> trsm_first, trsm_count, upd_first, upd_hp, upd_count, hp_cblk, fact_dep0, fact_dep, trsm_left,
+        queue, hp_queue, ready, qctr, status;
     DevBuf<int64_t> trace;   // per-item task trace, allocated when the trace option is on
     // levels for the sweeps
     Level lv;
@@ -206,6 +206,16 @@ void build_tasks(spx_handle* h)
     const Plan& P = h->plan;
     const int32_t nc = P.ncblk;
     constexpr int kTrsmRows = 64;
+    // high priority for the upper part of the block tree, where dependency
+    // levels hold few blocks and the elimination chains are critical
+    std::vector<int32_t> lvl(nc, 0), hp(nc, 0);
+    for (int32_t k = 0; k < nc; ++k)
+        for (int32_t q = P.uptr[k]; q < P.uptr[k + 1]; ++q) lvl[P.utgt[q]] = std::max(lvl[P.utgt[q]], lvl[k] + 1);
+    {
+        std::vector<int32_t> per_level(static_cast<size_t>(nc) + 1, 0);
+        for (int32_t k = 0; k < nc; ++k) ++per_level[lvl[k]];
+        for (int32_t k = 0; k < nc; ++k) hp[k] = per_level[lvl[k]] <= 32 ? 1 : 0;
+    }
     std::vector<int4> desc;
     desc.reserve(static_cast<size_t>(nc) * 2);
     std::vector<int32_t> tf(nc), tc(nc), uf(nc), uh(nc), ucnt(nc), dep(nc, 0);
@@ -265,7 +275,7 @@ void build_tasks(spx_handle* h)
                     desc.push_back(int4{mr, c0, ncl, mbase});
                     ++dep[j];
                     ++id;
-                    if (first_pair) ++uh[k];
+                    if (first_pair && hp[k]) ++uh[k];
                 }
             }
             first_pair = false;
@@ -275,12 +285,19 @@ void build_tasks(spx_handle* h)
         nhp_upd += uh[k];
     }
     h->total = id;
-    h->hp_total = static_cast<int32_t>(nc + ntrsm + nhp_upd);
-    h->total_normal = h->total - h->hp_total;
-    std::vector<int32_t> ready;
+    int64_t hp_items = nhp_upd;
     for (int32_t k = 0; k < nc; ++k)
-        if (dep[k] == 0) ready.push_back(k);
+        if (hp[k]) hp_items += 1 + tc[k];
+    h->hp_total = static_cast<int32_t>(hp_items);
+    h->total_normal = h->total - h->hp_total;
+    std::vector<int32_t> ready;   // high-priority ones first
+    for (int32_t k = 0; k < nc; ++k)
+        if (dep[k] == 0 && hp[k]) ready.push_back(k);
+    h->nready_hp = static_cast<int32_t>(ready.size());
+    for (int32_t k = 0; k < nc; ++k)
+        if (dep[k] == 0 && !hp[k]) ready.push_back(k);
     h->nready = static_cast<int32_t>(ready.size());
+    h->hp_cblk.upload(hp);
     h->desc.upload(desc);
     h->rmap.upload(rmap);
     h->trsm_first.upload(tf);
@@ -513,6 +530,7 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
         a.upd_first = h->upd_first.p;
         a.upd_hp = h->upd_hp.p;
         a.upd_count = h->upd_count.p;
+        a.hp_cblk = h->hp_cblk.p;
         a.fact_dep = h->fact_dep.p;
         a.trsm_left = h->trsm_left.p;
         a.queue = h->queue.p;
@@ -528,7 +546,7 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
             h->trace.alloc(static_cast<size_t>(h->total) * 4);
             a.trace = h->trace.p;
         }
-        HIPCHK(launch_sched_init(a, h->ready.p, h->nready, h->fact_dep0.p, P.ncblk, s));
+        HIPCHK(launch_sched_init(a, h->ready.p, h->nready, h->nready_hp, h->fact_dep0.p, P.ncblk, s));
         HIPCHK(hipEventRecord(h->ev[1], s));
         if (h->total > 0) HIPCHK(launch_sched(a, h->grid, s));
         HIPCHK(hipEventRecord(h->ev[2], s));

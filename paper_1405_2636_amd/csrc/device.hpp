@@ -41,6 +41,7 @@ struct SchedArgs {
     const int32_t* upd_first;
     const int32_t* upd_hp;   // leading update items of a cblk that go to the high-priority queue
     const int32_t* upd_count;
+    const int32_t* hp_cblk;  // 1 if the items of the cblk go to the high-priority queue
     int32_t* fact_dep;
     int32_t* trsm_left;
     int32_t* queue;

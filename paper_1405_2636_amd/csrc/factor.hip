@@ -125,7 +125,7 @@ __device__ __forceinline__ void wave_gemm(d4 (&acc)[NB][4], const GOp& X, const 
 #pragma unroll
             for (int b = 0; b < NB; ++b) yc[u][b] = yn[u][b];
         }
-        load(min(ch + 1, nchunks - 1));   // next operands in flight during the products
+        load(min(ch + 1, nchunks - 1));
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -444,7 +444,7 @@ __device__ __forceinline__ void push_items(const SchedArgs& a, bool hp, int base
 // ---------------------------------------------------------------- scheduler
 __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 {
-    __shared__ double Ls[kNB * 33];
+    __shared__ double Ls[kNB * 33 + kNB];
     __shared__ double Gs[kNB * 33 * 7];
     __shared__ int rpos[256], cpos[128];
     __shared__ int s_item;
@@ -496,8 +496,13 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         if (tid == 0) {
             int hf = 0, hc = 0, nf = 0, nc = 0;
             if (d0.x == kFact) {
-                hf = a.trsm_first[d0.y];
-                hc = a.trsm_count[d0.y];
+                if (a.hp_cblk[d0.y]) {
+                    hf = a.trsm_first[d0.y];
+                    hc = a.trsm_count[d0.y];
+                } else {
+                    nf = a.trsm_first[d0.y];
+                    nc = a.trsm_count[d0.y];
+                }
             } else if (d0.x == kTrsm) {
                 if (__hip_atomic_fetch_add(&a.trsm_left[d0.y], -1, __ATOMIC_RELAXED, AGENT) == 1) {
                     hf = a.upd_first[d0.y];
@@ -507,8 +512,8 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
                 }
             } else {
                 if (__hip_atomic_fetch_add(&a.fact_dep[d0.z], -1, __ATOMIC_RELAXED, AGENT) == 1) {
-                    hf = d0.z;
-                    hc = 1;
+                    if (a.hp_cblk[d0.z]) { hf = d0.z; hc = 1; }
+                    else { nf = d0.z; nc = 1; }
                 }
             }
             s_push[0] = hf;
@@ -554,22 +559,25 @@ __global__ void assemble_kernel(double* panels, const int64_t* amap, const doubl
 }
 
 // queues and counters of one factorization: the ready FACT items are the
-// first entries of the high-priority queue
-__global__ void sched_init(SchedArgs a, const int32_t* ready, int32_t nready, const int32_t* fact_dep0, int32_t ncblk)
+// first entries of their queues (ready[0..nready_hp) high priority, the rest
+// normal)
+__global__ void sched_init(SchedArgs a, const int32_t* ready, int32_t nready, int32_t nready_hp,
+                           const int32_t* fact_dep0, int32_t ncblk)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    for (int64_t i = t; i < a.total_normal; i += stride) a.queue[i] = -1;
-    for (int64_t i = t; i < a.hp_total; i += stride) a.hp_queue[i] = i < nready ? ready[i] : -1;
+    const int32_t nready_n = nready - nready_hp;
+    for (int64_t i = t; i < a.total_normal; i += stride) a.queue[i] = i < nready_n ? ready[nready_hp + i] : -1;
+    for (int64_t i = t; i < a.hp_total; i += stride) a.hp_queue[i] = i < nready_hp ? ready[i] : -1;
     for (int64_t i = t; i < ncblk; i += stride) {
         a.fact_dep[i] = fact_dep0[i];
         a.trsm_left[i] = a.trsm_count[i];
     }
     if (t == 0) {
         *a.qhead = 0;
-        *a.qtail = 0;
+        *a.qtail = nready_n;
         *a.hp_head = 0;
-        *a.hp_tail = nready;
+        *a.hp_tail = nready_hp;
         a.status[0] = 0x7fffffff;
         a.status[1] = 0;
         a.status[2] = 0;
@@ -601,12 +609,12 @@ hipError_t launch_assemble(double* panels, const int64_t* amap, const double* va
     return hipGetLastError();
 }
 
-hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, const int32_t* fact_dep0,
-                             int32_t ncblk, hipStream_t s)
+hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, int32_t nready_hp,
+                             const int32_t* fact_dep0, int32_t ncblk, hipStream_t s)
 {
     const int64_t n = std::max<int64_t>(std::max<int64_t>(a.total_normal, a.hp_total), ncblk);
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
-    sched_init<<<blocks, 256, 0, s>>>(a, ready, nready, fact_dep0, ncblk);
+    sched_init<<<blocks, 256, 0, s>>>(a, ready, nready, nready_hp, fact_dep0, ncblk);
     return hipGetLastError();
 }
 
