@@ -194,8 +194,8 @@ int guarded(spx_handle* h, F&& f)
 
 // Work items of the device scheduler, in id order: FACT(k) = k, then per cblk
 // its TRSM row tiles (64 rows), then per cblk its UPDATE tiles.  The update
-// tiles of a pair (k, j) are 256 rows by 64 facing columns (32 when at most
-// 32 rows of k face j); tiles entirely in the strict upper
+// tiles of a pair (k, j) are 256 rows by 64 facing columns; tiles entirely
+// in the strict upper
 // triangle of j's diagonal block are not generated.  The tiles into the
 // first facing cblk (the next block of an elimination chain) come first and
 // go to the high-priority queue, like FACT and TRSM items.
@@ -265,7 +265,7 @@ void build_tasks(spx_handle* h)
             }
             const int32_t mbase = static_cast<int32_t>(moff - rs);
             const int32_t nf = re - rs;
-            const int32_t tr = 256, tcl = nf > 32 ? 64 : 32;
+            const int32_t tr = 256, tcl = 64;
             for (int32_t r0 = rs; r0 < ld; r0 += tr) {
                 const int32_t mr = std::min(tr, ld - r0);
                 for (int32_t c0 = rs; c0 < re; c0 += tcl) {

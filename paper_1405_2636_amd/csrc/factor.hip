@@ -87,8 +87,9 @@ __device__ __forceinline__ double gload(const GOp& g, int voff)
 // l holds D[4v + l/16][l%16].  Y feeds operand A and X operand B, so
 //   acc[bi][bj][v] = C(16*bj + l%16, 16*bi + 4v + l/16)
 // and the 16 lanes of a result slot cover 16 consecutive rows of C.  The
-// inner dimension advances 8 at a time; the operands of the next 8 are
-// loaded before the products of the current 8 are issued.
+// inner dimension advances 8 at a time through two register buffers: the
+// operands of the next 8 are in flight while the products of the current 8
+// are issued.
 template <int NB>
 __device__ __forceinline__ void wave_gemm(d4 (&acc)[NB][4], const GOp& X, const GOp& Y, int K)
 {
@@ -105,34 +106,33 @@ __device__ __forceinline__ void wave_gemm(d4 (&acc)[NB][4], const GOp& X, const 
         for (int b = 0; b < NB; ++b) yo[u][b] = Y.off + (16 * b + li) * Y.si + (4 * u + lk) * Y.sk;
     }
     const int dx = 8 * X.sk, dy = 8 * Y.sk;
-    double xn[2][4], yn[2][NB];
-    auto load = [&](int ch) {
+    double xa[2][4], ya[2][NB], xb[2][4], yb[2][NB];
+    auto load = [&](double (&xs)[2][4], double (&ys)[2][NB], int ch) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) xn[u][b] = gload(X, xo[u][b] + ch * dx);
+            for (int b = 0; b < 4; ++b) xs[u][b] = gload(X, xo[u][b] + ch * dx);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) yn[u][b] = gload(Y, yo[u][b] + ch * dy);
+            for (int b = 0; b < NB; ++b) ys[u][b] = gload(Y, yo[u][b] + ch * dy);
         }
     };
-    load(0);
-    for (int ch = 0; ch < nchunks; ++ch) {
-        double xc[2][4], yc[2][NB];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) xc[u][b] = xn[u][b];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) yc[u][b] = yn[u][b];
-        }
-        load(min(ch + 1, nchunks - 1));
+    auto mma = [&](const double (&xs)[2][4], const double (&ys)[2][NB]) {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_f64(yc[u][bi], xc[u][bj], acc[bi][bj]);
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_f64(ys[u][bi], xs[u][bj], acc[bi][bj]);
+    };
+    load(xa, ya, 0);
+    int ch = 0;
+    for (; ch + 2 <= nchunks; ch += 2) {
+        load(xb, yb, ch + 1);
+        mma(xa, ya);
+        load(xa, ya, min(ch + 2, nchunks - 1));
+        mma(xb, yb);
     }
+    if (ch < nchunks) mma(xa, ya);
 }
 
 // Same product with Y in LDS: Y(c, p) = Y[c*ysc + p*ysp], masked to c < nv, p < K.
@@ -348,9 +348,9 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Ls, do
 
 // ---------------------------------------------------------------- TRSM(k, rows)
 // Rows [row0, row0+nrows) (nrows <= 64) of panel k below its diagonal block
-// are replaced by B L_kk^{-T} = B D^T.  Wave v computes the 32-column slices
-// starting at 32v and 128+32v; the inner range of a slice stops at the
-// diagonal of the lower triangular D.
+// are replaced by B L_kk^{-T} = B D^T.  Wave v computes the 64 output columns
+// starting at 64v; the inner range stops at the diagonal of the lower
+// triangular D.
 __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int nrows)
 {
     const DevPlan& pl = a.pl;
@@ -360,17 +360,13 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
     double* B = P + row0;
     const double* D = a.dinv + pl.dinv_off[k];
     const int wave = threadIdx.x >> 6;
-    d4 acc0[2][4], acc1[2][4];
-    zero_acc(acc0);
-    zero_acc(acc1);
-    const int c0 = 32 * wave, c1 = 128 + 32 * wave;
-    const int n0 = min(32, w - c0), n1 = min(32, w - c1);
-    const GOp X = make_gop(P, ld * w, row0, 1, ld);
-    if (n0 > 0) wave_gemm<2>(acc0, X, make_gop(D, (int64_t)w * w, c0, 1, w), min(w, c0 + 32));
-    if (n1 > 0) wave_gemm<2>(acc1, X, make_gop(D, (int64_t)w * w, c1, 1, w), min(w, c1 + 32));
+    d4 acc[4][4];
+    zero_acc(acc);
+    const int c0 = 64 * wave;
+    const int nv = min(64, w - c0);
+    if (nv > 0) wave_gemm<4>(acc, make_gop(P, ld * w, row0, 1, ld), make_gop(D, (int64_t)w * w, c0, 1, w), min(w, c0 + 64));
     __syncthreads();   // every wave has read all of B before any result is written
-    if (n0 > 0) wave_store(acc0, nrows, n0, [&](int r, int c, double v) { B[r + (int64_t)(c0 + c) * ld] = v; });
-    if (n1 > 0) wave_store(acc1, nrows, n1, [&](int r, int c, double v) { B[r + (int64_t)(c1 + c) * ld] = v; });
+    if (nv > 0) wave_store(acc, nrows, nv, [&](int r, int c, double v) { B[r + (int64_t)(c0 + c) * ld] = v; });
 }
 
 // ---------------------------------------------------------------- UPDATE
@@ -378,9 +374,8 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // width of k), C_j[rmap(row), rmap(col)] -= W on the lower triangle of j.
 // rmap (precomputed from the symbolic structure) gives, for every panel row
 // of k from the first block facing j on, its row inside panel j; for facing
-// rows that is also the column of j.  ncols <= 64, mrows <= 256: with more
-// than 32 columns the four 64x32 wave tiles cover 128x64 per pass (two
-// passes), else 256x32 in one pass.
+// rows that is also the column of j.  ncols <= 64, mrows <= 256: the four
+// waves cover 64 rows each.
 __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos, int* cpos)
 {
     const DevPlan& pl = a.pl;
@@ -394,21 +389,16 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
     if (tid < mrows) rpos[tid] = a.rmap[mbase + row0 + tid];
     if (tid < ncols) cpos[tid] = a.rmap[mbase + col0 + tid];
     __syncthreads();
-    const bool wide = ncols > 32;
-    const int npass = wide ? 2 : 1;
-    for (int pass = 0; pass < npass; ++pass) {
-        const int r0 = wide ? 128 * pass + 64 * (wave & 1) : 64 * wave;
-        const int c0 = wide ? 32 * (wave >> 1) : 0;
-        const int mv = min(64, mrows - r0), nv = min(32, ncols - c0);
-        if (mv > 0 && nv > 0) {
-            d4 acc[2][4];
-            zero_acc(acc);
-            wave_gemm<2>(acc, make_gop(A, ld * w, row0 + r0, 1, ld), make_gop(A, ld * w, col0 + c0, 1, ld), w);
-            wave_store(acc, mv, nv, [&](int r, int c, double v) {
-                const int tr = rpos[r0 + r], tc = cpos[c0 + c];
-                if (tr >= tc) unsafeAtomicAdd(C + (int64_t)tc * ldj + tr, -v);
-            });
-        }
+    const int r0 = 64 * wave;
+    const int mv = min(64, mrows - r0);
+    if (mv > 0) {
+        d4 acc[4][4];
+        zero_acc(acc);
+        wave_gemm<4>(acc, make_gop(A, ld * w, row0 + r0, 1, ld), make_gop(A, ld * w, col0, 1, ld), w);
+        wave_store(acc, mv, ncols, [&](int r, int c, double v) {
+            const int tr = rpos[r0 + r], tc = cpos[c];
+            if (tr >= tc) unsafeAtomicAdd(C + (int64_t)tc * ldj + tr, -v);
+        });
     }
 }
 
