@@ -54,7 +54,12 @@ enum spx_status {
 enum spx_method { SPX_LLT = 0 };
 
 enum spx_precision {
-    SPX_FP64 = 0      /* factor stored and computed in FP64 */
+    SPX_FP64 = 0,     /* factor stored and computed in FP64 */
+    SPX_FP32_IR = 1   /* factor stored in FP32, products on the FP32 matrix cores
+                       * (the 32x32 diagonal tiles are factored and inverted in
+                       * FP64 and rounded); the solve applies the FP32 factor
+                       * in FP64 arithmetic and refines with the FP64 residual
+                       * until omega <= ir_tol */
 };
 
 typedef struct spx_options {
@@ -64,7 +69,8 @@ typedef struct spx_options {
     int32_t split_width;      /* column blocks wider than this are split (256, at most 256) */
     const int32_t* user_perm; /* optional ordering (new -> old) replacing nested dissection */
     int32_t precision;        /* enum spx_precision */
-    int32_t ir_max_iter;      /* refinement steps after the first solve (2) */
+    int32_t ir_max_iter;      /* refinement steps after the first solve; -1 (default):
+                               * 2 for SPX_FP64, 10 for SPX_FP32_IR */
     double ir_tol;            /* componentwise backward error target (1e-14) */
     int32_t trace;            /* 1: record a per-work-item trace of each factorization (0) */
 } spx_options;
@@ -145,7 +151,8 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
 /* Solve A X = B for nrhs right-hand sides stored column-major with leading
  * dimension ldb >= n; B is overwritten with X.  b is a device pointer if
  * b_on_device, else a host pointer.  Runs the forward and backward sweeps,
- * then FP64 refinement until omega <= ir_tol or ir_max_iter steps.
+ * then FP64 refinement until omega <= ir_tol, ir_max_iter steps, or
+ * stagnation (omega above half its previous value in two consecutive steps).
  * info may be NULL.  Errors: SPX_ESTATE, SPX_EINVAL, SPX_ENOCONV, SPX_EDEVICE. */
 int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_device,
               spx_solve_info* info, void* hip_stream);
@@ -159,7 +166,8 @@ int spx_export_symbolic(const spx_handle* h, spx_symbolic_view* view);
 
 /* Copy the factor panels (panel_entries doubles, layout of the symbolic
  * view; the strict upper triangle of diagonal blocks is zero) to dst, a host
- * or device pointer.  Errors: SPX_ESTATE before a factorization. */
+ * or device pointer.  An FP32 factor is widened to FP64.  Errors: SPX_ESTATE
+ * before a factorization. */
 int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip_stream);
 
 /* Task trace of the last factorization (trace option on): 4 int64 per work

@@ -21,12 +21,15 @@
 namespace spx {
 
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
-hipError_t launch_assemble(double* panels, const int64_t* amap, const double* values, int64_t nnz, hipStream_t s);
+hipError_t launch_assemble(void* panels, bool f32, const int64_t* amap, const double* values, int64_t nnz,
+                           hipStream_t s);
+hipError_t launch_widen(double* dst, const float* src, int64_t n, hipStream_t s);
 hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, int32_t nready_hp,
                              const int32_t* fact_dep0, int32_t ncblk, hipStream_t s);
-int sched_blocks_per_cu();
-hipError_t launch_sched(const SchedArgs& a, int grid, hipStream_t s);
+int sched_blocks_per_cu(bool f32);
+hipError_t launch_sched(const SchedArgs& a, bool f32, int grid, hipStream_t s);
 hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
 hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
 hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
@@ -36,6 +39,7 @@ hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int3
 hipError_t launch_permute_out(double* x, int64_t ldx, const double* y, const int32_t* perm, int32_t n, int32_t nrhs,
                               hipStream_t s);
 hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const int64_t* rval, const double* vals,
                            const double* x, const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
                            unsigned long long* stats, hipStream_t s);
@@ -122,17 +126,23 @@ struct spx_handle {
     Level lv;
     DevBuf<int32_t> lv_cblk;
     DevBuf<int2> lv_chunk;
-    // numeric
+    // numeric: FP64 panels and inverses, or their FP32 counterparts
     DevBuf<double> panels, dinv, vals;
+    DevBuf<float> panels_f, dinv_f;
     int64_t dinv_size = 0;
     bool factorized = false;
     int32_t fail_col = -1;
     bool logdet_valid = false;
     double logdet = 0.0;
     double factor_ms = 0.0, assemble_ms = 0.0;
-    // solve work
-    DevBuf<double> y, tacc, xw, rw, bw;
+    // solve work (internal buffers, n x nrhs_cap) and the captured sweep graph
+    DevBuf<double> y, tacc, xw, rw, dw, bw;
     DevBuf<unsigned long long> stats;
+    int32_t nrhs_cap = 0;
+    int32_t graph_nrhs = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     int device = 0;
     int grid = 0;
@@ -143,7 +153,22 @@ struct spx_handle {
     {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
+
+    void drop_graph()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+        graph_nrhs = 0;
+    }
+
+    bool f32() const { return opt.precision == SPX_FP32_IR; }
+    void* panel_ptr() { return f32() ? static_cast<void*>(panels_f.p) : static_cast<void*>(panels.p); }
+    void* dinv_ptr() { return f32() ? static_cast<void*>(dinv_f.p) : static_cast<void*>(dinv.p); }
 
     DevPlan devplan() const
     {
@@ -395,7 +420,7 @@ void upload_plan(spx_handle* h)
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
     if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess || clk_khz <= 0)
         clk_khz = 100000;
-    h->grid = std::max(1, ncu * sched_blocks_per_cu());
+    h->grid = std::max(1, ncu * sched_blocks_per_cu(h->f32()));
     h->timeout_ticks = static_cast<int64_t>(clk_khz) * 1000 * 20;   // 20 s per wait
 }
 
@@ -403,8 +428,9 @@ void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
 {
     SweepArgs a;
     a.pl = h->devplan();
-    a.panels = h->panels.p;
-    a.dinv = h->dinv.p;
+    a.panels = h->panel_ptr();
+    a.dinv = h->dinv_ptr();
+    a.f32 = h->f32() ? 1 : 0;
     a.rowg = h->rowg.p;
     a.rowg_off = h->rowg_off.p;
     a.y = y;
@@ -448,7 +474,7 @@ void spx_default_options(spx_options* o)
     o->split_width = 256;
     o->user_perm = nullptr;
     o->precision = SPX_FP64;
-    o->ir_max_iter = 2;
+    o->ir_max_iter = -1;
     o->ir_tol = 1e-14;
     o->trace = 0;
 }
@@ -467,8 +493,10 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
     if (opt) h->opt = *opt; else spx_default_options(&h->opt);
     int rc = guarded(h, [&]() -> int {
         if (h->opt.method != SPX_LLT) throw InvalidArgument("only SPX_LLT is supported");
-        if (h->opt.precision != SPX_FP64) throw InvalidArgument("unsupported precision");
-        if (h->opt.ir_max_iter < 0) throw InvalidArgument("ir_max_iter must be >= 0");
+        if (h->opt.precision != SPX_FP64 && h->opt.precision != SPX_FP32_IR)
+            throw InvalidArgument("unsupported precision");
+        if (h->opt.ir_max_iter < -1) throw InvalidArgument("ir_max_iter must be >= 0, or -1 for the default");
+        if (h->opt.ir_max_iter == -1) h->opt.ir_max_iter = h->opt.precision == SPX_FP32_IR ? 10 : 2;
         Options o;
         o.leaf_size = h->opt.leaf_size;
         o.amalg_pct = h->opt.amalg_pct;
@@ -508,19 +536,27 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
         if (h->nnz > 0)
             HIPCHK(hipMemcpyAsync(h->vals.p, values, h->nnz * sizeof(double),
                                   values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
-        h->panels.alloc(static_cast<size_t>(P.panel_entries));
-        if (!h->dinv.p) {
+        const bool f32 = h->f32();
+        if (f32) h->panels_f.alloc(static_cast<size_t>(P.panel_entries));
+        else h->panels.alloc(static_cast<size_t>(P.panel_entries));
+        if (!h->dinv_ptr()) {
             // blocks above the diagonal of each inverse are never written: zero them once
-            h->dinv.alloc(static_cast<size_t>(h->dinv_size));
-            HIPCHK(launch_fill_f64(h->dinv.p, h->dinv_size, 0.0, s));
+            if (f32) {
+                h->dinv_f.alloc(static_cast<size_t>(h->dinv_size));
+                HIPCHK(launch_fill_f32(h->dinv_f.p, h->dinv_size, 0.0f, s));
+            } else {
+                h->dinv.alloc(static_cast<size_t>(h->dinv_size));
+                HIPCHK(launch_fill_f64(h->dinv.p, h->dinv_size, 0.0, s));
+            }
         }
         HIPCHK(hipEventRecord(h->ev[0], s));
-        HIPCHK(launch_fill_f64(h->panels.p, P.panel_entries, 0.0, s));
-        HIPCHK(launch_assemble(h->panels.p, h->amap.p, h->vals.p, h->nnz, s));
+        if (f32) HIPCHK(launch_fill_f32(h->panels_f.p, P.panel_entries, 0.0f, s));
+        else HIPCHK(launch_fill_f64(h->panels.p, P.panel_entries, 0.0, s));
+        HIPCHK(launch_assemble(h->panel_ptr(), f32, h->amap.p, h->vals.p, h->nnz, s));
         SchedArgs a;
         a.pl = h->devplan();
-        a.panels = h->panels.p;
-        a.dinv = h->dinv.p;
+        a.panels = h->panel_ptr();
+        a.dinv = h->dinv_ptr();
         a.desc = h->desc.p;
         a.rmap = h->rmap.p;
         a.hp_total = h->hp_total;
@@ -548,7 +584,7 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
         }
         HIPCHK(launch_sched_init(a, h->ready.p, h->nready, h->nready_hp, h->fact_dep0.p, P.ncblk, s));
         HIPCHK(hipEventRecord(h->ev[1], s));
-        if (h->total > 0) HIPCHK(launch_sched(a, h->grid, s));
+        if (h->total > 0) HIPCHK(launch_sched(a, f32, h->grid, s));
         HIPCHK(hipEventRecord(h->ev[2], s));
         int32_t st[4] = {INT_MAX, 0, 0, 0};
         HIPCHK(hipMemcpyAsync(st, h->status.p, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -585,30 +621,40 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
         const int32_t n = h->n;
         const size_t tot = static_cast<size_t>(n) * nrhs;
-        h->y.alloc(tot);
-        h->tacc.alloc(tot);
-        h->xw.alloc(tot);
-        h->rw.alloc(tot);
-        h->stats.alloc(5);
-        const double* bd = b;
-        int64_t ldbd = ldb;
-        if (!b_on_device) {
-            h->bw.alloc(tot);
-            HIPCHK(hipMemcpy2DAsync(h->bw.p, n * sizeof(double), b, ldb * sizeof(double), n * sizeof(double), nrhs,
-                                    hipMemcpyHostToDevice, s));
-            bd = h->bw.p;
-            ldbd = n;
+        if (nrhs > h->nrhs_cap) {
+            // new buffers: a graph captured on the old ones is stale
+            h->drop_graph();
+            const size_t cap = static_cast<size_t>(n) * nrhs;
+            h->y.release(); h->tacc.release(); h->xw.release(); h->rw.release(); h->dw.release(); h->bw.release();
+            h->y.alloc(cap); h->tacc.alloc(cap); h->xw.alloc(cap); h->rw.alloc(cap); h->dw.alloc(cap); h->bw.alloc(cap);
+            h->nrhs_cap = nrhs;
         }
+        h->stats.alloc(5);
+        if (h->graph_nrhs != nrhs) {
+            // one application of A^{-1}: dw = P^T L^{-T} L^{-1} P rw, captured once per nrhs
+            h->drop_graph();
+            if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+            HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            HIPCHK(launch_permute_in(h->y.p, h->rw.p, n, h->perm.p, n, nrhs, h->cap_stream));
+            sweeps(h, h->y.p, nrhs, h->cap_stream);
+            HIPCHK(launch_permute_out(h->dw.p, n, h->y.p, h->perm.p, n, nrhs, h->cap_stream));
+            HIPCHK(hipStreamEndCapture(h->cap_stream, &h->graph));
+            HIPCHK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+            h->graph_nrhs = nrhs;
+        }
+        // the right-hand side, packed (leading dimension n)
+        HIPCHK(hipMemcpy2DAsync(h->bw.p, n * sizeof(double), b, ldb * sizeof(double), n * sizeof(double), nrhs,
+                                b_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         // x0 = A^{-1} b
-        HIPCHK(launch_permute_in(h->y.p, bd, ldbd, h->perm.p, n, nrhs, s));
-        sweeps(h, h->y.p, nrhs, s);
-        HIPCHK(launch_permute_out(h->xw.p, n, h->y.p, h->perm.p, n, nrhs, s));
-        int iters = 0;
-        double omega = 0.0, eta = 0.0;
+        HIPCHK(hipMemcpyAsync(h->rw.p, h->bw.p, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipGraphLaunch(h->graph_exec, s));
+        HIPCHK(hipMemcpyAsync(h->xw.p, h->dw.p, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+        int iters = 0, slow = 0;
+        double omega = 0.0, eta = 0.0, prev = INFINITY;
         const double tol = h->opt.ir_tol;
         for (;;) {
-            HIPCHK(hipMemsetAsync(h->stats.p, 0, 5 * sizeof(unsigned long long), s));
-            HIPCHK(launch_residual(h->rptr.p, h->rcol.p, h->rval.p, h->vals.p, h->xw.p, bd, ldbd, h->rw.p, n, nrhs,
+            HIPCHK(launch_zero_u64(h->stats.p, 5, s));
+            HIPCHK(launch_residual(h->rptr.p, h->rcol.p, h->rval.p, h->vals.p, h->xw.p, h->bw.p, n, h->rw.p, n, nrhs,
                                    h->stats.p, s));
             unsigned long long st[5];
             HIPCHK(hipMemcpyAsync(st, h->stats.p, sizeof st, hipMemcpyDeviceToHost, s));
@@ -619,20 +665,17 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
             const double den = v[4] * v[2] + v[3];
             eta = v[1] == 0.0 ? 0.0 : (den == 0.0 ? INFINITY : v[1] / den);
             if (omega <= tol || iters >= h->opt.ir_max_iter) break;
+            // stagnation: omega above half its previous value twice in a row
+            slow = omega > 0.5 * prev ? slow + 1 : 0;
+            if (slow >= 2) break;
+            prev = omega;
             // d = A^{-1} r ; x += d
-            HIPCHK(launch_permute_in(h->y.p, h->rw.p, n, h->perm.p, n, nrhs, s));
-            sweeps(h, h->y.p, nrhs, s);
-            HIPCHK(launch_permute_out(h->rw.p, n, h->y.p, h->perm.p, n, nrhs, s));
-            HIPCHK(launch_axpy(h->xw.p, h->rw.p, static_cast<int64_t>(tot), s));
+            HIPCHK(hipGraphLaunch(h->graph_exec, s));
+            HIPCHK(launch_axpy(h->xw.p, h->dw.p, static_cast<int64_t>(tot), s));
             ++iters;
         }
-        if (b_on_device) {
-            HIPCHK(hipMemcpy2DAsync(b, ldb * sizeof(double), h->xw.p, n * sizeof(double), n * sizeof(double), nrhs,
-                                    hipMemcpyDeviceToDevice, s));
-        } else {
-            HIPCHK(hipMemcpy2DAsync(b, ldb * sizeof(double), h->xw.p, n * sizeof(double), n * sizeof(double), nrhs,
-                                    hipMemcpyDeviceToHost, s));
-        }
+        HIPCHK(hipMemcpy2DAsync(b, ldb * sizeof(double), h->xw.p, n * sizeof(double), n * sizeof(double), nrhs,
+                                b_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         const bool conv = omega <= tol;
         if (info) *info = spx_solve_info{iters, conv ? 1 : 0, omega, eta};
@@ -650,12 +693,18 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
         if (h->factorized && !h->logdet_valid) {
             // 2 * sum log l_jj with pairwise summation, from the diagonal of each panel
             std::vector<double> diag(static_cast<size_t>(P.n));
+            std::vector<float> diag_f(h->f32() ? static_cast<size_t>(P.n) : 0);
             for (int32_t k = 0; k < P.ncblk; ++k) {
                 const int32_t w = P.lcol[k] - P.fcol[k] + 1;
-                HIPCHK(hipMemcpy2D(diag.data() + P.fcol[k], sizeof(double), h->panels.p + P.panel_off[k],
-                                   (static_cast<size_t>(P.stride[k]) + 1) * sizeof(double), sizeof(double), w,
-                                   hipMemcpyDeviceToHost));
+                const size_t pitch = static_cast<size_t>(P.stride[k]) + 1;
+                if (h->f32())
+                    HIPCHK(hipMemcpy2D(diag_f.data() + P.fcol[k], sizeof(float), h->panels_f.p + P.panel_off[k],
+                                       pitch * sizeof(float), sizeof(float), w, hipMemcpyDeviceToHost));
+                else
+                    HIPCHK(hipMemcpy2D(diag.data() + P.fcol[k], sizeof(double), h->panels.p + P.panel_off[k],
+                                       pitch * sizeof(double), sizeof(double), w, hipMemcpyDeviceToHost));
             }
+            if (h->f32()) std::copy(diag_f.begin(), diag_f.end(), diag.begin());
             for (auto& d : diag) d = 2.0 * std::log(d);
             h->logdet = pairwise_sum(diag.data(), P.n);
             h->logdet_valid = true;
@@ -719,9 +768,21 @@ int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip
         if (!h->factorized) throw StatusError(SPX_ESTATE, "no factorization");
         if (!dst && h->plan.panel_entries > 0) throw InvalidArgument("dst is NULL");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        if (h->plan.panel_entries > 0)
-            HIPCHK(hipMemcpyAsync(dst, h->panels.p, h->plan.panel_entries * sizeof(double),
+        const int64_t ne = h->plan.panel_entries;
+        if (ne > 0 && h->f32()) {
+            if (dst_on_device) {
+                HIPCHK(launch_widen(dst, h->panels_f.p, ne, s));
+            } else {
+                DevBuf<double> tmp;
+                tmp.alloc(static_cast<size_t>(ne));
+                HIPCHK(launch_widen(tmp.p, h->panels_f.p, ne, s));
+                HIPCHK(hipMemcpyAsync(dst, tmp.p, ne * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+            }
+        } else if (ne > 0) {
+            HIPCHK(hipMemcpyAsync(dst, h->panels.p, ne * sizeof(double),
                                   dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+        }
         HIPCHK(hipStreamSynchronize(s));
         return SPX_OK;
     });

@@ -30,8 +30,8 @@ enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2 };
 //            mrows, col0 (first facing panel row), ncols, mbase (row-map base)
 struct SchedArgs {
     DevPlan pl;
-    double* panels;
-    double* dinv;
+    void* panels;            // double, or float in the FP32 refinement mode
+    void* dinv;              // same element type as the panels
     const int4* desc;
     const int32_t* rmap;     // panel row of k -> row inside panel j, per update pair
     int32_t hp_total;        // items of the high-priority queue (FACT, TRSM, chain updates)
@@ -58,8 +58,9 @@ struct SchedArgs {
 // Arguments of the triangular sweeps.
 struct SweepArgs {
     DevPlan pl;
-    const double* panels;
-    const double* dinv;
+    const void* panels;       // double, or float in the FP32 refinement mode
+    const void* dinv;
+    int32_t f32;              // 1: panels and inverses are float
     const int32_t* rowg;      // global row of every off-diagonal panel row
     const int64_t* rowg_off;  // [ncblk] start of cblk k's rows in rowg
     double* y;                // permuted vectors, n x nrhs, leading dimension n

@@ -17,19 +17,41 @@
 // into j is done, the TRSM tiles of k when FACT(k) is done, the UPDATE tiles
 // of k when its last TRSM tile is done.  FACT, TRSM and the updates into the
 // next block of a chain go to a high-priority queue that workers poll first.
-// Products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+// Products run on the matrix cores: v_mfma_f64_16x16x4f64 for the FP64
+// factor, v_mfma_f32_16x16x4f32 for the FP32 factor of the refinement mode
+// (whose 32x32 diagonal tiles are still factored and inverted in FP64).
 #include "device.hpp"
 
 namespace spx {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 #define AGENT __HIP_MEMORY_SCOPE_AGENT
 
-__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// The 16x16x4 matrix-core product of one element type.  Operand A lane l
+// holds A[l%16][l/16], operand B lane l holds B[l/16][l%16]; the four result
+// slots of lane l hold column l%16 of D, at the rows drow(v, l/16).
+template <class T>
+struct MM;
+template <>
+struct MM<double> {
+    typedef d4 acc;
+    static __device__ __forceinline__ acc mfma(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int v, int lk) { return 4 * v + lk; }
+};
+template <>
+struct MM<float> {
+    typedef f4 acc;
+    static __device__ __forceinline__ acc mfma(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int v, int lk) { return 4 * lk + v; }
+};
 
 __device__ __forceinline__ double readlane_d(double v, int lane)
 {
@@ -55,43 +77,52 @@ struct GOp {
 // Values the whole wave shares, moved to scalar registers (buffer resources
 // must be uniform; the compiler cannot prove it for values read from memory).
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ const double* uni(const double* p)
+template <class T>
+__device__ __forceinline__ const T* uni(const T* p)
 {
     const uint64_t u = reinterpret_cast<uint64_t>(p);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-    return reinterpret_cast<const double*>(((uint64_t)hi << 32) | lo);
+    return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ GOp make_gop(const double* base, int64_t count, int64_t off, int64_t si, int64_t sk)
+template <class T>
+__device__ __forceinline__ GOp make_gop(const T* base, int64_t count, int64_t off, int64_t si, int64_t sk)
 {
+    constexpr int e = (int)sizeof(T);
     GOp g;
-    g.rs = __builtin_amdgcn_make_buffer_rsrc((void*)uni(base), (short)0, uni((int)(count * 8)), 0x00020000);
-    g.off = uni((int)(off * 8));
-    g.si = uni((int)(si * 8));
-    g.sk = uni((int)(sk * 8));
+    g.rs = __builtin_amdgcn_make_buffer_rsrc((void*)uni(base), (short)0, uni((int)(count * e)), 0x00020000);
+    g.off = uni((int)(off * e));
+    g.si = uni((int)(si * e));
+    g.sk = uni((int)(sk * e));
     return g;
 }
 
-__device__ __forceinline__ double gload(const GOp& g, int voff)
+template <class T>
+__device__ __forceinline__ T gload(const GOp& g, int voff);
+template <>
+__device__ __forceinline__ double gload<double>(const GOp& g, int voff)
 {
     const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(g.rs, voff, 0, 0);
     return __builtin_bit_cast(double, b);
+}
+template <>
+__device__ __forceinline__ float gload<float>(const GOp& g, int voff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(g.rs, voff, 0, 0));
 }
 
 // One wave accumulates a 64 x (16*NB) tile: acc += X Y^T, X(r, p) r < 64,
 // Y(c, p) c < 16*NB, p < K (K rounded up to 8 reads zeros or is exact).  The
 // whole tile is always computed (no per-block predicates); rows and columns
 // beyond the caller's bounds produce results that are not stored.
-// The f64 16x16x4 matrix-core lane layout is: operand A lane l holds
-// A[l%16][l/16], operand B lane l holds B[l/16][l%16], result slot v of lane
-// l holds D[4v + l/16][l%16].  Y feeds operand A and X operand B, so
-//   acc[bi][bj][v] = C(16*bj + l%16, 16*bi + 4v + l/16)
+// Y feeds operand A and X operand B (lane layout in MM), so
+//   acc[bi][bj][v] = C(16*bj + l%16, 16*bi + drow(v, l/16))
 // and the 16 lanes of a result slot cover 16 consecutive rows of C.  The
-// inner dimension advances 8 at a time through two register buffers: the
-// operands of the next 8 are in flight while the products of the current 8
+// inner dimension advances 8 at a time through three register buffers: the
+// operands of the next 16 are in flight while the products of the current 8
 // are issued.
-template <int NB>
-__device__ __forceinline__ void wave_gemm(d4 (&acc)[NB][4], const GOp& X, const GOp& Y, int K)
+template <int NB, class T>
+__device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][4], const GOp& X, const GOp& Y, int K)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -106,74 +137,54 @@ __device__ __forceinline__ void wave_gemm(d4 (&acc)[NB][4], const GOp& X, const 
         for (int b = 0; b < NB; ++b) yo[u][b] = Y.off + (16 * b + li) * Y.si + (4 * u + lk) * Y.sk;
     }
     const int dx = 8 * X.sk, dy = 8 * Y.sk;
-    double xa[2][4], ya[2][NB], xb[2][4], yb[2][NB];
-    auto load = [&](double (&xs)[2][4], double (&ys)[2][NB], int ch) {
+    T xa[2][4], ya[2][NB], xb[2][4], yb[2][NB], xc[2][4], yc[2][NB];
+    auto load = [&](T (&xs)[2][4], T (&ys)[2][NB], int ch) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) xs[u][b] = gload(X, xo[u][b] + ch * dx);
+            for (int b = 0; b < 4; ++b) xs[u][b] = gload<T>(X, xo[u][b] + ch * dx);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) ys[u][b] = gload(Y, yo[u][b] + ch * dy);
+            for (int b = 0; b < NB; ++b) ys[u][b] = gload<T>(Y, yo[u][b] + ch * dy);
         }
     };
-    auto mma = [&](const double (&xs)[2][4], const double (&ys)[2][NB]) {
+    auto mma = [&](const T (&xs)[2][4], const T (&ys)[2][NB]) {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma_f64(ys[u][bi], xs[u][bj], acc[bi][bj]);
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MM<T>::mfma(ys[u][bi], xs[u][bj], acc[bi][bj]);
     };
+    // three register buffers: two chunks in flight while one is multiplied
+    // (reads past the last chunk repeat it and are not used)
+    const int last = nchunks - 1;
     load(xa, ya, 0);
+    load(xb, yb, min(1, last));
     int ch = 0;
-    for (; ch + 2 <= nchunks; ch += 2) {
-        load(xb, yb, ch + 1);
+    for (; ch + 3 <= nchunks; ch += 3) {
+        load(xc, yc, min(ch + 2, last));
         mma(xa, ya);
-        load(xa, ya, min(ch + 2, nchunks - 1));
+        load(xa, ya, min(ch + 3, last));
         mma(xb, yb);
+        load(xb, yb, min(ch + 4, last));
+        mma(xc, yc);
     }
     if (ch < nchunks) mma(xa, ya);
+    if (ch + 1 < nchunks) mma(xb, yb);
 }
 
-// Same product with Y in LDS: Y(c, p) = Y[c*ysc + p*ysp], masked to c < nv, p < K.
-template <int NB>
-__device__ __forceinline__ void wave_gemm_lds(d4 (&acc)[NB][4], const GOp& X, int nbx, const double* Y, int ysc,
-                                              int ysp, int nv, int K)
-{
-    const int lane = threadIdx.x & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int nby = min(NB, (nv + 15) >> 4);
-    if (nbx <= 0 || nby <= 0) return;
-    for (int p0 = 0; p0 < K; p0 += 4) {
-        const int p = p0 + lk;
-        double xs[4], ys[NB];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) xs[b] = b < nbx ? gload(X, X.off + (16 * b + li) * X.si + p * X.sk) : 0.0;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int c = 16 * b + li;
-            ys[b] = (c < nv && p < K) ? Y[c * ysc + p * ysp] : 0.0;
-        }
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
-                if (bi < nby && bj < nbx) acc[bi][bj] = mfma_f64(ys[bi], xs[bj], acc[bi][bj]);
-    }
-}
-
-template <int NB>
-__device__ __forceinline__ void zero_acc(d4 (&acc)[NB][4])
+template <int NB, class A>
+__device__ __forceinline__ void zero_acc(A (&acc)[NB][4])
 {
 #pragma unroll
     for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 4; ++j) acc[i][j] = A{0, 0, 0, 0};
 }
 
 // epi(r, c, value) over a wave's accumulator, r < mv, c < nv
-template <int NB, class Epi>
-__device__ __forceinline__ void wave_store(const d4 (&acc)[NB][4], int mv, int nv, Epi epi)
+template <class T, int NB, class Epi>
+__device__ __forceinline__ void wave_store(const typename MM<T>::acc (&acc)[NB][4], int mv, int nv, Epi epi)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -183,164 +194,255 @@ __device__ __forceinline__ void wave_store(const d4 (&acc)[NB][4], int mv, int n
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = 16 * bj + li, c = 16 * bi + 4 * v + lk;
+                const int r = 16 * bj + li, c = 16 * bi + MM<T>::drow(v, lk);
                 if (r < mv && c < nv) epi(r, c, acc[bi][bj][v]);
             }
 }
 
-__device__ __forceinline__ int nblk(int n) { return (n + 15) >> 4; }
-
 // ---------------------------------------------------------------- FACT(k)
-// Cholesky of one 32x32 tile kept in LDS (Ls, column-major, ld 33), by one
-// wave: row r is loaded into registers of lanes r and r+32, columns are
-// eliminated one by one with the pivot column broadcast through readlane.
-// Rows/columns >= jb must hold the identity.  Pivots that are not > 0 record
-// their column with atomicMin and the computation goes on (NaN propagates).
-__device__ __noinline__ void tile_potrf(double* Ls, int jb, int col0, int32_t* status)
+// Cholesky factor and inverse of one 32x32 diagonal tile, in FP64, by one
+// wave.  Lt (column-major, ld 33) holds the lower triangle of the tile; rows
+// and columns >= jb hold the identity.  Lane r < 32 keeps row r of the tile,
+// lane 32 + q keeps column q of X = L^{-1}, starting from the unit vector
+// e_q.  One right-looking loop over the columns c serves both halves: the
+// pivot l_cc is broadcast by readlane, column c is scaled by 1/l_cc (the
+// pivot itself becomes sqrt of it), its entries l_ic go to LDS (bc), and every
+// lane updates v[i] -= v[c] * l_ic for i > c.  For a row of the tile that is
+// the Cholesky update of its remaining columns; for a column of X it is the
+// forward substitution step x_iq -= l_ic x_cq after x_cq was divided by
+// l_cc.  Entries above the diagonal of the tile rows are not meaningful and
+// never read.  A pivot that is not > 0 records its column with atomicMin
+// (NaN propagates).  Out: L in Lt (upper triangle zero), X in Dt.
+template <class T>
+__device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb, int col0, int32_t* status)
 {
     const int lane = threadIdx.x & 63;
     const int r = lane & 31;
-    double t[32];
-#pragma unroll
-    for (int c = 0; c < 32; ++c) t[c] = Ls[r + c * 33];
+    const bool upper = lane >= 32;
+    double v[32];
 #pragma unroll
     for (int c = 0; c < 32; ++c) {
-        const double d = readlane_d(t[c], c);
-        if (c < jb && !(d > 0.0) && lane == 0) atomicMin(status, col0 + c);
-        const double s = sqrt(d);
-        const double inv = 1.0 / s;
-        if (r == c) t[c] = s;
-        else if (r > c) t[c] *= inv;
-#pragma unroll
-        for (int c2 = c + 1; c2 < 32; ++c2) {
-            const double l2 = readlane_d(t[c], c2);
-            if (r >= c2) t[c2] -= t[c] * l2;
-        }
+        const double l = Lt[r + c * 33];
+        v[c] = upper ? (c == r ? 1.0 : 0.0) : l;
     }
-    if (lane < 32) {
+    // pivot of column c: s = sqrt(l_cc), inv = 1/s by the hardware reciprocal
+    // and two Newton-Raphson steps (the IEEE division expansion spills
+    // registers in this unrolled loop)
+    int fail = 32;
+    auto pivot = [&](int c, double& s, double& inv) {
+        const double d = readlane_d(v[c], c);
+        fail = (c < jb && !(d > 0.0) && fail == 32) ? c : fail;
+        s = sqrt(d);
+        inv = __builtin_amdgcn_rcp(s);
+        inv = __builtin_fma(inv, __builtin_fma(-s, inv, 1.0), inv);
+        inv = __builtin_fma(inv, __builtin_fma(-s, inv, 1.0), inv);
+    };
+    double s, inv;
+    pivot(0, s, inv);
 #pragma unroll
-        for (int c = 0; c < 32; ++c) Ls[r + c * 33] = c <= r ? t[c] : 0.0;
+    for (int c = 0; c < 32; ++c) {
+        v[c] = lane == c ? s : v[c] * inv;
+        if (c < 31) {
+            // column c to bc[0..31] (the upper half writes the unused
+            // bc[32..63]); LDS operations of one wave complete in order, so
+            // the reads below see it (compiler barrier only)
+            bc[lane] = v[c];
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            // column c+1 first: its pivot overlaps the rest of the update
+            v[c + 1] -= v[c] * bc[c + 1];
+            double sn, invn;
+            pivot(c + 1, sn, invn);
+#pragma unroll
+            for (int i = c + 2; i < 32; ++i) v[i] -= v[c] * bc[i];
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            s = sn;
+            inv = invn;
+        }
+        // keep the scheduler from interleaving column steps (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (lane == 0 && fail < jb) atomicMin(status, col0 + fail);
+    if (!upper) {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) Lt[r + c * 33] = c <= r ? v[c] : 0.0;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) Dt[c + r * 33] = c >= r ? (T)v[c] : T(0);
     }
 }
 
-// Inverse X = L^{-1} of the lower triangular 32x32 tile Ls, by one wave in
-// the same row-per-lane layout: column c of L is eliminated from the rows
-// below once row c of X is final (row c of X divided by l_cc, then
-// x_r -= l_rc x_c for r > c, with x_c broadcast through readlane).  Row r of
-// X (r < jb) is stored at D + r, columns strided by ldd.
-__device__ __noinline__ void tile_trtri(const double* Ls, double* D, int ldd, int jb)
+// Small product of the diagonal-block factorization: acc += X Y^T with
+// X(i, p), i < 64, and Y(c, p), c < 16*NB, given by loader functions;
+// p < K <= 32 (masked).  Fully unrolled, so that every operand load is
+// issued before the first product.
+template <int NB, class T, class LX, class LY>
+__device__ __forceinline__ void wave_mm(typename MM<T>::acc (&acc)[NB][4], LX ldx, LY ldy, int K)
 {
     const int lane = threadIdx.x & 63;
-    const int r = lane & 31;
-    double t[32], x[32];
+    const int li = lane & 15, lk = lane >> 4;
+    T xs[8][4], ys[8][NB];
 #pragma unroll
-    for (int c = 0; c < 32; ++c) {
-        t[c] = Ls[r + c * 33];
-        x[c] = (c == r) ? 1.0 : 0.0;
+    for (int q = 0; q < 8; ++q) {
+        const int p = 4 * q + lk;
+        const bool ok = p < K;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) xs[q][b] = ok ? ldx(16 * b + li, p) : T(0);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) ys[q][b] = ok ? ldy(16 * b + li, p) : T(0);
     }
 #pragma unroll
-    for (int c = 0; c < 32; ++c) {
-        const double inv = 1.0 / readlane_d(t[c], c);
+    for (int q = 0; q < 8; ++q)
 #pragma unroll
-        for (int q = 0; q <= c; ++q) x[q] = (r == c) ? x[q] * inv : x[q];
+        for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-        for (int q = 0; q <= c; ++q) {
-            const double xc = readlane_d(x[q], c);
-            if (r > c) x[q] -= t[c] * xc;
-        }
-    }
-    if (lane < jb) {
-#pragma unroll
-        for (int q = 0; q < 32; ++q)
-            if (q < jb) D[r + (int64_t)q * ldd] = q <= r ? x[q] : 0.0;
-    }
+            for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MM<T>::mfma(ys[q][bi], xs[q][bj], acc[bi][bj]);
 }
 
-// Left-looking blocked Cholesky of the w x w diagonal block (w <= 256) by one
-// workgroup, 32 columns at a time: subtract the products of the factored
-// columns (matrix cores), factor and invert the 32x32 diagonal tile in
-// registers (wave 0), multiply the rows below by the tile inverse's
-// transpose.  Then the blocked inverse D = L_kk^{-1} (lower, w x w,
-// column-major; its upper triangle stays zero) is formed block row by block
-// row:  D_IJ = -D_II * sum_{J<=K<I} L_IK D_KJ.
-__device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Ls, double* Gs)
+// acc -> C with C(r, c) = f(old C(r, c), value) at ptr(r, c) for the entries
+// with r < mv, c < nv and keep(r, c): every old value is loaded before the
+// first store (the stores could otherwise alias later loads and serialize
+// them).
+template <class T, int NB, class Ptr, class Keep, class F>
+__device__ __forceinline__ void wave_rmw(const typename MM<T>::acc (&acc)[NB][4], int mv, int nv, Ptr ptr, Keep keep,
+                                         F f)
 {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    T old[NB][4][4];
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * bj + li, c = 16 * bi + MM<T>::drow(v, lk);
+                old[bi][bj][v] = (r < mv && c < nv && keep(r, c)) ? *ptr(r, c) : T(0);
+            }
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * bj + li, c = 16 * bi + MM<T>::drow(v, lk);
+                if (r < mv && c < nv && keep(r, c)) *ptr(r, c) = f(old[bi][bj][v], acc[bi][bj][v]);
+            }
+}
+
+constexpr int kPbLd = 228;   // leading dimension of the LDS copy of the rows below a tile (<= 224 rows)
+
+// Cholesky factorization of the w x w diagonal block (w <= 256) of panel k
+// and the inverse D = L_kk^{-1}, by one workgroup, right-looking over 32
+// columns at a time.  The running inverse uses the block form of L D = I:
+// block row I of D is D_II (E_I - sum_{K<I} L_IK D_K), accumulated as the
+// columns of L become final.  Step J (tile columns J .. J+jb):
+//   1. the tile, fully updated, is factored and inverted by wave 0
+//      (tile_chol_inv): L_JJ -> panel, D_JJ -> D;
+//   2. the rows below: P = A[J+jb:w, J:J+jb] D_JJ^T -> panel and LDS (Pb);
+//      block row J of D: D_J[:, 0:J] = D_JJ X_J[:, 0:J], in place;
+//   3. trailing updates, 64x32 tiles dealt to the four waves:
+//      A[J+jb:, J+jb:] -= P P^T (lower triangle) and
+//      X[J+jb:, 0:J+jb] -= P D_J (columns J .. J+jb written for the first time).
+// Products run on the matrix cores; P and D_JJ are read from LDS.
+template <class T>
+__device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T* Dt, T* Pb)
+{
+    typedef typename MM<T>::acc acc_t;
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k];
     const int w = pl.lcol[k] - f + 1;
     const int64_t ld = pl.stride[k];
-    double* A = a.panels + pl.panel_off[k];
-    double* D = a.dinv + pl.dinv_off[k];
+    T* A = static_cast<T*>(a.panels) + pl.panel_off[k];
+    T* D = static_cast<T*>(a.dinv) + pl.dinv_off[k];
     const int64_t nA = ld * w, nD = (int64_t)w * w;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nt = (w + kNB - 1) / kNB;
+    const GOp gA = make_gop(A, nA, 0, 1, ld);   // A(i, p) at i + p*ld
+    const GOp gD = make_gop(D, nD, 0, 1, w);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    double* bc = Lt + kNB * 33;
     for (int J = 0; J < w; J += kNB) {
         const int jb = min(kNB, w - J);
-        if (J > 0) {
-            const int m = w - J, r0 = 64 * wave;
-            if (r0 < m) {
-                d4 acc[2][4];
-                zero_acc(acc);
-                wave_gemm<2>(acc, make_gop(A, nA, J + r0, 1, ld), make_gop(A, nA, J, 1, ld), J);
-                wave_store(acc, min(64, m - r0), jb, [&](int r, int c, double v) {
-                    if (r0 + r >= c) A[(J + r0 + r) + (int64_t)(J + c) * ld] -= v;
-                });
-            }
-            __syncthreads();
-        }
+        const int R = w - J - jb;   // rows below the tile inside the block
+        // 1. tile (identity padded) -> Lt; factor and invert
         for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
             const int r = idx & 31, c = idx >> 5;
-            Ls[r + c * 33] = (r < jb && c < jb) ? (c <= r ? A[(J + r) + (int64_t)(J + c) * ld] : 0.0)
+            Lt[r + c * 33] = (r < jb && c < jb) ? (c <= r ? (double)A[(J + r) + (int64_t)(J + c) * ld] : 0.0)
                                                 : (r == c ? 1.0 : 0.0);
         }
         __syncthreads();
-        if (wave == 0) {
-            tile_potrf(Ls, jb, f + J, a.status);
-            tile_trtri(Ls, D + J + (int64_t)J * w, w, jb);
-        }
+        if (wave == 0) tile_chol_inv<T>(Lt, bc, Dt, jb, f + J, a.status);
         __syncthreads();
         for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
             const int r = idx & 31, c = idx >> 5;
-            if (r < jb && c <= r) A[(J + r) + (int64_t)(J + c) * ld] = Ls[r + c * 33];
+            if (r < jb && c <= r) {
+                A[(J + r) + (int64_t)(J + c) * ld] = (T)Lt[r + c * 33];
+                D[(J + r) + (int64_t)(J + c) * w] = Dt[r + c * 33];
+            }
+        }
+        // 2a. rows below: P = A_rows D_JJ^T (wave v: rows 64v ..)
+        const int r0 = 64 * wave;
+        if (r0 < R) {
+            acc_t acc[2][4];
+            zero_acc(acc);
+            const int gbase = gA.off + (J + jb + r0) * gA.si + J * gA.sk;
+            wave_mm<2, T>(acc, [&](int i, int p) { return gload<T>(gA, gbase + i * gA.si + p * gA.sk); },
+                          [&](int c, int p) { return Dt[c + p * 33]; }, jb);
+            wave_store<T>(acc, min(64, R - r0), jb, [&](int r, int c, T v) {
+                Pb[(r0 + r) + c * kPbLd] = v;
+                A[(J + jb + r0 + r) + (int64_t)(J + c) * ld] = v;
+            });
+        }
+        // 2b. block row J of D for columns < J (transposed: rows c of the
+        // product are columns of D), each wave a 64-column slice, in place
+        for (int c0 = 64 * wave; c0 < J; c0 += 64 * (kThreads / 64)) {
+            acc_t acc[2][4];
+            zero_acc(acc);
+            wave_mm<2, T>(acc,
+                          [&](int i, int p) { return gload<T>(gD, gD.off + (J + p) * gD.si + (c0 + i) * gD.sk); },
+                          [&](int c, int p) { return Dt[c + p * 33]; }, jb);
+            wave_store<T>(acc, min(64, J - c0), jb,
+                          [&](int r, int c, T v) { D[(J + c) + (int64_t)(c0 + r) * w] = v; });
         }
         __syncthreads();
-        // rows below the tile: B <- B * D_JJ^T  (in place, each wave owns its rows)
-        const int m2 = w - J - jb, r0 = 64 * wave;
-        if (r0 < m2) {
-            d4 acc[2][4];
+        if (R == 0) break;
+        // 3. trailing updates: syrk tiles (rt, ct) with ct*32 < rt*64 + 64,
+        // then inverse tiles (rt, ct), ct*32 < J + jb
+        const int nrt = (R + 63) >> 6, ncs = (R + 31) >> 5, nci = (J + jb + 31) >> 5;
+        int nsyrk = 0;
+        for (int rt = 0; rt < nrt; ++rt) nsyrk += min(ncs, 2 * rt + 2);
+        const int ntiles = nsyrk + nrt * nci;
+        for (int t = wave; t < ntiles; t += kThreads / 64) {
+            int rt = 0, ct = t;
+            const bool syrk = t < nsyrk;
+            if (syrk) {
+                while (ct >= min(ncs, 2 * rt + 2)) { ct -= min(ncs, 2 * rt + 2); ++rt; }
+            } else {
+                rt = (t - nsyrk) / nci;
+                ct = (t - nsyrk) - rt * nci;
+            }
+            const int i0 = 64 * rt, c0 = 32 * ct;
+            const int mv = min(64, R - i0);
+            acc_t acc[2][4];
             zero_acc(acc);
-            wave_gemm<2>(acc, make_gop(A, nA, (J + jb + r0) + (int64_t)J * ld, 1, ld),
-                         make_gop(D, nD, J + (int64_t)J * w, 1, w), jb);
-            double* B = A + (J + jb + r0) + (int64_t)J * ld;
-            wave_store(acc, min(64, m2 - r0), jb, [&](int r, int c, double v) { B[r + (int64_t)c * ld] = v; });
-        }
-        __syncthreads();
-    }
-    // inverse, block rows I = 1 .. nt-1 (D_II already stored); the ib x I0
-    // products are dealt to the waves in 32-column slices
-    for (int I = 1; I < nt; ++I) {
-        const int I0 = I * kNB, ib = min(kNB, w - I0);
-        // rows ib..31 of G stay zero (they meet the padded inner range below)
-        for (int idx = tid; idx < kNB * I0; idx += kThreads) {
-            const int rr = idx & 31, cc = idx >> 5;
-            if (rr >= ib) Gs[rr + cc * 33] = 0.0;
-        }
-        // G = L[I0:I0+ib, 0:I0] * D[0:I0, 0:I0]   (ib x I0) -> Gs (column-major, ld 33)
-        for (int c0 = 32 * wave; c0 < I0; c0 += 128) {
-            d4 acc[2][4];
-            zero_acc(acc);
-            wave_gemm<2>(acc, make_gop(A, nA, I0, 1, ld), make_gop(D, nD, (int64_t)c0 * w, w, 1), I0);
-            wave_store(acc, ib, min(32, I0 - c0), [&](int r, int c, double v) { Gs[r + (c0 + c) * 33] = v; });
-        }
-        __syncthreads();
-        // D[I0:I0+ib, 0:I0] = -D_II * G
-        for (int c0 = 32 * wave; c0 < I0; c0 += 128) {
-            d4 acc[2][4];
-            zero_acc(acc);
-            wave_gemm_lds<2>(acc, make_gop(D, nD, I0 + (int64_t)I0 * w, 1, w), nblk(ib), Gs + c0 * 33, 33, 1,
-                             min(32, I0 - c0), ib);
-            wave_store(acc, ib, min(32, I0 - c0),
-                       [&](int r, int c, double v) { D[(I0 + r) + (int64_t)(c0 + c) * w] = -v; });
+            auto ldx = [&](int i, int p) { return i < mv ? Pb[(i0 + i) + p * kPbLd] : T(0); };
+            if (syrk) {
+                const int nv = min(32, R - c0);
+                wave_mm<2, T>(acc, ldx, [&](int c, int p) { return c < nv ? Pb[(c0 + c) + p * kPbLd] : T(0); }, jb);
+                wave_rmw<T>(
+                    acc, mv, nv, [&](int r, int c) { return A + (J + jb + i0 + r) + (int64_t)(J + jb + c0 + c) * ld; },
+                    [&](int r, int c) { return i0 + r >= c0 + c; }, [](T o, T v) { return o - v; });
+            } else {
+                const int nv = min(32, J + jb - c0);
+                wave_mm<2, T>(acc, ldx,
+                              [&](int c, int p) { return gload<T>(gD, gD.off + (J + p) * gD.si + (c0 + c) * gD.sk); },
+                              jb);
+                if (c0 >= J)   // columns written for the first time
+                    wave_store<T>(acc, mv, nv,
+                                  [&](int r, int c, T v) { D[(J + jb + i0 + r) + (int64_t)(c0 + c) * w] = -v; });
+                else
+                    wave_rmw<T>(
+                        acc, mv, nv, [&](int r, int c) { return D + (J + jb + i0 + r) + (int64_t)(c0 + c) * w; },
+                        [](int, int) { return true; }, [](T o, T v) { return o - v; });
+            }
         }
         __syncthreads();
     }
@@ -351,22 +453,24 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Ls, do
 // are replaced by B L_kk^{-T} = B D^T.  Wave v computes the 64 output columns
 // starting at 64v; the inner range stops at the diagonal of the lower
 // triangular D.
+template <class T>
 __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int nrows)
 {
     const DevPlan& pl = a.pl;
     const int w = pl.lcol[k] - pl.fcol[k] + 1;
     const int64_t ld = pl.stride[k];
-    double* P = a.panels + pl.panel_off[k];
-    double* B = P + row0;
-    const double* D = a.dinv + pl.dinv_off[k];
+    T* P = static_cast<T*>(a.panels) + pl.panel_off[k];
+    T* B = P + row0;
+    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
     const int wave = threadIdx.x >> 6;
-    d4 acc[4][4];
+    typename MM<T>::acc acc[4][4];
     zero_acc(acc);
     const int c0 = 64 * wave;
     const int nv = min(64, w - c0);
-    if (nv > 0) wave_gemm<4>(acc, make_gop(P, ld * w, row0, 1, ld), make_gop(D, (int64_t)w * w, c0, 1, w), min(w, c0 + 64));
+    if (nv > 0)
+        wave_gemm<4, T>(acc, make_gop(P, ld * w, row0, 1, ld), make_gop(D, (int64_t)w * w, c0, 1, w), min(w, c0 + 64));
     __syncthreads();   // every wave has read all of B before any result is written
-    if (nv > 0) wave_store(acc, nrows, nv, [&](int r, int c, double v) { B[r + (int64_t)(c0 + c) * ld] = v; });
+    if (nv > 0) wave_store<T>(acc, nrows, nv, [&](int r, int c, T v) { B[r + (int64_t)(c0 + c) * ld] = v; });
 }
 
 // ---------------------------------------------------------------- UPDATE
@@ -376,6 +480,7 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // of k from the first block facing j on, its row inside panel j; for facing
 // rows that is also the column of j.  ncols <= 64, mrows <= 256: the four
 // waves cover 64 rows each.
+template <class T>
 __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos, int* cpos)
 {
     const DevPlan& pl = a.pl;
@@ -383,8 +488,8 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
     const int mrows = d1.x, col0 = d1.y, ncols = d1.z, mbase = d1.w;
     const int w = pl.lcol[k] - pl.fcol[k] + 1;
     const int64_t ld = pl.stride[k], ldj = pl.stride[j];
-    const double* A = a.panels + pl.panel_off[k];
-    double* C = a.panels + pl.panel_off[j];
+    const T* A = static_cast<const T*>(a.panels) + pl.panel_off[k];
+    T* C = static_cast<T*>(a.panels) + pl.panel_off[j];
     const int tid = threadIdx.x, wave = tid >> 6;
     if (tid < mrows) rpos[tid] = a.rmap[mbase + row0 + tid];
     if (tid < ncols) cpos[tid] = a.rmap[mbase + col0 + tid];
@@ -392,10 +497,10 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
     const int r0 = 64 * wave;
     const int mv = min(64, mrows - r0);
     if (mv > 0) {
-        d4 acc[4][4];
+        typename MM<T>::acc acc[4][4];
         zero_acc(acc);
-        wave_gemm<4>(acc, make_gop(A, ld * w, row0 + r0, 1, ld), make_gop(A, ld * w, col0, 1, ld), w);
-        wave_store(acc, mv, ncols, [&](int r, int c, double v) {
+        wave_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0, 1, ld), make_gop(A, ld * w, col0, 1, ld), w);
+        wave_store<T>(acc, mv, ncols, [&](int r, int c, T v) {
             const int tr = rpos[r0 + r], tc = cpos[c];
             if (tr >= tc) unsafeAtomicAdd(C + (int64_t)tc * ldj + tr, -v);
         });
@@ -432,10 +537,12 @@ __device__ __forceinline__ void push_items(const SchedArgs& a, bool hp, int base
 }
 
 // ---------------------------------------------------------------- scheduler
+template <class T>
 __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 {
-    __shared__ double Ls[kNB * 33 + kNB];
-    __shared__ double Gs[kNB * 33 * 7];
+    __shared__ double Lt[kNB * 33 + 2 * kNB];
+    __shared__ T Dt[kNB * 33];
+    __shared__ T Pb[kPbLd * kNB];
     __shared__ int rpos[256], cpos[128];
     __shared__ int s_item;
     __shared__ int s_push[6];   // {hp first, hp count, hp base, normal first, normal count, normal base}
@@ -476,9 +583,9 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         __syncthreads();
         const int4 d0 = a.desc[2 * item];
         const int4 d1 = a.desc[2 * item + 1];
-        if (d0.x == kFact) task_fact(a, d0.y, Ls, Gs);
-        else if (d0.x == kTrsm) task_trsm(a, d0.y, d0.z, d0.w);
-        else task_update(a, d0, d1, rpos, cpos);
+        if (d0.x == kFact) task_fact<T>(a, d0.y, Lt, Dt, Pb);
+        else if (d0.x == kTrsm) task_trsm<T>(a, d0.y, d0.z, d0.w);
+        else task_update<T>(a, d0, d1, rpos, cpos);
         // every wave's stores and atomics have completed before the barrier
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -529,7 +636,8 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 }
 
 // ---------------------------------------------------------------- set-up kernels
-__global__ void fill_f64(double* p, int64_t n, double v)
+template <class T>
+__global__ void fill_kernel(T* p, int64_t n, T v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -539,12 +647,14 @@ __global__ void fill_i32(int32_t* p, int64_t n, int32_t v)
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// panels[amap[p]] = values[p] for entries read by the factorization
-__global__ void assemble_kernel(double* panels, const int64_t* amap, const double* values, int64_t nnz)
+// panels[amap[p]] = values[p] (rounded to the panel type) for entries read
+// by the factorization
+template <class T>
+__global__ void assemble_kernel(T* panels, const int64_t* amap, const double* values, int64_t nnz)
 {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = amap[p];
-        if (d >= 0) panels[d] = values[p];
+        if (d >= 0) panels[d] = (T)values[p];
     }
 }
 
@@ -579,7 +689,15 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
-    fill_f64<<<blocks, 256, 0, s>>>(p, n, v);
+    fill_kernel<double><<<blocks, 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    fill_kernel<float><<<blocks, 256, 0, s>>>(p, n, v);
     return hipGetLastError();
 }
 
@@ -591,11 +709,28 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(double* panels, const int64_t* amap, const double* values, int64_t nnz, hipStream_t s)
+hipError_t launch_assemble(void* panels, bool f32, const int64_t* amap, const double* values, int64_t nnz,
+                           hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
     const int blocks = (int)std::min<int64_t>((nnz + 255) / 256, 8192);
-    assemble_kernel<<<blocks, 256, 0, s>>>(panels, amap, values, nnz);
+    if (f32) assemble_kernel<float><<<blocks, 256, 0, s>>>(static_cast<float*>(panels), amap, values, nnz);
+    else assemble_kernel<double><<<blocks, 256, 0, s>>>(static_cast<double*>(panels), amap, values, nnz);
+    return hipGetLastError();
+}
+
+// FP32 panels widened to FP64 (export of the refinement-mode factor)
+__global__ void widen_kernel(double* dst, const float* src, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
+hipError_t launch_widen(double* dst, const float* src, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    widen_kernel<<<blocks, 256, 0, s>>>(dst, src, n);
     return hipGetLastError();
 }
 
@@ -608,16 +743,19 @@ hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t n
     return hipGetLastError();
 }
 
-int sched_blocks_per_cu()
+int sched_blocks_per_cu(bool f32)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel, kThreads, 0) != hipSuccess) return 1;
+    const hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<float>, kThreads, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double>, kThreads, 0);
+    if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_sched(const SchedArgs& a, int grid, hipStream_t s)
+hipError_t launch_sched(const SchedArgs& a, bool f32, int grid, hipStream_t s)
 {
-    sched_kernel<<<grid, kThreads, 0, s>>>(a);
+    if (f32) sched_kernel<float><<<grid, kThreads, 0, s>>>(a);
+    else sched_kernel<double><<<grid, kThreads, 0, s>>>(a);
     return hipGetLastError();
 }
 

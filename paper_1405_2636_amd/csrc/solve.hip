@@ -10,6 +10,8 @@
 //   x_k <- L_kk^{-T} (y_k - t_k)
 // Both use the inverse of each diagonal block kept by the factorization.
 // The sweeps stream the panels once each: they are bound by HBM bandwidth.
+// The factor is read in its storage type T (double, or float in the FP32
+// refinement mode); vectors and arithmetic are FP64 in both cases.
 #include "device.hpp"
 
 namespace spx {
@@ -19,30 +21,29 @@ constexpr int kChunk = 256;   // off-diagonal rows per workgroup
 // ---- forward, diagonal block: y_k <- D y_k with D = L_kk^{-1} (lower, w x w,
 // column-major, kept by the factorization).  Thread r owns row r; the loads
 // D[r + p*w] of one p are contiguous over the threads.
+template <class T>
 __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblks)
 {
     __shared__ double ys[256];
     const int k = cblks[blockIdx.x];
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
-    const double* D = a.dinv + pl.dinv_off[k];
+    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
     const int tid = threadIdx.x;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
         double* y = a.y + (int64_t)rhs * a.n + f;
         if (tid < w) ys[tid] = y[tid];
         __syncthreads();
         if (tid < w) {
-            const double* row = D + tid;
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+            const T* row = D + tid;
+            double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             int p = 0;
-            for (; p + 4 <= tid + 1; p += 4) {
-                v0 += row[(int64_t)p * w] * ys[p];
-                v1 += row[(int64_t)(p + 1) * w] * ys[p + 1];
-                v2 += row[(int64_t)(p + 2) * w] * ys[p + 2];
-                v3 += row[(int64_t)(p + 3) * w] * ys[p + 3];
+            for (; p + 8 <= tid + 1; p += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] += row[(int64_t)(p + u) * w] * ys[p + u];
             }
-            for (; p <= tid; ++p) v0 += row[(int64_t)p * w] * ys[p];
-            y[tid] = (v0 + v1) + (v2 + v3);
+            for (; p <= tid; ++p) v[0] += row[(int64_t)p * w] * ys[p];
+            y[tid] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
         }
         __syncthreads();
     }
@@ -50,6 +51,7 @@ __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblk
 
 // ---- forward, off-diagonal rows: y[g(r)] -= sum_c L[r, c] y_k[c]; thread per
 // row, loads contiguous over the threads
+template <class T>
 __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
 {
     __shared__ double yk[256];
@@ -59,7 +61,7 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
     const int64_t ld = pl.stride[k];
     const int nr = min(kChunk, (int)ld - row0);
-    const double* L = a.panels + pl.panel_off[k] + row0;
+    const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0;
     const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
     const int tid = threadIdx.x;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
@@ -67,17 +69,15 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
         if (tid < w) yk[tid] = y[f + tid];
         __syncthreads();
         if (tid < nr) {
-            const double* row = L + tid;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            const T* row = L + tid;
+            double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             int c = 0;
-            for (; c + 4 <= w; c += 4) {
-                s0 += row[c * ld] * yk[c];
-                s1 += row[(c + 1) * ld] * yk[c + 1];
-                s2 += row[(c + 2) * ld] * yk[c + 2];
-                s3 += row[(c + 3) * ld] * yk[c + 3];
+            for (; c + 8 <= w; c += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] += row[(c + u) * ld] * yk[c + u];
             }
-            for (; c < w; ++c) s0 += row[c * ld] * yk[c];
-            unsafeAtomicAdd(y + g[tid], -((s0 + s1) + (s2 + s3)));
+            for (; c < w; ++c) v[0] += row[c * ld] * yk[c];
+            unsafeAtomicAdd(y + g[tid], -(((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))));
         }
         __syncthreads();
     }
@@ -85,6 +85,7 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
 
 // ---- backward, off-diagonal rows: tacc[f + c] += sum_r L[r, c] x[g(r)];
 // thread per column, each streaming down its own column of the chunk
+template <class T>
 __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
 {
     __shared__ double xr[kChunk];
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
     const int64_t ld = pl.stride[k];
     const int nr = min(kChunk, (int)ld - row0);
-    const double* L = a.panels + pl.panel_off[k] + row0;
+    const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0;
     const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
     const int tid = threadIdx.x;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
@@ -102,17 +103,16 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
         if (tid < nr) xr[tid] = x[g[tid]];
         __syncthreads();
         if (tid < w) {
-            const double* col = L + (int64_t)tid * ld;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            const T* col = L + (int64_t)tid * ld;
+            double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             int r = 0;
-            for (; r + 4 <= nr; r += 4) {
-                s0 += col[r] * xr[r];
-                s1 += col[r + 1] * xr[r + 1];
-                s2 += col[r + 2] * xr[r + 2];
-                s3 += col[r + 3] * xr[r + 3];
+            for (; r + 8 <= nr; r += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] += col[r + u] * xr[r + u];
             }
-            for (; r < nr; ++r) s0 += col[r] * xr[r];
-            unsafeAtomicAdd(a.tacc + (int64_t)rhs * a.n + f + tid, (s0 + s1) + (s2 + s3));
+            for (; r < nr; ++r) v[0] += col[r] * xr[r];
+            unsafeAtomicAdd(a.tacc + (int64_t)rhs * a.n + f + tid,
+                            ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])));
         }
         __syncthreads();
     }
@@ -120,13 +120,14 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
 
 // ---- backward, diagonal block: x_k <- D^T (y_k - t_k); thread c streams
 // down column c of D
+template <class T>
 __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblks)
 {
     __shared__ double zs[256];
     const int k = cblks[blockIdx.x];
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
-    const double* D = a.dinv + pl.dinv_off[k];
+    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
     const int tid = threadIdx.x;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
         double* y = a.y + (int64_t)rhs * a.n + f;
@@ -134,17 +135,15 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblk
         if (tid < w) zs[tid] = y[tid] - t[tid];
         __syncthreads();
         if (tid < w) {
-            const double* col = D + (int64_t)tid * w;
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+            const T* col = D + (int64_t)tid * w;
+            double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             int p = tid;
-            for (; p + 4 <= w; p += 4) {
-                v0 += col[p] * zs[p];
-                v1 += col[p + 1] * zs[p + 1];
-                v2 += col[p + 2] * zs[p + 2];
-                v3 += col[p + 3] * zs[p + 3];
+            for (; p + 8 <= w; p += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] += col[p + u] * zs[p + u];
             }
-            for (; p < w; ++p) v0 += col[p] * zs[p];
-            y[tid] = (v0 + v1) + (v2 + v3);
+            for (; p < w; ++p) v[0] += col[p] * zs[p];
+            y[tid] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
         }
         __syncthreads();
     }
@@ -167,6 +166,11 @@ __global__ void permute_out(double* x, int64_t ldx, const double* y, const int32
         const int64_t c = t / n, i = t - c * n;
         x[c * ldx + perm[i]] = y[t];
     }
+}
+
+__global__ void zero_u64(unsigned long long* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 __global__ void axpy_kernel(double* x, const double* d, int64_t n)
@@ -252,22 +256,30 @@ static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64
 
 hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s)
 {
-    if (count > 0) fwd_diag<<<count, 256, 0, s>>>(a, cblks);
+    if (count <= 0) return hipSuccess;
+    if (a.f32) fwd_diag<float><<<count, 256, 0, s>>>(a, cblks);
+    else fwd_diag<double><<<count, 256, 0, s>>>(a, cblks);
     return hipGetLastError();
 }
 hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s)
 {
-    if (count > 0) fwd_off<<<count, 256, 0, s>>>(a, chunks);
+    if (count <= 0) return hipSuccess;
+    if (a.f32) fwd_off<float><<<count, 256, 0, s>>>(a, chunks);
+    else fwd_off<double><<<count, 256, 0, s>>>(a, chunks);
     return hipGetLastError();
 }
 hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s)
 {
-    if (count > 0) bwd_off<<<count, 256, 0, s>>>(a, chunks);
+    if (count <= 0) return hipSuccess;
+    if (a.f32) bwd_off<float><<<count, 256, 0, s>>>(a, chunks);
+    else bwd_off<double><<<count, 256, 0, s>>>(a, chunks);
     return hipGetLastError();
 }
 hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s)
 {
-    if (count > 0) bwd_diag<<<count, 256, 0, s>>>(a, cblks);
+    if (count <= 0) return hipSuccess;
+    if (a.f32) bwd_diag<float><<<count, 256, 0, s>>>(a, cblks);
+    else bwd_diag<double><<<count, 256, 0, s>>>(a, cblks);
     return hipGetLastError();
 }
 hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,
@@ -282,6 +294,12 @@ hipError_t launch_permute_out(double* x, int64_t ldx, const double* y, const int
     permute_out<<<grid_for((int64_t)n * nrhs), 256, 0, s>>>(x, ldx, y, perm, n, nrhs);
     return hipGetLastError();
 }
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s)
+{
+    zero_u64<<<1, 64, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s)
 {
     axpy_kernel<<<grid_for(n), 256, 0, s>>>(x, d, n);

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspx.so")
 
 SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ESTATE, SPX_ENOTPD, SPX_ENOCONV = 0, -1, -2, -3, -4, -5, -6
+PRECISIONS = {"fp64": 0, "fp32_ir": 1}   # enum spx_precision
 
 
 class SpxError(RuntimeError):
@@ -124,10 +125,13 @@ class Solver:
 
     colptr/rowind: CSC pattern (host arrays, full symmetric pattern or its lower
     triangle).  values passed to factorize are aligned with the pattern.
+    precision: "fp64" (FP64 factor) or "fp32_ir" (FP32 factor, FP64 residual
+    and refinement).  ir_max_iter None: the library's default for the
+    precision (2 for fp64, 10 for fp32_ir).
     """
 
     def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,
-                 ir_max_iter=2, ir_tol=1e-14, trace=False):
+                 precision="fp64", ir_max_iter=None, ir_tol=1e-14, trace=False):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -137,7 +141,12 @@ class Solver:
         opt = Options()
         L.spx_default_options(C.byref(opt))
         opt.leaf_size, opt.amalg_pct, opt.split_width = leaf_size, amalg_pct, split_width
-        opt.ir_max_iter, opt.ir_tol = ir_max_iter, ir_tol
+        if precision not in PRECISIONS:
+            raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
+        self.precision = precision
+        opt.precision = PRECISIONS[precision]
+        opt.ir_max_iter = -1 if ir_max_iter is None else int(ir_max_iter)
+        opt.ir_tol = ir_tol
         opt.trace = 1 if trace else 0
         up = None
         if user_perm is not None:

@@ -183,3 +183,96 @@ def test_solve_before_factorize(torch):
     with pytest.raises(SpxError) as ei:
         s.solve(torch.zeros(p.n, dtype=torch.float64, device="cuda"))
     assert ei.value.code == -4
+
+
+# ---------------------------------------------------------------- FP32 factor + FP64 refinement
+# The FP32 factor is checked against the backward-error bound of Cholesky
+# in precision u = 2^-24: ||P A P^T - L L^T||_F <= gamma_{m+1} || |L| |L|^T ||_F
+# with m the largest column count and gamma_k = k u / (1 - k u) (the rounding
+# of A to FP32 adds u |A|, inside the same bound for m >= 1).  The refined
+# solution must reach the FP64 backward-error target and agree with the
+# oracle's FP64 solution to within kappa * omega.
+
+U32 = 2.0 ** -24
+
+
+def _fp32_bound(orc, sym, F, p):
+    ri, ci, v = orc.unpack(sym, F)
+    L = sp.csc_matrix((v, (ri, ci)), shape=(p.n, p.n))
+    m = int(np.max(np.diff(L.indptr)))
+    g = (m + 1) * U32 / (1 - (m + 1) * U32)
+    absL = abs(L)
+    return g * sp.linalg.norm(absL @ absL.T)
+
+
+def _check_fp32(orc, torch, p, nrhs=1, **kw):
+    print("fp32 case n=%d nnz=%d opts=%s" % (p.n, p.nnz, kw), flush=True)
+    s, F = _gpu_factor(torch, p, precision="fp32_ir", **kw)
+    sym, P = _oracle(orc, p, **kw)
+    ri, ci, v = orc.unpack(sym, F)
+    L = sp.csc_matrix((v, (ri, ci)), shape=(p.n, p.n))
+    A = sp.csc_matrix((p.values, p.rowind, p.colptr), shape=(p.n, p.n))
+    PA = A[sym.perm][:, sym.perm]
+    # the stored factor is FP32: every entry is exactly a float
+    assert np.array_equal(F, F.astype(np.float32).astype(np.float64))
+    assert sp.linalg.norm(PA - L @ L.T) <= _fp32_bound(orc, sym, F, p)
+    B = rhs(p.n, nrhs, 77)
+    b = torch.tensor(np.ascontiguousarray(B.T), device="cuda")
+    if nrhs == 1:
+        b = b[0].contiguous()
+    x, info = s.solve(b.clone())
+    assert info["converged"] and info["omega"] <= 1e-14 and info["ir_iters"] <= 10
+    xo = orc.solve(sym, P, B)
+    xg = x.cpu().numpy().reshape(nrhs, p.n).T
+    assert np.max(np.abs(xg - xo)) <= 1e-10 * np.max(np.abs(xo))
+    return s, info
+
+
+def test_fp32_ir_config1(orc, torch):
+    s, info = _check_fp32(orc, torch, make_config(1))
+    assert info["ir_iters"] >= 1   # an FP32 factor alone does not reach 1e-14
+
+
+@pytest.mark.parametrize("case", ["rand", "dense", "grid3", "split"])
+def test_fp32_ir_parity(orc, torch, case):
+    if case == "rand":
+        _check_fp32(orc, torch, random_spd(1500, 0.003, 7), nrhs=3, amalg_pct=40, split_width=64)
+    elif case == "dense":
+        rng = np.random.default_rng(5)
+        n = 600
+        M = rng.uniform(-1, 1, (n, n))
+        Ac = sp.csc_matrix(M @ M.T / n + np.eye(n))
+        from gen.stencils import Problem
+        _check_fp32(orc, torch, Problem(n, Ac.indptr.astype(np.int64), Ac.indices.astype(np.int32), Ac.data.copy()))
+    elif case == "grid3":
+        _check_fp32(orc, torch, grid_laplacian((20, 20, 20), shift=1e-3), nrhs=2)
+    else:
+        _check_fp32(orc, torch, random_spd(400, 0.01, 4), split_width=7, leaf_size=16)
+
+
+def test_fp32_ir_not_positive_definite(orc, torch):
+    p = grid_laplacian((40, 35))
+    vals = p.values.copy()
+    cols = np.repeat(np.arange(p.n), np.diff(p.colptr))
+    victim = 777
+    vals[(p.rowind == victim) & (cols == victim)] = -1.0
+    from paper_1405_2636_amd import NotPositiveDefinite, Solver
+    sym = orc.analyze(p.n, p.colptr, p.rowind)
+    with pytest.raises(orc.NotPositiveDefinite) as eo:
+        orc.factor(sym, p.colptr, p.rowind, vals)
+    s = Solver(p.n, p.colptr, p.rowind, precision="fp32_ir")
+    with pytest.raises(NotPositiveDefinite) as eg:
+        s.factorize(torch.tensor(vals, device="cuda"))
+    assert eg.value.col == eo.value.col_orig
+
+
+def test_fp32_ir_logdet(orc, torch):
+    # closed-form log det of the 64x64 5-point Laplacian; each log l_jj of the
+    # FP32 factor is off by at most about (m+1) u, so the sum by n (m+1) u
+    p = make_config(1)
+    s, F = _gpu_factor(torch, p, precision="fp32_ir")
+    ev = 2.0 - 2.0 * np.cos(np.arange(1, 65) * np.pi / 65)
+    ref = float(np.sum(np.log(np.add.outer(ev, ev))))
+    sym = orc.analyze(p.n, p.colptr, p.rowind)
+    m = int(np.max(sym.colcount))
+    assert abs(s.info()["logdet"] - ref) <= 2 * p.n * (m + 1) * U32
