@@ -111,6 +111,29 @@ __device__ __forceinline__ float gload<float>(const GOp& g, int voff)
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(g.rs, voff, 0, 0));
 }
 
+// Byte offset of a masked-off buffer load: past the end of any array here,
+// so the load returns zero (the value is discarded by a select anyway).
+constexpr int kOffNone = 0x7f000000;
+
+// Element at byte offset voff (per lane) + soff (wave-uniform) of g's array;
+// stores outside the array are dropped.
+__device__ __forceinline__ double gload_s(const GOp& g, int voff, int soff, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(g.rs, voff, soff, 0));
+}
+__device__ __forceinline__ float gload_s(const GOp& g, int voff, int soff, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(g.rs, voff, soff, 0));
+}
+__device__ __forceinline__ void gstore_s(const GOp& g, int voff, int soff, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), g.rs, voff, soff, 0);
+}
+__device__ __forceinline__ void gstore_s(const GOp& g, int voff, int soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), g.rs, voff, soff, 0);
+}
+
 // One wave accumulates a 64 x (16*NB) tile: acc += X Y^T, X(r, p) r < 64,
 // Y(c, p) c < 16*NB, p < K (K rounded up to 8 reads zeros or is exact).  The
 // whole tile is always computed (no per-block predicates); rows and columns
@@ -225,17 +248,18 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
         const double l = Lt[r + c * 33];
         v[c] = upper ? (c == r ? 1.0 : 0.0) : l;
     }
-    // pivot of column c: s = sqrt(l_cc), inv = 1/s by the hardware reciprocal
-    // and two Newton-Raphson steps (the IEEE division expansion spills
-    // registers in this unrolled loop)
+    // pivot of column c: inv = 1/sqrt(l_cc) from the hardware estimate and
+    // two Newton-Raphson steps y <- y (3 - d y^2) / 2, s = d inv (a short
+    // dependency chain; within a few ulps of the rounded values)
     int fail = 32;
     auto pivot = [&](int c, double& s, double& inv) {
         const double d = readlane_d(v[c], c);
         fail = (c < jb && !(d > 0.0) && fail == 32) ? c : fail;
-        s = sqrt(d);
-        inv = __builtin_amdgcn_rcp(s);
-        inv = __builtin_fma(inv, __builtin_fma(-s, inv, 1.0), inv);
-        inv = __builtin_fma(inv, __builtin_fma(-s, inv, 1.0), inv);
+        double y = __builtin_amdgcn_rsq(d);
+        y = y * __builtin_fma(-0.5 * d, y * y, 1.5);
+        y = y * __builtin_fma(-0.5 * d, y * y, 1.5);
+        inv = y;
+        s = d * y;
     };
     double s, inv;
     pivot(0, s, inv);
@@ -272,42 +296,47 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
 }
 
 // Small product of the diagonal-block factorization: acc += X Y^T with
-// X(i, p), i < 64, and Y(c, p), c < 16*NB, given by loader functions;
-// p < K <= 32 (masked).  Fully unrolled, so that every operand load is
-// issued before the first product.
+// X(i, p), i < 64, and Y(c, p), c < 16*NB, p < 32, given by loader functions
+// that load unconditionally (no masks: callers arrange that entries outside
+// the operands are zeros or only reach results that are not stored).  Fully
+// unrolled in two halves of 16: the operand loads of a half are issued
+// before its products.
 template <int NB, class T, class LX, class LY>
-__device__ __forceinline__ void wave_mm(typename MM<T>::acc (&acc)[NB][4], LX ldx, LY ldy, int K)
+__device__ __forceinline__ void wave_mm(typename MM<T>::acc (&acc)[NB][4], LX ldx, LY ldy)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    T xs[8][4], ys[8][NB];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int p = 4 * q + lk;
-        const bool ok = p < K;
+    for (int h = 0; h < 2; ++h) {
+        T xs[4][4], ys[4][NB];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) xs[q][b] = ok ? ldx(16 * b + li, p) : T(0);
+        for (int q = 0; q < 4; ++q) {
+            const int p = 16 * h + 4 * q + lk;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) ys[q][b] = ok ? ldy(16 * b + li, p) : T(0);
+            for (int b = 0; b < 4; ++b) xs[q][b] = ldx(16 * b + li, p);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) ys[q][b] = ldy(16 * b + li, p);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MM<T>::mfma(ys[q][bi], xs[q][bj], acc[bi][bj]);
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MM<T>::mfma(ys[q][bi], xs[q][bj], acc[bi][bj]);
 }
 
-// acc -> C with C(r, c) = f(old C(r, c), value) at ptr(r, c) for the entries
-// with r < mv, c < nv and keep(r, c): every old value is loaded before the
-// first store (the stores could otherwise alias later loads and serialize
-// them).
-template <class T, int NB, class Ptr, class Keep, class F>
-__device__ __forceinline__ void wave_rmw(const typename MM<T>::acc (&acc)[NB][4], int mv, int nv, Ptr ptr, Keep keep,
-                                         F f)
+// C(r, c) = f(old C(r, c), (X Y^T)(r, c)) for r < mv, c < nv, keep(r, c),
+// with C(r, c) at byte offset C.off + r*C.si + c*C.sk of C's array.  The old
+// values are requested first, so that their latency overlaps the products;
+// each offset is a per-lane part plus a wave-uniform part (scalar offset).
+template <int NB, class T, class LX, class LY, class Keep, class F>
+__device__ __forceinline__ void wave_mm_rmw(LX ldx, LY ldy, int mv, int nv, const GOp& C, Keep keep, F f)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
+    // drow(v, lk) = MM<T>::drow(0, lk) + MM<T>::drow(v, 0)
+    const int vl = C.off + li * C.si + MM<T>::drow(0, lk) * C.sk;
     T old[NB][4][4];
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi)
@@ -316,8 +345,14 @@ __device__ __forceinline__ void wave_rmw(const typename MM<T>::acc (&acc)[NB][4]
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = 16 * bj + li, c = 16 * bi + MM<T>::drow(v, lk);
-                old[bi][bj][v] = (r < mv && c < nv && keep(r, c)) ? *ptr(r, c) : T(0);
+                const int so = uni(16 * bj * C.si + (16 * bi + MM<T>::drow(v, 0)) * C.sk);
+                const bool in = r < mv && c < nv && keep(r, c);
+                const T o = gload_s(C, in ? vl : kOffNone, so, T(0));
+                old[bi][bj][v] = in ? o : T(0);
             }
+    typename MM<T>::acc acc[NB][4];
+    zero_acc(acc);
+    wave_mm<NB, T>(acc, ldx, ldy);
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
@@ -325,7 +360,8 @@ __device__ __forceinline__ void wave_rmw(const typename MM<T>::acc (&acc)[NB][4]
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = 16 * bj + li, c = 16 * bi + MM<T>::drow(v, lk);
-                if (r < mv && c < nv && keep(r, c)) *ptr(r, c) = f(old[bi][bj][v], acc[bi][bj][v]);
+                const int so = uni(16 * bj * C.si + (16 * bi + MM<T>::drow(v, 0)) * C.sk);
+                if (r < mv && c < nv && keep(r, c)) gstore_s(C, vl, so, f(old[bi][bj][v], acc[bi][bj][v]));
             }
 }
 
@@ -384,8 +420,9 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
             acc_t acc[2][4];
             zero_acc(acc);
             const int gbase = gA.off + (J + jb + r0) * gA.si + J * gA.sk;
+            // (R > 0 implies jb = 32: full inner range)
             wave_mm<2, T>(acc, [&](int i, int p) { return gload<T>(gA, gbase + i * gA.si + p * gA.sk); },
-                          [&](int c, int p) { return Dt[c + p * 33]; }, jb);
+                          [&](int c, int p) { return Dt[c + p * 33]; });
             wave_store<T>(acc, min(64, R - r0), jb, [&](int r, int c, T v) {
                 Pb[(r0 + r) + c * kPbLd] = v;
                 A[(J + jb + r0 + r) + (int64_t)(J + c) * ld] = v;
@@ -396,9 +433,11 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
         for (int c0 = 64 * wave; c0 < J; c0 += 64 * (kThreads / 64)) {
             acc_t acc[2][4];
             zero_acc(acc);
-            wave_mm<2, T>(acc,
-                          [&](int i, int p) { return gload<T>(gD, gD.off + (J + p) * gD.si + (c0 + i) * gD.sk); },
-                          [&](int c, int p) { return Dt[c + p * 33]; }, jb);
+            // with jb < 32 (last step) the inner indices p >= jb read entries
+            // of D below row w (finite: the top of the next column, or zero
+            // past the array) that meet D_JJ[r][p] = 0 for r < jb
+            wave_mm<2, T>(acc, [&](int i, int p) { return gload<T>(gD, gD.off + (J + p) * gD.si + (c0 + i) * gD.sk); },
+                          [&](int c, int p) { return Dt[c + p * 33]; });
             wave_store<T>(acc, min(64, J - c0), jb,
                           [&](int r, int c, T v) { D[(J + c) + (int64_t)(c0 + r) * w] = v; });
         }
@@ -421,27 +460,31 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
             }
             const int i0 = 64 * rt, c0 = 32 * ct;
             const int mv = min(64, R - i0);
-            acc_t acc[2][4];
-            zero_acc(acc);
-            auto ldx = [&](int i, int p) { return i < mv ? Pb[(i0 + i) + p * kPbLd] : T(0); };
+            // rows i >= mv (and columns c >= nv below) only reach results
+            // that are not stored; Pb is padded for their indices
+            auto ldx = [&](int i, int p) { return Pb[(i0 + i) + p * kPbLd]; };
+            auto sub = [](T o, T v) { return o - v; };
             if (syrk) {
                 const int nv = min(32, R - c0);
-                wave_mm<2, T>(acc, ldx, [&](int c, int p) { return c < nv ? Pb[(c0 + c) + p * kPbLd] : T(0); }, jb);
-                wave_rmw<T>(
-                    acc, mv, nv, [&](int r, int c) { return A + (J + jb + i0 + r) + (int64_t)(J + jb + c0 + c) * ld; },
-                    [&](int r, int c) { return i0 + r >= c0 + c; }, [](T o, T v) { return o - v; });
+                GOp cA = gA;
+                cA.off = uni(gA.off + (J + jb + i0) * gA.si + (J + jb + c0) * gA.sk);
+                wave_mm_rmw<2, T>(
+                    ldx, [&](int c, int p) { return Pb[(c0 + c) + p * kPbLd]; }, mv, nv, cA,
+                    [&](int r, int c) { return i0 + r >= c0 + c; }, sub);
             } else {
                 const int nv = min(32, J + jb - c0);
-                wave_mm<2, T>(acc, ldx,
-                              [&](int c, int p) { return gload<T>(gD, gD.off + (J + p) * gD.si + (c0 + c) * gD.sk); },
-                              jb);
-                if (c0 >= J)   // columns written for the first time
+                auto ldy = [&](int c, int p) { return gload<T>(gD, gD.off + (J + p) * gD.si + (c0 + c) * gD.sk); };
+                if (c0 >= J) {   // columns written for the first time
+                    acc_t acc[2][4];
+                    zero_acc(acc);
+                    wave_mm<2, T>(acc, ldx, ldy);
                     wave_store<T>(acc, mv, nv,
                                   [&](int r, int c, T v) { D[(J + jb + i0 + r) + (int64_t)(c0 + c) * w] = -v; });
-                else
-                    wave_rmw<T>(
-                        acc, mv, nv, [&](int r, int c) { return D + (J + jb + i0 + r) + (int64_t)(c0 + c) * w; },
-                        [](int, int) { return true; }, [](T o, T v) { return o - v; });
+                } else {
+                    GOp cD = gD;
+                    cD.off = uni(gD.off + (J + jb + i0) * gD.si + c0 * gD.sk);
+                    wave_mm_rmw<2, T>(ldx, ldy, mv, nv, cD, [](int, int) { return true; }, sub);
+                }
             }
         }
         __syncthreads();
@@ -542,7 +585,7 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 {
     __shared__ double Lt[kNB * 33 + 2 * kNB];
     __shared__ T Dt[kNB * 33];
-    __shared__ T Pb[kPbLd * kNB];
+    __shared__ T Pb[kPbLd * kNB + 32];   // + padding: tile row indices up to 255
     __shared__ int rpos[256], cpos[128];
     __shared__ int s_item;
     __shared__ int s_push[6];   // {hp first, hp count, hp base, normal first, normal count, normal base}
