@@ -71,6 +71,19 @@ def cpu_baseline(p, budget_flops: float = 1.0e10):
                       % (kend, len(lcol), fl, sym.stats["flops_alg"], dt)}
 
 
+def copy_probe():
+    """Three copies of 64 Mi doubles (512 MiB read + 512 MiB written each): the
+    reference dispatch that scales rocprofv3's FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied 3 x %d bytes" % (n * 8), flush=True)
+
+
 def run_leg(torch, np, Solver, p, vals, b0, precision, steps, warmup):
     """Warm-up, then `steps` timed passes of factorize + refined solve in one
     precision mode.  Times are HIP events on the torch stream the library is
@@ -121,7 +134,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run three plain device copies of 512 MiB (scale for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the build is single-GPU (see DESIGN.md on sharding)", file=sys.stderr)
         sys.exit(2)
