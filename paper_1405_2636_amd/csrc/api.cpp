@@ -30,10 +30,10 @@ hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t n
                              const int32_t* fact_dep0, int32_t ncblk, hipStream_t s);
 int sched_blocks_per_cu(bool f32);
 hipError_t launch_sched(const SchedArgs& a, bool f32, int grid, hipStream_t s);
-hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
+hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s);
 hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
 hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
-hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
+hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s);
 hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,
                              hipStream_t s);
 hipError_t launch_permute_out(double* x, int64_t ldx, const double* y, const int32_t* perm, int32_t n, int32_t nrhs,
@@ -94,6 +94,7 @@ struct DevBuf {
 struct Level {
     std::vector<int32_t> cptr;   // cblks of level l: cblk[cptr[l]..cptr[l+1])
     std::vector<int32_t> cblk;
+    std::vector<int32_t> maxw;   // widest cblk of level l
     std::vector<int32_t> kptr;   // chunks of level l
     std::vector<int2> chunk;
 };
@@ -136,7 +137,7 @@ struct spx_handle {
     double logdet = 0.0;
     double factor_ms = 0.0, assemble_ms = 0.0;
     // solve work (internal buffers, n x nrhs_cap) and the captured sweep graph
-    DevBuf<double> y, tacc, xw, rw, dw, bw;
+    DevBuf<double> y, zv, xv, tacc, xw, rw, dw, bw;
     DevBuf<unsigned long long> stats;
     int32_t nrhs_cap = 0;
     int32_t graph_nrhs = 0;
@@ -341,7 +342,7 @@ void build_tasks(spx_handle* h)
 }
 
 // Dependency levels for the sweeps: level(k) = 1 + max level of the cblks
-// updating k.  Off-diagonal rows are cut into chunks of 256 rows.
+// updating k.  Off-diagonal rows are cut into chunks of 64 rows.
 void build_levels(spx_handle* h)
 {
     const Plan& P = h->plan;
@@ -364,11 +365,13 @@ void build_levels(spx_handle* h)
     std::vector<int32_t> pos(L.cptr.begin(), L.cptr.end() - 1);
     for (int32_t k = 0; k < nc; ++k) L.cblk[pos[lvl[k]]++] = k;
     L.kptr.assign(nl + 1, 0);
+    L.maxw.assign(nl, 1);
     for (int32_t l = 0; l < nl; ++l) {
         for (int32_t q = L.cptr[l]; q < L.cptr[l + 1]; ++q) {
             const int32_t k = L.cblk[q];
             const int32_t w = P.lcol[k] - P.fcol[k] + 1;
-            for (int32_t r = w; r < P.stride[k]; r += 256) L.chunk.push_back(int2{k, r});
+            L.maxw[l] = std::max(L.maxw[l], w);
+            for (int32_t r = w; r < P.stride[k]; r += 64) L.chunk.push_back(int2{k, r});
         }
         L.kptr[l + 1] = static_cast<int32_t>(L.chunk.size());
     }
@@ -424,6 +427,8 @@ void upload_plan(spx_handle* h)
     h->timeout_ticks = static_cast<int64_t>(clk_khz) * 1000 * 20;   // 20 s per wait
 }
 
+// One application of (L L^T)^{-1} to the permuted vectors in y (consumed):
+// result in h->xv.
 void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
 {
     SweepArgs a;
@@ -434,19 +439,21 @@ void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
     a.rowg = h->rowg.p;
     a.rowg_off = h->rowg_off.p;
     a.y = y;
+    a.z = h->zv.p;
+    a.x = h->xv.p;
     a.tacc = h->tacc.p;
     a.n = h->n;
     a.nrhs = nrhs;
     const Level& L = h->lv;
     const int nl = static_cast<int>(L.cptr.size()) - 1;
     for (int l = 0; l < nl; ++l) {
-        HIPCHK(launch_fwd_diag(a, h->lv_cblk.p + L.cptr[l], L.cptr[l + 1] - L.cptr[l], s));
+        HIPCHK(launch_fwd_diag(a, h->lv_cblk.p + L.cptr[l], L.cptr[l + 1] - L.cptr[l], L.maxw[l], s));
         HIPCHK(launch_fwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
     }
     HIPCHK(launch_fill_f64(h->tacc.p, static_cast<int64_t>(h->n) * nrhs, 0.0, s));
     for (int l = nl - 1; l >= 0; --l) {
         HIPCHK(launch_bwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
-        HIPCHK(launch_bwd_diag(a, h->lv_cblk.p + L.cptr[l], L.cptr[l + 1] - L.cptr[l], s));
+        HIPCHK(launch_bwd_diag(a, h->lv_cblk.p + L.cptr[l], L.cptr[l + 1] - L.cptr[l], L.maxw[l], s));
     }
 }
 
@@ -625,8 +632,10 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
             // new buffers: a graph captured on the old ones is stale
             h->drop_graph();
             const size_t cap = static_cast<size_t>(n) * nrhs;
-            h->y.release(); h->tacc.release(); h->xw.release(); h->rw.release(); h->dw.release(); h->bw.release();
-            h->y.alloc(cap); h->tacc.alloc(cap); h->xw.alloc(cap); h->rw.alloc(cap); h->dw.alloc(cap); h->bw.alloc(cap);
+            for (DevBuf<double>* b : {&h->y, &h->zv, &h->xv, &h->tacc, &h->xw, &h->rw, &h->dw, &h->bw}) {
+                b->release();
+                b->alloc(cap);
+            }
             h->nrhs_cap = nrhs;
         }
         h->stats.alloc(5);
@@ -637,7 +646,7 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
             HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
             HIPCHK(launch_permute_in(h->y.p, h->rw.p, n, h->perm.p, n, nrhs, h->cap_stream));
             sweeps(h, h->y.p, nrhs, h->cap_stream);
-            HIPCHK(launch_permute_out(h->dw.p, n, h->y.p, h->perm.p, n, nrhs, h->cap_stream));
+            HIPCHK(launch_permute_out(h->dw.p, n, h->xv.p, h->perm.p, n, nrhs, h->cap_stream));
             HIPCHK(hipStreamEndCapture(h->cap_stream, &h->graph));
             HIPCHK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
             h->graph_nrhs = nrhs;

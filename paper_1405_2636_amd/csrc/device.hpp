@@ -63,8 +63,10 @@ struct SweepArgs {
     int32_t f32;              // 1: panels and inverses are float
     const int32_t* rowg;      // global row of every off-diagonal panel row
     const int64_t* rowg_off;  // [ncblk] start of cblk k's rows in rowg
-    double* y;                // permuted vectors, n x nrhs, leading dimension n
-    double* tacc;             // backward partial sums, n x nrhs
+    double* y;                // permuted right-hand side, accumulates the forward updates (n x nrhs, ld n)
+    double* z;                // forward sweep result L^{-1} P b
+    double* x;                // backward sweep result L^{-T} z
+    double* tacc;             // backward partial sums
     int32_t n;
     int32_t nrhs;
 };

@@ -3,88 +3,120 @@
 // problem, the sweeps are the standard supernodal ones).
 //
 // Forward sweep, column blocks in ascending dependency levels:
-//   y_k <- L_kk^{-1} y_k                  (one workgroup per block)
-//   y[rows of k] -= L_k,off y_k           (row chunks, FP64 atomics)
+//   z_k = L_kk^{-1} y_k                   (diagonal rows split over workgroups)
+//   y[rows of k] -= L_k,off z_k           (64-row chunks, FP64 atomics)
 // Backward sweep, levels descending:
-//   t_k  = L_k,off^T x[rows of k]         (row chunks, wave reductions)
-//   x_k <- L_kk^{-T} (y_k - t_k)
+//   t_k  = L_k,off^T x[rows of k]         (64-row chunks)
+//   x_k  = L_kk^{-T} (z_k - t_k)
 // Both use the inverse of each diagonal block kept by the factorization.
-// The sweeps stream the panels once each: they are bound by HBM bandwidth.
+// Every sweep step writes a different vector than it reads (y -> z -> x), so
+// a diagonal block can be spread over several workgroups.  Every dot product
+// is split over four lanes (interleaved inner indices) and combined by two
+// shuffles: the dependent load rounds per thread are a quarter of a
+// one-lane loop.  The sweeps stream the panels once each: they are bound by
+// HBM bandwidth and, on the narrow top levels, by load latency.
 // The factor is read in its storage type T (double, or float in the FP32
 // refinement mode); vectors and arithmetic are FP64 in both cases.
 #include "device.hpp"
 
 namespace spx {
 
-constexpr int kChunk = 256;   // off-diagonal rows per workgroup
+constexpr int kChunk = 64;   // off-diagonal rows per chunk of the level lists
 
-// ---- forward, diagonal block: y_k <- D y_k with D = L_kk^{-1} (lower, w x w,
-// column-major, kept by the factorization).  Thread r owns row r; the loads
-// D[r + p*w] of one p are contiguous over the threads.
-template <class T>
-__global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblks)
+// sum over the LANES consecutive lanes of a group (LANES = 4 or 16)
+template <int LANES>
+__device__ __forceinline__ double group_sum(double v)
 {
+#pragma unroll
+    for (int o = 1; o < LANES; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ---- forward, diagonal block: z_k = D y_k, D = L_kk^{-1} (lower, w x w,
+// column-major).  LANES lanes per row, 256/LANES rows per workgroup
+// (workgroup g of a block: rows g*256/LANES ..); lane q of a row takes the
+// columns p = q, q+LANES, ..., sixteen loads at a time (p > row clamped and
+// multiplied by zero).  Narrow levels (few blocks) use 16 lanes: fewer
+// dependent load rounds; wide levels 4.  grid = blocks * parts.
+template <class T, int LANES>
+__global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblks, int parts)
+{
+    constexpr int ROWS = 256 / LANES;
     __shared__ double ys[256];
-    const int k = cblks[blockIdx.x];
+    const int k = cblks[blockIdx.x / parts];
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
+    const int r0 = ROWS * (blockIdx.x % parts);
+    if (r0 >= w) return;
     const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, q = tid % LANES, row = min(r0 + tid / LANES, w - 1);
+    const T* Dr = D + row;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        double* y = a.y + (int64_t)rhs * a.n + f;
+        const double* y = a.y + (int64_t)rhs * a.n + f;
         if (tid < w) ys[tid] = y[tid];
         __syncthreads();
-        if (tid < w) {
-            const T* row = D + tid;
-            double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            int p = 0;
-            for (; p + 8 <= tid + 1; p += 8) {
+        double v = 0.0;
+        for (int pb = 0; pb <= row; pb += 16 * LANES) {
+            T d[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] += row[(int64_t)(p + u) * w] * ys[p + u];
+            for (int u = 0; u < 16; ++u) d[u] = Dr[(int64_t)min(pb + q + LANES * u, row) * w];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int p = pb + q + LANES * u;
+                v += (double)d[u] * (p <= row ? ys[min(p, 255)] : 0.0);
             }
-            for (; p <= tid; ++p) v[0] += row[(int64_t)p * w] * ys[p];
-            y[tid] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
         }
+        const double sum = group_sum<LANES>(v);
+        if (r0 + tid / LANES < w && q == 0) a.z[(int64_t)rhs * a.n + f + row] = sum;
         __syncthreads();
     }
 }
 
-// ---- forward, off-diagonal rows: y[g(r)] -= sum_c L[r, c] y_k[c]; thread per
-// row, loads contiguous over the threads
+// ---- forward, off-diagonal rows: y[g(r)] -= sum_c L[r, c] z_k[c].  One
+// workgroup per chunk of 64 rows: lane = row (each load covers 64
+// consecutive rows of one column), wave v = quarter v of the columns (at
+// most 64, issued 16 at a time); the four partial sums meet in LDS.
 template <class T>
 __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
 {
-    __shared__ double yk[256];
+    __shared__ double zk[256];
+    __shared__ double part[4][64];
     const int2 it = chunks[blockIdx.x];
     const int k = it.x, row0 = it.y;
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
     const int64_t ld = pl.stride[k];
     const int nr = min(kChunk, (int)ld - row0);
-    const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0;
-    const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = min(lane, nr - 1);
+    const int qw = (w + 3) >> 2, cb = wave * qw, ce = min(w, cb + qw);
+    const T* Lr = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0 + r;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        double* y = a.y + (int64_t)rhs * a.n;
-        if (tid < w) yk[tid] = y[f + tid];
+        if (tid < w) zk[tid] = a.z[(int64_t)rhs * a.n + f + tid];
         __syncthreads();
-        if (tid < nr) {
-            const T* row = L + tid;
-            double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            int c = 0;
-            for (; c + 8 <= w; c += 8) {
+        double v = 0.0;
+        for (int c = cb; c < ce; c += 16) {
+            T l[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] += row[(c + u) * ld] * yk[c + u];
-            }
-            for (; c < w; ++c) v[0] += row[c * ld] * yk[c];
-            unsafeAtomicAdd(y + g[tid], -(((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))));
+            for (int u = 0; u < 16; ++u) l[u] = Lr[(int64_t)min(c + u, ce - 1) * ld];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v += (double)l[u] * (c + u < ce ? zk[min(c + u, w - 1)] : 0.0);
+        }
+        part[wave][lane] = v;
+        __syncthreads();
+        if (wave == 0 && lane < nr) {
+            const double sum = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+            unsafeAtomicAdd(a.y + (int64_t)rhs * a.n + a.rowg[a.rowg_off[k] + (row0 - w) + lane], -sum);
         }
         __syncthreads();
     }
 }
 
-// ---- backward, off-diagonal rows: tacc[f + c] += sum_r L[r, c] x[g(r)];
-// thread per column, each streaming down its own column of the chunk
+// ---- backward, off-diagonal rows: tacc[f + c] += sum_r L[r, c] x[g(r)].
+// One workgroup per chunk of 64 rows; four lanes per column (columns
+// tid/4, tid/4 + 64, ...), lane q takes the rows q, q+4, ..., q+60 with all
+// sixteen loads in flight; each load instruction covers four consecutive
+// rows of sixteen columns.
 template <class T>
 __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
 {
@@ -95,56 +127,63 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
     const int64_t ld = pl.stride[k];
     const int nr = min(kChunk, (int)ld - row0);
-    const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0;
     const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, q = tid & 3;
+    const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        const double* x = a.y + (int64_t)rhs * a.n;
+        const double* x = a.x + (int64_t)rhs * a.n;
         if (tid < nr) xr[tid] = x[g[tid]];
         __syncthreads();
-        if (tid < w) {
-            const T* col = L + (int64_t)tid * ld;
-            double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            int r = 0;
-            for (; r + 8 <= nr; r += 8) {
+        for (int cb = 0; cb < w; cb += 64) {
+            const int c = min(cb + (tid >> 2), w - 1);
+            const T* Lc = L + (int64_t)c * ld;
+            T l[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] += col[r + u] * xr[r + u];
-            }
-            for (; r < nr; ++r) v[0] += col[r] * xr[r];
-            unsafeAtomicAdd(a.tacc + (int64_t)rhs * a.n + f + tid,
-                            ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])));
+            for (int u = 0; u < 16; ++u) l[u] = Lc[min(q + 4 * u, nr - 1)];
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v += (double)l[u] * (q + 4 * u < nr ? xr[q + 4 * u] : 0.0);
+            const double sum = group_sum<4>(v);
+            if (cb + (tid >> 2) < w && q == 0) unsafeAtomicAdd(a.tacc + (int64_t)rhs * a.n + f + c, sum);
         }
         __syncthreads();
     }
 }
 
-// ---- backward, diagonal block: x_k <- D^T (y_k - t_k); thread c streams
-// down column c of D
-template <class T>
-__global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblks)
+// ---- backward, diagonal block: x_k = D^T (z_k - t_k); LANES lanes per
+// column c of D, lane q takes the rows p = c+q, c+q+LANES, ... (p >= w
+// clamped and multiplied by zero); same grid as the forward kernel
+template <class T, int LANES>
+__global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblks, int parts)
 {
+    constexpr int ROWS = 256 / LANES;
     __shared__ double zs[256];
-    const int k = cblks[blockIdx.x];
+    const int k = cblks[blockIdx.x / parts];
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
+    const int c0 = ROWS * (blockIdx.x % parts);
+    if (c0 >= w) return;
     const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, q = tid % LANES, col = min(c0 + tid / LANES, w - 1);
+    const T* Dc = D + (int64_t)col * w;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        double* y = a.y + (int64_t)rhs * a.n + f;
+        const double* z = a.z + (int64_t)rhs * a.n + f;
         const double* t = a.tacc + (int64_t)rhs * a.n + f;
-        if (tid < w) zs[tid] = y[tid] - t[tid];
+        if (tid < w) zs[tid] = z[tid] - t[tid];
         __syncthreads();
-        if (tid < w) {
-            const T* col = D + (int64_t)tid * w;
-            double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            int p = tid;
-            for (; p + 8 <= w; p += 8) {
+        double v = 0.0;
+        for (int pb = col; pb < w; pb += 16 * LANES) {
+            T d[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] += col[p + u] * zs[p + u];
+            for (int u = 0; u < 16; ++u) d[u] = Dc[min(pb + q + LANES * u, w - 1)];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int p = pb + q + LANES * u;
+                v += (double)d[u] * (p < w ? zs[min(p, w - 1)] : 0.0);
             }
-            for (; p < w; ++p) v[0] += col[p] * zs[p];
-            y[tid] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
         }
+        const double sum = group_sum<LANES>(v);
+        if (c0 + tid / LANES < w && q == 0) a.x[(int64_t)rhs * a.n + f + col] = sum;
         __syncthreads();
     }
 }
@@ -254,11 +293,21 @@ __global__ void __launch_bounds__(256) residual_kernel(const int64_t* rptr, cons
 // ---- host launchers
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
-hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s)
+// levels with fewer blocks than this use 16 lanes per row in the diagonal kernels
+constexpr int kNarrowLevel = 64;
+
+hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    if (a.f32) fwd_diag<float><<<count, 256, 0, s>>>(a, cblks);
-    else fwd_diag<double><<<count, 256, 0, s>>>(a, cblks);
+    if (count < kNarrowLevel) {
+        const int parts = (maxw + 15) / 16;
+        if (a.f32) fwd_diag<float, 16><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+        else fwd_diag<double, 16><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+    } else {
+        const int parts = (maxw + 63) / 64;
+        if (a.f32) fwd_diag<float, 4><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+        else fwd_diag<double, 4><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+    }
     return hipGetLastError();
 }
 hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s)
@@ -275,11 +324,18 @@ hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hip
     else bwd_off<double><<<count, 256, 0, s>>>(a, chunks);
     return hipGetLastError();
 }
-hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s)
+hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    if (a.f32) bwd_diag<float><<<count, 256, 0, s>>>(a, cblks);
-    else bwd_diag<double><<<count, 256, 0, s>>>(a, cblks);
+    if (count < kNarrowLevel) {
+        const int parts = (maxw + 15) / 16;
+        if (a.f32) bwd_diag<float, 16><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+        else bwd_diag<double, 16><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+    } else {
+        const int parts = (maxw + 63) / 64;
+        if (a.f32) bwd_diag<float, 4><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+        else bwd_diag<double, 4><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+    }
     return hipGetLastError();
 }
 hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,
