@@ -232,16 +232,10 @@ void build_tasks(spx_handle* h)
     const Plan& P = h->plan;
     const int32_t nc = P.ncblk;
     constexpr int kTrsmRows = 64;
-    // high priority for the upper part of the block tree, where dependency
-    // levels hold few blocks and the elimination chains are critical
-    std::vector<int32_t> lvl(nc, 0), hp(nc, 0);
-    for (int32_t k = 0; k < nc; ++k)
-        for (int32_t q = P.uptr[k]; q < P.uptr[k + 1]; ++q) lvl[P.utgt[q]] = std::max(lvl[P.utgt[q]], lvl[k] + 1);
-    {
-        std::vector<int32_t> per_level(static_cast<size_t>(nc) + 1, 0);
-        for (int32_t k = 0; k < nc; ++k) ++per_level[lvl[k]];
-        for (int32_t k = 0; k < nc; ++k) hp[k] = per_level[lvl[k]] <= 32 ? 1 : 0;
-    }
+    // high priority: FACT, the TRSM tiles and the update tiles into the first
+    // facing block (the elimination chain) of every block; the other update
+    // tiles form the bulk in the normal queue
+    std::vector<int32_t> hp(nc, 1);
     std::vector<int4> desc;
     desc.reserve(static_cast<size_t>(nc) * 2);
     std::vector<int32_t> tf(nc), tc(nc), uf(nc), uh(nc), ucnt(nc), dep(nc, 0);

@@ -16,7 +16,7 @@
 // Dependencies are counters: FACT(j) becomes ready when every UPDATE tile
 // into j is done, the TRSM tiles of k when FACT(k) is done, the UPDATE tiles
 // of k when its last TRSM tile is done.  FACT, TRSM and the updates into the
-// next block of a chain go to a high-priority queue that workers poll first.
+// first facing block go to a high-priority queue that workers poll first.
 // Products run on the matrix cores: v_mfma_f64_16x16x4f64 for the FP64
 // factor, v_mfma_f32_16x16x4f32 for the FP32 factor of the refinement mode
 // (whose 32x32 diagonal tiles are still factored and inverted in FP64).
@@ -551,22 +551,6 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
 }
 
 // ---------------------------------------------------------------- queues
-// Try to take the oldest published item of the high-priority queue.
-__device__ __forceinline__ int try_claim_hp(const SchedArgs& a)
-{
-    for (int tries = 0; tries < 4; ++tries) {
-        const int h = __hip_atomic_load(a.hp_head, __ATOMIC_RELAXED, AGENT);
-        if (h >= a.hp_total) return -1;
-        const int it = __hip_atomic_load(&a.hp_queue[h], __ATOMIC_RELAXED, AGENT);
-        if (it < 0) return -1;
-        int expected = h;
-        if (__hip_atomic_compare_exchange_strong(a.hp_head, &expected, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 AGENT))
-            return it;
-    }
-    return -1;
-}
-
 __device__ __forceinline__ void push_items(const SchedArgs& a, bool hp, int base, int first, int count)
 {
     int32_t* q = hp ? a.hp_queue : a.queue;
@@ -591,7 +575,13 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
     __shared__ int s_push[6];   // {hp first, hp count, hp base, normal first, normal count, normal base}
     __shared__ int64_t s_t0, s_t1;
     const int tid = threadIdx.x;
-    int my_slot = -1;   // claimed normal-queue slot not yet served (thread 0)
+    // Tickets of the two FIFO queues held by this worker and not yet served
+    // (thread 0).  A ticket below the queue's total is always served: its item
+    // is pushed eventually.  A high-priority ticket is taken only when the
+    // next slot is already published, so that an idle worker picks up a
+    // released critical item at once; a worker holding one serves whichever
+    // of its two items is published first.
+    int my_slot = -1, hp_slot = -1;
     for (;;) {
         if (tid == 0) {
             int item = -1;
@@ -599,14 +589,23 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
             const int64_t t0 = s_t0;
             for (;;) {
                 if (__hip_atomic_load(&a.status[1], __ATOMIC_RELAXED, AGENT) != 0) { item = -1; break; }
-                item = try_claim_hp(a);
-                if (item >= 0) break;
+                if (hp_slot < 0) {
+                    const int h = __hip_atomic_load(a.hp_head, __ATOMIC_RELAXED, AGENT);
+                    if (h < a.hp_total && __hip_atomic_load(&a.hp_queue[h], __ATOMIC_RELAXED, AGENT) >= 0) {
+                        const int t = __hip_atomic_fetch_add(a.hp_head, 1, __ATOMIC_RELAXED, AGENT);
+                        hp_slot = t < a.hp_total ? t : -1;
+                    }
+                }
+                if (hp_slot >= 0) {
+                    item = __hip_atomic_load(&a.hp_queue[hp_slot], __ATOMIC_RELAXED, AGENT);
+                    if (item >= 0) { hp_slot = -1; break; }
+                }
                 if (my_slot < 0) my_slot = __hip_atomic_fetch_add(a.qhead, 1, __ATOMIC_RELAXED, AGENT);
                 if (my_slot < a.total_normal) {
                     item = __hip_atomic_load(&a.queue[my_slot], __ATOMIC_RELAXED, AGENT);
                     if (item >= 0) { my_slot = -1; break; }
-                } else if (__hip_atomic_load(a.hp_head, __ATOMIC_RELAXED, AGENT) >= a.hp_total) {
-                    item = -1;   // both queues exhausted
+                } else if (hp_slot < 0 && __hip_atomic_load(a.hp_head, __ATOMIC_RELAXED, AGENT) >= a.hp_total) {
+                    item = -1;   // no ticket left to serve in either queue
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
