@@ -29,6 +29,19 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 #define AGENT __HIP_MEMORY_SCOPE_AGENT
 
+// Pointers into device (global) memory.  The panels reach the tasks as
+// generic pointers; typing them as global lets the compiler use global
+// stores and atomics (scalar base, 32-bit lane offset) instead of flat ones.
+template <class T>
+struct Glob {
+    typedef __attribute__((address_space(1))) T type;
+};
+template <class T>
+__device__ __forceinline__ typename Glob<T>::type* glob(T* p)
+{
+    return (typename Glob<T>::type*)p;
+}
+
 // The 16x16x4 matrix-core product of one element type.  Operand A lane l
 // holds A[l%16][l/16], operand B lane l holds B[l/16][l%16]; the four result
 // slots of lane l hold column l%16 of D, at the rows drow(v, l/16).
@@ -503,7 +516,7 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
     const int w = pl.lcol[k] - pl.fcol[k] + 1;
     const int64_t ld = pl.stride[k];
     T* P = static_cast<T*>(a.panels) + pl.panel_off[k];
-    T* B = P + row0;
+    auto B = glob(P + row0);
     const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
     const int wave = threadIdx.x >> 6;
     typename MM<T>::acc acc[4][4];
@@ -532,7 +545,7 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
     const int w = pl.lcol[k] - pl.fcol[k] + 1;
     const int64_t ld = pl.stride[k], ldj = pl.stride[j];
     const T* A = static_cast<const T*>(a.panels) + pl.panel_off[k];
-    T* C = static_cast<T*>(a.panels) + pl.panel_off[j];
+    auto Cg = glob(static_cast<T*>(a.panels) + pl.panel_off[j]);
     const int tid = threadIdx.x, wave = tid >> 6;
     if (tid < mrows) rpos[tid] = a.rmap[mbase + row0 + tid];
     if (tid < ncols) cpos[tid] = a.rmap[mbase + col0 + tid];
@@ -545,7 +558,7 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
         wave_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0, 1, ld), make_gop(A, ld * w, col0, 1, ld), w);
         wave_store<T>(acc, mv, ncols, [&](int r, int c, T v) {
             const int tr = rpos[r0 + r], tc = cpos[c];
-            if (tr >= tc) unsafeAtomicAdd(C + (int64_t)tc * ldj + tr, -v);
+            if (tr >= tc) __hip_atomic_fetch_add(Cg + (int64_t)tc * ldj + tr, -v, __ATOMIC_RELAXED, AGENT);
         });
     }
 }
@@ -625,10 +638,20 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         __syncthreads();
         const int4 d0 = a.desc[2 * item];
         const int4 d1 = a.desc[2 * item + 1];
-        if (d0.x == kFact) task_fact<T>(a, d0.y, Lt, Dt, Pb);
-        else if (d0.x == kTrsm) task_trsm<T>(a, d0.y, d0.z, d0.w);
-        else task_update<T>(a, d0, d1, rpos, cpos);
+        if (d0.x == kFact) {
+            __builtin_amdgcn_s_setprio(3);
+            task_fact<T>(a, d0.y, Lt, Dt, Pb);
+            __builtin_amdgcn_s_setprio(0);
+        } else if (d0.x == kTrsm) {
+            __builtin_amdgcn_s_setprio(2);
+            task_trsm<T>(a, d0.y, d0.z, d0.w);
+            __builtin_amdgcn_s_setprio(0);
+        } else {
+            task_update<T>(a, d0, d1, rpos, cpos);
+        }
         // every wave's stores and atomics have completed before the barrier
+        // (FACT and TRSM items ran at raised wave priority: they are on the
+        // elimination chain and share their CU with update tiles)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid < 64 && d0.x != kUpdate) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
