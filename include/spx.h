@@ -157,6 +157,21 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
 int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_device,
               spx_solve_info* info, void* hip_stream);
 
+/* Adjoint of the solve (x = A^{-1} b): gradient of a loss with respect to
+ * the values passed to spx_factorize, given x and db = A^{-T} xbar (for
+ * symmetric A, db is spx_solve applied to xbar with the same factor).  The
+ * derivative with respect to the matrix is dA = -db x^T summed over the
+ * right-hand sides, restricted to the pattern; a stored lower entry a_ij
+ * (i > j) stands for both a_ij and a_ji, so
+ *   grad[p] = -sum_k (db[i,k] x[j,k] + db[j,k] x[i,k])   for p = (i, j), i > j,
+ *   grad[p] = -sum_k db[i,k] x[i,k]                       for i = j,
+ *   grad[p] = 0                                           for i < j (not read).
+ * x, db: device, n x nrhs column-major with leading dimension ld >= n;
+ * grad: device, colptr[n] doubles aligned with the analysed pattern.
+ * Errors: SPX_ESTATE (no device plan yet), SPX_EINVAL, SPX_EDEVICE. */
+int spx_values_grad(spx_handle* h, int32_t nrhs, const double* x, const double* db, int64_t ld,
+                    double* grad, void* hip_stream);
+
 /* Statistics of the analysis and of the last factorization. */
 int spx_get_info(const spx_handle* h, spx_info* info);
 

@@ -318,3 +318,32 @@ def unpack(sym: Symbolic, P):
     q = L.orc_unpack(C.c_void_p(sym.handle), _p(_c(P, np.float64)), _p(ri), _p(ci), _p(v))
     assert q == cnt
     return ri, ci, v
+
+
+def values_grad(n, colptr, rowind, x, db):
+    """Gradient of a loss through x = A^{-1} b with respect to the stored values
+    of A, given x and db = A^{-T} xbar (the derivative of x = A^{-1} b with
+    respect to A is dA = -db x^T, summed over right-hand sides).  A stored
+    lower entry a_ij (i > j) sets both A_ij and A_ji, so its gradient is
+    -(db_i x_j + db_j x_i); a diagonal entry gets -db_i x_i; an entry above
+    the diagonal is not read by the factorization and gets 0."""
+    colptr = np.asarray(colptr, np.int64)
+    rowind = np.asarray(rowind, np.int64)
+    x = np.asarray(x, np.float64).reshape(n, -1)
+    db = np.asarray(db, np.float64).reshape(n, -1)
+    col = np.repeat(np.arange(n), np.diff(colptr))
+    g = np.zeros(len(rowind))
+    for p in range(len(rowind)):
+        i, j = int(rowind[p]), int(col[p])
+        if i > j:
+            g[p] = -float(np.dot(db[i], x[j]) + np.dot(db[j], x[i]))
+        elif i == j:
+            g[p] = -float(np.dot(db[i], x[i]))
+    return g
+
+
+def adjoint(sym: Symbolic, P, colptr, rowind, values, x, xbar):
+    """Backward pass of x = A^{-1} b for symmetric A: db = A^{-T} xbar = A^{-1} xbar
+    (the same factor, refined), and the value gradient of ``values_grad``."""
+    db, _ = solve_refined(sym, P, colptr, rowind, values, xbar)
+    return db, values_grad(sym.n, colptr, rowind, x, db)

@@ -13,5 +13,6 @@ from .spx import (  # noqa: F401
     NotPositiveDefinite,
     NotConverged,
     load_library,
+    solve_autograd,
     SYMBOLIC_FIELDS,
 )

@@ -40,6 +40,8 @@ hipError_t launch_permute_out(double* x, int64_t ldx, const double* y, const int
                               hipStream_t s);
 hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+hipError_t launch_values_grad(const int32_t* erow, const int32_t* ecol, int64_t nnz, const double* x, const double* db,
+                              int64_t ld, int32_t nrhs, double* grad, hipStream_t s);
 hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const int64_t* rval, const double* vals,
                            const double* x, const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
                            unsigned long long* stats, hipStream_t s);
@@ -114,6 +116,7 @@ struct spx_handle {
     DevBuf<int64_t> panel_off, dinv_off;
     DevBuf<int64_t> amap, rptr, rval;
     DevBuf<int32_t> rcol;
+    DevBuf<int32_t> erow, ecol;   // row and column of every stored entry (-1: above the diagonal)
     DevBuf<int32_t> rowg;
     DevBuf<int64_t> rowg_off;
     // scheduler tables
@@ -409,6 +412,20 @@ void upload_plan(spx_handle* h)
     rgo[P.ncblk] = static_cast<int64_t>(rg.size());
     h->rowg.upload(rg);
     h->rowg_off.upload(rgo);
+    {
+        // coordinates of the entries read by the factorization, from the
+        // symmetric row lists of the residual (each lower entry appears in
+        // row i with column j <= i)
+        std::vector<int32_t> er(static_cast<size_t>(h->nnz), -1), ec(static_cast<size_t>(h->nnz), -1);
+        for (int32_t i = 0; i < P.n; ++i)
+            for (int64_t q = P.rptr[i]; q < P.rptr[i + 1]; ++q)
+                if (P.rcol[q] <= i) {
+                    er[static_cast<size_t>(P.rval[q])] = i;
+                    ec[static_cast<size_t>(P.rval[q])] = P.rcol[q];
+                }
+        h->erow.upload(er);
+        h->ecol.upload(ec);
+    }
     build_tasks(h);
     build_levels(h);
     for (auto& e : h->ev)
@@ -683,6 +700,22 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
         const bool conv = omega <= tol;
         if (info) *info = spx_solve_info{iters, conv ? 1 : 0, omega, eta};
         if (!conv) throw StatusError(SPX_ENOCONV, "refinement stopped above the tolerance");
+        return SPX_OK;
+    });
+}
+
+int spx_values_grad(spx_handle* h, int32_t nrhs, const double* x, const double* db, int64_t ld, double* grad,
+                    void* hip_stream)
+{
+    if (!h) return SPX_EINVAL;
+    return guarded(h, [&]() -> int {
+        if (!h->uploaded) throw StatusError(SPX_ESTATE, "no device plan (no factorization yet)");
+        if (nrhs < 0 || (nrhs > 0 && ld < h->n)) throw InvalidArgument("bad vector shape");
+        if (h->nnz > 0 && !grad) throw InvalidArgument("grad is NULL");
+        if (nrhs > 0 && h->n > 0 && (!x || !db)) throw InvalidArgument("x or db is NULL");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        HIPCHK(launch_values_grad(h->erow.p, h->ecol.p, h->nnz, x, db, ld, nrhs, grad, s));
+        HIPCHK(hipStreamSynchronize(s));
         return SPX_OK;
     });
 }

@@ -290,6 +290,27 @@ __global__ void __launch_bounds__(256) residual_kernel(const int64_t* rptr, cons
     }
 }
 
+// ---- value gradient of x = A^{-1} b (adjoint): for a stored entry p = (i, j),
+// grad[p] = -sum_k (db[i,k] x[j,k] + db[j,k] x[i,k]) if i > j, -sum_k db[i,k] x[i,k]
+// if i == j, and 0 for entries above the diagonal (erow[p] < 0: not read by
+// the factorization)
+__global__ void values_grad_kernel(const int32_t* erow, const int32_t* ecol, int64_t nnz, const double* x,
+                                   const double* db, int64_t ld, int32_t nrhs, double* grad)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = erow[p], j = ecol[p];
+        double g = 0.0;
+        if (i >= 0) {
+            for (int32_t k = 0; k < nrhs; ++k) {
+                const double* xk = x + (int64_t)k * ld;
+                const double* dk = db + (int64_t)k * ld;
+                g -= i == j ? dk[i] * xk[i] : dk[i] * xk[j] + dk[j] * xk[i];
+            }
+        }
+        grad[p] = g;
+    }
+}
+
 // ---- host launchers
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
@@ -369,4 +390,14 @@ hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const int64
     return hipGetLastError();
 }
 
+}  // namespace spx
+
+namespace spx {
+hipError_t launch_values_grad(const int32_t* erow, const int32_t* ecol, int64_t nnz, const double* x, const double* db,
+                              int64_t ld, int32_t nrhs, double* grad, hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    values_grad_kernel<<<grid_for(nnz), 256, 0, s>>>(erow, ecol, nnz, x, db, ld, nrhs, grad);
+    return hipGetLastError();
+}
 }  // namespace spx

@@ -71,7 +71,7 @@ class SymView(C.Structure):
 
 EXPORTED = ["spx_default_options", "spx_analyze", "spx_factorize", "spx_solve", "spx_get_info",
             "spx_export_symbolic", "spx_copy_factor", "spx_get_trace", "spx_destroy", "spx_strerror",
-            "spx_last_error"]
+            "spx_last_error", "spx_values_grad"]
 
 _lib = None
 
@@ -101,6 +101,8 @@ def load_library():
     L.spx_copy_factor.argtypes = [vp, vp, C.c_int32, vp]
     L.spx_get_trace.restype = C.c_int64
     L.spx_get_trace.argtypes = [vp, vp, C.c_int64, vp]
+    L.spx_values_grad.restype = C.c_int
+    L.spx_values_grad.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, vp, vp]
     L.spx_destroy.restype = None
     L.spx_destroy.argtypes = [vp]
     L.spx_strerror.restype = C.c_char_p
@@ -259,3 +261,61 @@ class Solver:
         rc = self._lib.spx_copy_factor(self._h, C.c_void_p(out.data_ptr()), 1, _stream_ptr(stream))
         self._check(rc, "copy_factor")
         return out[:cnt]
+
+    def values_grad(self, x, db, stream=None):
+        """Adjoint of the solve: gradient with respect to the values given x and
+        db = A^{-1} xbar (torch CUDA float64 tensors of shape (n,) or (nrhs, n),
+        one right-hand side per row).  Returns a float64 CUDA tensor of nnz
+        entries (zero for entries above the diagonal, which are not read)."""
+        import torch
+        for t in (x, db):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("x and db must be contiguous float64 CUDA tensors")
+        if x.shape != db.shape or x.shape[-1] != self.n:
+            raise ValueError("x and db must have the same shape (n,) or (nrhs, n)")
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        grad = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=x.device)
+        rc = self._lib.spx_values_grad(self._h, nrhs, C.c_void_p(x.data_ptr()), C.c_void_p(db.data_ptr()), self.n,
+                                       C.c_void_p(grad.data_ptr()), _stream_ptr(stream))
+        self._check(rc, "values_grad")
+        return grad[:self.nnz]
+
+
+def _solve_function():
+    import torch
+
+    class SolveFunction(torch.autograd.Function):
+        """x = A(values)^{-1} b with a hand-written adjoint: the backward pass
+        solves with the same factor (db = A^{-1} xbar, A symmetric) and forms the
+        value gradient -db x^T restricted to the pattern (spx_values_grad)."""
+
+        @staticmethod
+        def forward(ctx, values, b, solver):
+            solver.factorize(values.detach().contiguous())
+            x, _ = solver.solve(b.detach().clone().contiguous())
+            ctx.solver = solver
+            ctx.save_for_backward(x)
+            return x
+
+        @staticmethod
+        def backward(ctx, xbar):
+            (x,) = ctx.saved_tensors
+            solver = ctx.solver
+            db, _ = solver.solve(xbar.detach().clone().contiguous())
+            gv = solver.values_grad(x, db) if ctx.needs_input_grad[0] else None
+            return gv, (db if ctx.needs_input_grad[1] else None), None
+
+    return SolveFunction
+
+
+_SOLVE_FN = None
+
+
+def solve_autograd(solver, values, b):
+    """Differentiable x = A^{-1} b for the pattern analysed by ``solver``:
+    values (nnz,) and b ((n,) or (nrhs, n)) are float64 CUDA tensors; gradients
+    flow to both.  Each call factorizes ``values``."""
+    global _SOLVE_FN
+    if _SOLVE_FN is None:
+        _SOLVE_FN = _solve_function()
+    return _SOLVE_FN.apply(values, b, solver)
