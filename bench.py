@@ -120,11 +120,23 @@ def run_leg(torch, np, Solver, p, vals, b0, precision, steps, warmup):
         its.append(si["ir_iters"])
         print("[%s] step %d: factorize %.2f ms (kernel %.2f) solve %.2f ms omega %.2e ir %d"
               % (precision, i, fac_ms[-1], ker_ms[-1], sol_ms[-1], oms[-1], its[-1]), flush=True)
+    # adjoint of the solve (backward pass of solve_autograd): db = A^{-1} xbar
+    # with the same factor, then the value gradient on the pattern
+    xbar = torch.ones_like(b0)
+    adj_ms = []
+    for i in range(3):
+        ev[0].record(stream)
+        db = xbar.clone()
+        s.solve(db)
+        s.values_grad(b, db)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        adj_ms.append(ev[0].elapsed_time(ev[1]))
     del s
     torch.cuda.synchronize()
     return {"factor_ms": float(np.median(fac_ms)), "solve_ms": float(np.median(sol_ms)),
             "kernel_ms": float(np.mean(ker_ms)), "omega": float(max(oms)), "ir_iters": int(max(its)),
-            "flops": info["flops_alg"], "nnz_l": info["nnz_l"]}
+            "flops": info["flops_alg"], "nnz_l": info["nnz_l"], "adjoint_ms": float(np.median(adj_ms))}
 
 
 def main():
@@ -177,6 +189,7 @@ def main():
         "solve_ms": r64["solve_ms"],
         "omega": r64["omega"],
         "ir_iters": r64["ir_iters"],
+        "adjoint_ms": r64["adjoint_ms"],
         "fp32_ir": {"factor_ms": r32["factor_ms"], "solve_ms": r32["solve_ms"],
                     "factor_gflops": flops / (r32["factor_ms"] * 1e-3) / 1e9, "omega": r32["omega"],
                     "ir_iters": r32["ir_iters"], "kernel_ms": r32["kernel_ms"],

@@ -42,9 +42,10 @@ hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 hipError_t launch_values_grad(const int32_t* erow, const int32_t* ecol, int64_t nnz, const double* x, const double* db,
                               int64_t ld, int32_t nrhs, double* grad, hipStream_t s);
-hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const int64_t* rval, const double* vals,
-                           const double* x, const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
+hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const double* rv, const double* x,
+                           const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
                            unsigned long long* stats, hipStream_t s);
+hipError_t launch_gather(double* rv, const double* vals, const int64_t* idx, int64_t m, hipStream_t s);
 
 struct DeviceError : std::runtime_error {
     explicit DeviceError(const std::string& s) : std::runtime_error(s) {}
@@ -131,7 +132,7 @@ struct spx_handle {
     DevBuf<int32_t> lv_cblk;
     DevBuf<int2> lv_chunk;
     // numeric: FP64 panels and inverses, or their FP32 counterparts
-    DevBuf<double> panels, dinv, vals;
+    DevBuf<double> panels, dinv, vals, rv;   // rv: values in the order of the residual's row lists
     DevBuf<float> panels_f, dinv_f;
     int64_t dinv_size = 0;
     bool factorized = false;
@@ -571,6 +572,9 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
         if (f32) HIPCHK(launch_fill_f32(h->panels_f.p, P.panel_entries, 0.0f, s));
         else HIPCHK(launch_fill_f64(h->panels.p, P.panel_entries, 0.0, s));
         HIPCHK(launch_assemble(h->panel_ptr(), f32, h->amap.p, h->vals.p, h->nnz, s));
+        const int64_t nsym = P.rptr.empty() ? 0 : P.rptr.back();
+        h->rv.alloc(static_cast<size_t>(nsym));
+        HIPCHK(launch_gather(h->rv.p, h->vals.p, h->rval.p, nsym, s));
         SchedArgs a;
         a.pl = h->devplan();
         a.panels = h->panel_ptr();
@@ -674,7 +678,7 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
         const double tol = h->opt.ir_tol;
         for (;;) {
             HIPCHK(launch_zero_u64(h->stats.p, 5, s));
-            HIPCHK(launch_residual(h->rptr.p, h->rcol.p, h->rval.p, h->vals.p, h->xw.p, h->bw.p, n, h->rw.p, n, nrhs,
+            HIPCHK(launch_residual(h->rptr.p, h->rcol.p, h->rv.p, h->xw.p, h->bw.p, n, h->rw.p, n, nrhs,
                                    h->stats.p, s));
             unsigned long long st[5];
             HIPCHK(hipMemcpyAsync(st, h->stats.p, sizeof st, hipMemcpyDeviceToHost, s));

@@ -242,12 +242,13 @@ __device__ __forceinline__ unsigned long long block_max(unsigned long long v)
 }
 
 // r = b - A x and componentwise / normwise error statistics, in FP64.
-// A is read through the symmetric row pattern (rptr, rcol) whose values are
-// the input entries rval[q] (lower triangle mirrored).
+// A is read through the symmetric row pattern (rptr, rcol) with its values rv
+// in the same order (the input's lower triangle mirrored, gathered once per
+// factorization by gather_kernel so that the residual reads them in order).
 // stats[0] = max_i |r_i| / (|A||x| + |b|)_i   (0/0 = 0, p/0 = inf)
 // stats[1] = max |r_i|, stats[2] = max |x_i|, stats[3] = max |b_i|, stats[4] = max_i sum_j |a_ij|
-__global__ void __launch_bounds__(256) residual_kernel(const int64_t* rptr, const int32_t* rcol, const int64_t* rval,
-                                                       const double* vals, const double* x, const double* b,
+__global__ void __launch_bounds__(256) residual_kernel(const int64_t* rptr, const int32_t* rcol, const double* rv,
+                                                       const double* x, const double* b,
                                                        int64_t ldb, double* r, int32_t n, int32_t nrhs,
                                                        unsigned long long* stats)
 {
@@ -259,7 +260,7 @@ __global__ void __launch_bounds__(256) residual_kernel(const int64_t* rptr, cons
         const double bi = b[c * ldb + i];
         double acc = bi, den = fabs(bi), arow = 0.0;
         for (int64_t q = rptr[i]; q < rptr[i + 1]; ++q) {
-            const double av = vals[rval[q]];
+            const double av = rv[q];
             const double xv = xc[rcol[q]];
             acc -= av * xv;
             den += fabs(av) * fabs(xv);
@@ -288,6 +289,13 @@ __global__ void __launch_bounds__(256) residual_kernel(const int64_t* rptr, cons
         atomicMax(stats + 3, m3);
         atomicMax(stats + 4, m4);
     }
+}
+
+// ---- rv[q] = vals[idx[q]]
+__global__ void gather_kernel(double* rv, const double* vals, const int64_t* idx, int64_t m)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < m; q += (int64_t)gridDim.x * blockDim.x)
+        rv[q] = vals[idx[q]];
 }
 
 // ---- value gradient of x = A^{-1} b (adjoint): for a stored entry p = (i, j),
@@ -382,17 +390,23 @@ hipError_t launch_axpy(double* x, const double* d, int64_t n, hipStream_t s)
     axpy_kernel<<<grid_for(n), 256, 0, s>>>(x, d, n);
     return hipGetLastError();
 }
-hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const int64_t* rval, const double* vals,
-                           const double* x, const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
+hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const double* rv, const double* x,
+                           const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
                            unsigned long long* stats, hipStream_t s)
 {
-    residual_kernel<<<grid_for((int64_t)n * nrhs), 256, 0, s>>>(rptr, rcol, rval, vals, x, b, ldb, r, n, nrhs, stats);
+    residual_kernel<<<grid_for((int64_t)n * nrhs), 256, 0, s>>>(rptr, rcol, rv, x, b, ldb, r, n, nrhs, stats);
     return hipGetLastError();
 }
 
 }  // namespace spx
 
 namespace spx {
+hipError_t launch_gather(double* rv, const double* vals, const int64_t* idx, int64_t m, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    gather_kernel<<<grid_for(m), 256, 0, s>>>(rv, vals, idx, m);
+    return hipGetLastError();
+}
 hipError_t launch_values_grad(const int32_t* erow, const int32_t* ecol, int64_t nnz, const double* x, const double* db,
                               int64_t ld, int32_t nrhs, double* grad, hipStream_t s)
 {
