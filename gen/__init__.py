@@ -10,5 +10,7 @@ from .stencils import (  # noqa: F401
     random_pattern,
     make_config,
     rhs,
+    weighted_grid,
+    grid_batch,
     CONFIG_NAMES,
 )

@@ -21,6 +21,7 @@ import numpy as np
 CONFIG_NAMES = {
     1: "laplace2d_5pt_64x64",
     2: "laplace3d_7pt_100^3_shift1e-3",
+    4: "batch512_wgrid2d_16-96",
 }
 
 
@@ -142,6 +143,50 @@ def rhs(n: int, nrhs: int, seed: int) -> np.ndarray:
     """
     rng = np.random.default_rng(seed)
     return np.asfortranarray(rng.uniform(-1.0, 1.0, size=(nrhs, n)).T)
+
+
+def weighted_grid(nx: int, ny: int, rng) -> Problem:
+    """Weighted graph Laplacian of an nx x ny grid with ghost edges: every grid
+    edge and every boundary-to-ghost edge (one per missing neighbour of a
+    boundary node) gets a weight ~ lognormal(0, 1); a_ij = -w_ij for grid
+    edges, a_ii = sum of the weights of all edges at i (ghost edges included),
+    so A is symmetric positive definite.  Draw order: x-edges, y-edges, ghost
+    edges (x-low, x-high, y-low, y-high)."""
+    n = nx * ny
+    x = np.arange(n) % nx
+    y = np.arange(n) // nx
+    idx = np.arange(n, dtype=np.int64)
+    ex = idx[x < nx - 1]
+    ey = idx[y < ny - 1]
+    wx = rng.lognormal(0.0, 1.0, len(ex))
+    wy = rng.lognormal(0.0, 1.0, len(ey))
+    diag = np.zeros(n)
+    np.add.at(diag, ex, wx)
+    np.add.at(diag, ex + 1, wx)
+    np.add.at(diag, ey, wy)
+    np.add.at(diag, ey + nx, wy)
+    for ghost in (x == 0, x == nx - 1, y == 0, y == ny - 1):
+        g = idx[ghost]
+        diag[g] += rng.lognormal(0.0, 1.0, len(g))
+    rows = np.concatenate([idx, ex, ex + 1, ey, ey + nx])
+    cols = np.concatenate([idx, ex + 1, ex, ey + nx, ey])
+    vals = np.concatenate([diag, -wx, -wx, -wy, -wy])
+    colptr, rowind, values = _coo_to_csc(n, rows, cols, vals)
+    return Problem(n, colptr, rowind, values, name="wgrid_%dx%d" % (nx, ny), meta={"dims": (nx, ny)})
+
+
+def grid_batch(nsys: int = 512, seed: int = 1004, lo: int = 16, hi: int = 96, nrhs: int = 1):
+    """Independent weighted grid Laplacians of uneven size: sides nx, ny drawn
+    uniformly from {lo..hi}, then each system's weights (``weighted_grid``)
+    and right-hand side uniform in [-1, 1], system by system."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(lo, hi + 1, size=(nsys, 2))
+    out = []
+    for q in range(nsys):
+        p = weighted_grid(int(sides[q, 0]), int(sides[q, 1]), rng)
+        p.b = np.asfortranarray(rng.uniform(-1.0, 1.0, (nrhs, p.n)).T)
+        out.append(p)
+    return out
 
 
 def make_config(i: int, seed: int | None = None) -> Problem:

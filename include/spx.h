@@ -73,6 +73,12 @@ typedef struct spx_options {
                                * 2 for SPX_FP64, 10 for SPX_FP32_IR */
     double ir_tol;            /* componentwise backward error target (1e-14) */
     int32_t trace;            /* 1: record a per-work-item trace of each factorization (0) */
+    int32_t graph;            /* 1: capture the device work of a factorization in a HIP graph
+                               * once and replay it for every later factorization (0) */
+    int32_t tune;             /* 1: on the first factorization, time one run per work
+                               * decomposition (update tile shape, priority policy) and
+                               * keep the fastest (0: 256x64 tiles, every chain first) */
+    int32_t tile;             /* update tile shape without tuning: 0 = 256 x 64, 1 = 128 x 128 (0) */
 } spx_options;
 
 typedef struct spx_info {
@@ -92,6 +98,10 @@ typedef struct spx_info {
     double logdet;            /* log det A after a factorization */
     double factor_kernel_ms;  /* last factorization: scheduler kernel time (HIP events) */
     double assemble_ms;       /* last factorization: assembly kernel time */
+    int32_t tile_rows;        /* update tile in use: 256 x 64 or 128 x 128 */
+    int32_t tile_cols;
+    int32_t hp_policy;        /* 0: every elimination chain first; 1: only the upper levels */
+    int32_t nsys;             /* independent systems of the handle (spx_analyze_batch), 1 otherwise */
 } spx_info;
 
 typedef struct spx_solve_info {
@@ -138,6 +148,18 @@ void spx_default_options(spx_options* opt);
  * to the current HIP device).  Errors: SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE. */
 int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind,
                 const spx_options* opt, spx_handle** out);
+
+/* Batch of independent systems A_q x_q = b_q (q < nsys, sizes n[q], patterns
+ * colptr[q] / rowind[q] as for spx_analyze) analysed as one block-diagonal
+ * system: every later call on the handle treats them together, so one
+ * factorization launch (one persistent scheduler kernel; with the graph
+ * option, one graph replay) factors all of them.  Values and right-hand
+ * sides are the systems' arrays concatenated in order (system q's values
+ * follow those of systems < q; its unknowns are rows off_q .. off_q + n[q] - 1
+ * with off_q = n[0] + ... + n[q-1]).  opt->user_perm must be NULL.
+ * Errors: as spx_analyze. */
+int spx_analyze_batch(int32_t nsys, const int32_t* n, const int64_t* const* colptr,
+                      const int32_t* const* rowind, const spx_options* opt, spx_handle** out);
 
 /* Numerical factorization (Section III and V: diagonal factorization,
  * panel triangular solve, sparse-GEMM updates scattered into the facing

@@ -149,6 +149,15 @@ struct spx_handle {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // work decomposition (chosen by the tuner when the tune option is on)
+    int32_t tile_rows = 256, tile_cols = 64;   // update tile: 256 x 64, or 128 x 128
+    int32_t hp_policy = 0;                     // 0: every chain high priority; 1: only levels of <= 32 blocks
+    int32_t nsys = 1;                          // independent systems (spx_analyze_batch)
+    bool tuned = false;
+    // captured factorization sequence (graph option): assembly + queue set-up,
+    // and the scheduler kernel (two graphs, timed by events between them)
+    hipGraph_t fgraph[2] = {nullptr, nullptr};
+    hipGraphExec_t fgraph_exec[2] = {nullptr, nullptr};
     int device = 0;
     int grid = 0;
     int64_t timeout_ticks = 0;
@@ -159,7 +168,18 @@ struct spx_handle {
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
         drop_graph();
+        drop_fgraph();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+
+    void drop_fgraph()
+    {
+        for (int i = 0; i < 2; ++i) {
+            if (fgraph_exec[i]) (void)hipGraphExecDestroy(fgraph_exec[i]);
+            if (fgraph[i]) (void)hipGraphDestroy(fgraph[i]);
+            fgraph_exec[i] = nullptr;
+            fgraph[i] = nullptr;
+        }
     }
 
     void drop_graph()
@@ -237,9 +257,18 @@ void build_tasks(spx_handle* h)
     const int32_t nc = P.ncblk;
     constexpr int kTrsmRows = 64;
     // high priority: FACT, the TRSM tiles and the update tiles into the first
-    // facing block (the elimination chain) of every block; the other update
-    // tiles form the bulk in the normal queue
+    // facing block (the elimination chain) of every block, or (policy 1) of
+    // the blocks in dependency levels of at most 32 blocks only; the other
+    // update tiles form the bulk in the normal queue
     std::vector<int32_t> hp(nc, 1);
+    if (h->hp_policy == 1) {
+        std::vector<int32_t> lvl(nc, 0), per_level(static_cast<size_t>(nc) + 1, 0);
+        for (int32_t k = 0; k < nc; ++k)
+            for (int32_t q = P.uptr[k]; q < P.uptr[k + 1]; ++q)
+                lvl[P.utgt[q]] = std::max(lvl[P.utgt[q]], lvl[k] + 1);
+        for (int32_t k = 0; k < nc; ++k) ++per_level[lvl[k]];
+        for (int32_t k = 0; k < nc; ++k) hp[k] = per_level[lvl[k]] <= 32 ? 1 : 0;
+    }
     std::vector<int4> desc;
     desc.reserve(static_cast<size_t>(nc) * 2);
     std::vector<int32_t> tf(nc), tc(nc), uf(nc), uh(nc), ucnt(nc), dep(nc, 0);
@@ -289,7 +318,7 @@ void build_tasks(spx_handle* h)
             }
             const int32_t mbase = static_cast<int32_t>(moff - rs);
             const int32_t nf = re - rs;
-            const int32_t tr = 256, tcl = 64;
+            const int32_t tr = h->tile_rows, tcl = h->tile_cols;
             for (int32_t r0 = rs; r0 < ld; r0 += tr) {
                 const int32_t mr = std::min(tr, ld - r0);
                 for (int32_t c0 = rs; c0 < re; c0 += tcl) {
@@ -469,6 +498,100 @@ void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
     }
 }
 
+// The device work of one factorization on stream s, in two parts: (0)
+// panels zeroed, values assembled (and gathered for the residual), queues
+// initialised; (1) the scheduler kernel.
+SchedArgs sched_args(spx_handle* h);
+
+void factor_part(spx_handle* h, int part, hipStream_t s)
+{
+    const Plan& P = h->plan;
+    const bool f32 = h->f32();
+    const SchedArgs a = sched_args(h);
+    if (part == 1) {
+        if (h->total > 0) HIPCHK(launch_sched(a, f32, h->grid, s));
+        return;
+    }
+    const int64_t nsym = P.rptr.empty() ? 0 : P.rptr.back();
+    if (f32) HIPCHK(launch_fill_f32(h->panels_f.p, P.panel_entries, 0.0f, s));
+    else HIPCHK(launch_fill_f64(h->panels.p, P.panel_entries, 0.0, s));
+    HIPCHK(launch_assemble(h->panel_ptr(), f32, h->amap.p, h->vals.p, h->nnz, s));
+    HIPCHK(launch_gather(h->rv.p, h->vals.p, h->rval.p, nsym, s));
+    HIPCHK(launch_sched_init(a, h->ready.p, h->nready, h->nready_hp, h->fact_dep0.p, P.ncblk, s));
+}
+
+SchedArgs sched_args(spx_handle* h)
+{
+    SchedArgs a;
+    a.pl = h->devplan();
+    a.panels = h->panel_ptr();
+    a.dinv = h->dinv_ptr();
+    a.desc = h->desc.p;
+    a.rmap = h->rmap.p;
+    a.hp_total = h->hp_total;
+    a.total_normal = h->total_normal;
+    a.trsm_first = h->trsm_first.p;
+    a.trsm_count = h->trsm_count.p;
+    a.upd_first = h->upd_first.p;
+    a.upd_hp = h->upd_hp.p;
+    a.upd_count = h->upd_count.p;
+    a.hp_cblk = h->hp_cblk.p;
+    a.fact_dep = h->fact_dep.p;
+    a.trsm_left = h->trsm_left.p;
+    a.queue = h->queue.p;
+    a.qhead = h->qctr.p;
+    a.qtail = h->qctr.p + 1;
+    a.hp_queue = h->hp_queue.p;
+    a.hp_head = h->qctr.p + 2;
+    a.hp_tail = h->qctr.p + 3;
+    a.status = h->status.p;
+    a.timeout_ticks = h->timeout_ticks;
+    a.trace = h->opt.trace ? h->trace.p : nullptr;
+    return a;
+}
+
+// One factorization of the values in h->vals: eagerly, or (graph option) by
+// replaying the captured sequence (captured on first use and after any
+// change of the work decomposition); then the status read-back.
+void run_factorization(spx_handle* h, hipStream_t s)
+{
+    if (h->opt.trace) h->trace.alloc(static_cast<size_t>(h->total) * 4);
+    if (h->opt.graph && !h->fgraph_exec[0]) {
+        if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        for (int part = 0; part < 2; ++part) {
+            HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            factor_part(h, part, h->cap_stream);
+            HIPCHK(hipStreamEndCapture(h->cap_stream, &h->fgraph[part]));
+            HIPCHK(hipGraphInstantiate(&h->fgraph_exec[part], h->fgraph[part], nullptr, nullptr, 0));
+        }
+    }
+    for (int part = 0; part < 2; ++part) {
+        HIPCHK(hipEventRecord(h->ev[part], s));
+        if (h->opt.graph) HIPCHK(hipGraphLaunch(h->fgraph_exec[part], s));
+        else factor_part(h, part, s);
+    }
+    HIPCHK(hipEventRecord(h->ev[2], s));
+    const Plan& P = h->plan;
+    int32_t st[4] = {INT_MAX, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(st, h->status.p, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms0 = 0.f, ms1 = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms0, h->ev[0], h->ev[1]));
+    HIPCHK(hipEventElapsedTime(&ms1, h->ev[1], h->ev[2]));
+    h->assemble_ms = ms0;
+    h->factor_ms = ms1;
+    if (h->total > 0 && (st[1] != 0 || st[2] != h->total)) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "device scheduler stopped early (%d of %d items, abort=%d)", st[2], h->total,
+                      st[1]);
+        throw DeviceError(buf);
+    }
+    if (st[0] != INT_MAX) {
+        h->fail_col = (st[0] >= 0 && st[0] < h->n) ? P.perm[st[0]] : st[0];
+        throw StatusError(SPX_ENOTPD, "pivot not positive at column " + std::to_string(h->fail_col));
+    }
+}
+
 double pairwise_sum(const double* v, int64_t n)
 {
     if (n <= 8) {
@@ -496,6 +619,9 @@ void spx_default_options(spx_options* o)
     o->ir_max_iter = -1;
     o->ir_tol = 1e-14;
     o->trace = 0;
+    o->graph = 0;
+    o->tune = 0;
+    o->tile = 0;
 }
 
 int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const spx_options* opt, spx_handle** out)
@@ -516,6 +642,9 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
             throw InvalidArgument("unsupported precision");
         if (h->opt.ir_max_iter < -1) throw InvalidArgument("ir_max_iter must be >= 0, or -1 for the default");
         if (h->opt.ir_max_iter == -1) h->opt.ir_max_iter = h->opt.precision == SPX_FP32_IR ? 10 : 2;
+        if (h->opt.tile != 0 && h->opt.tile != 1) throw InvalidArgument("tile must be 0 or 1");
+        h->tile_rows = h->opt.tile == 1 ? 128 : 256;
+        h->tile_cols = h->opt.tile == 1 ? 128 : 64;
         Options o;
         o.leaf_size = h->opt.leaf_size;
         o.amalg_pct = h->opt.amalg_pct;
@@ -538,6 +667,47 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
     }
     *out = h;
     return SPX_OK;
+}
+
+int spx_analyze_batch(int32_t nsys, const int32_t* n, const int64_t* const* colptr, const int32_t* const* rowind,
+                      const spx_options* opt, spx_handle** out)
+{
+    if (!out) return SPX_EINVAL;
+    *out = nullptr;
+    if (nsys <= 0 || !n || !colptr || !rowind || (opt && opt->user_perm)) return SPX_EINVAL;
+    // block-diagonal pattern: system s occupies rows and columns
+    // [off_s, off_s + n_s) and entries [colptr_all[off_s], ...)
+    int64_t ntot = 0, nnz = 0;
+    for (int32_t q = 0; q < nsys; ++q) {
+        if (n[q] < 0 || (n[q] > 0 && (!colptr[q] || !rowind[q]))) return SPX_EINVAL;
+        ntot += n[q];
+        nnz += n[q] > 0 ? colptr[q][n[q]] : 0;
+    }
+    if (ntot > INT32_MAX) return SPX_EINVAL;
+    std::vector<int64_t> cp;
+    std::vector<int32_t> ri;
+    try {
+        cp.reserve(static_cast<size_t>(ntot) + 1);
+        ri.reserve(static_cast<size_t>(nnz));
+    } catch (...) {
+        return SPX_ENOMEM;
+    }
+    cp.push_back(0);
+    int32_t off = 0;
+    for (int32_t q = 0; q < nsys; ++q) {
+        for (int32_t j = 0; j < n[q]; ++j) {
+            for (int64_t p = colptr[q][j]; p < colptr[q][j + 1]; ++p) {
+                const int32_t r = rowind[q][p];
+                if (r < 0 || r >= n[q]) return SPX_EINVAL;
+                ri.push_back(off + r);
+            }
+            cp.push_back(static_cast<int64_t>(ri.size()));
+        }
+        off += n[q];
+    }
+    const int rc = spx_analyze(static_cast<int32_t>(ntot), cp.data(), ri.data(), opt, out);
+    if (rc == SPX_OK) (*out)->nsys = nsys;
+    return rc;
 }
 
 int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device, void* hip_stream)
@@ -568,64 +738,37 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
                 HIPCHK(launch_fill_f64(h->dinv.p, h->dinv_size, 0.0, s));
             }
         }
-        HIPCHK(hipEventRecord(h->ev[0], s));
-        if (f32) HIPCHK(launch_fill_f32(h->panels_f.p, P.panel_entries, 0.0f, s));
-        else HIPCHK(launch_fill_f64(h->panels.p, P.panel_entries, 0.0, s));
-        HIPCHK(launch_assemble(h->panel_ptr(), f32, h->amap.p, h->vals.p, h->nnz, s));
         const int64_t nsym = P.rptr.empty() ? 0 : P.rptr.back();
         h->rv.alloc(static_cast<size_t>(nsym));
-        HIPCHK(launch_gather(h->rv.p, h->vals.p, h->rval.p, nsym, s));
-        SchedArgs a;
-        a.pl = h->devplan();
-        a.panels = h->panel_ptr();
-        a.dinv = h->dinv_ptr();
-        a.desc = h->desc.p;
-        a.rmap = h->rmap.p;
-        a.hp_total = h->hp_total;
-        a.total_normal = h->total_normal;
-        a.trsm_first = h->trsm_first.p;
-        a.trsm_count = h->trsm_count.p;
-        a.upd_first = h->upd_first.p;
-        a.upd_hp = h->upd_hp.p;
-        a.upd_count = h->upd_count.p;
-        a.hp_cblk = h->hp_cblk.p;
-        a.fact_dep = h->fact_dep.p;
-        a.trsm_left = h->trsm_left.p;
-        a.queue = h->queue.p;
-        a.qhead = h->qctr.p;
-        a.qtail = h->qctr.p + 1;
-        a.hp_queue = h->hp_queue.p;
-        a.hp_head = h->qctr.p + 2;
-        a.hp_tail = h->qctr.p + 3;
-        a.status = h->status.p;
-        a.timeout_ticks = h->timeout_ticks;
-        a.trace = nullptr;
-        if (h->opt.trace) {
-            h->trace.alloc(static_cast<size_t>(h->total) * 4);
-            a.trace = h->trace.p;
+        if (h->opt.tune && !h->tuned) {
+            // autotuner: time one factorization per work decomposition on these
+            // values and keep the fastest (update tile shape, priority policy)
+            struct Cand {
+                int32_t rows, cols, policy;
+            };
+            const Cand cand[] = {{256, 64, 0}, {128, 128, 0}, {256, 64, 1}, {128, 128, 1}};
+            double best = INFINITY;
+            Cand pick = cand[0];
+            for (const Cand& c : cand) {
+                h->tile_rows = c.rows;
+                h->tile_cols = c.cols;
+                h->hp_policy = c.policy;
+                build_tasks(h);
+                h->drop_fgraph();
+                run_factorization(h, s);   // throws on breakdown, like the real run
+                if (h->factor_ms < best) {
+                    best = h->factor_ms;
+                    pick = c;
+                }
+            }
+            h->tile_rows = pick.rows;
+            h->tile_cols = pick.cols;
+            h->hp_policy = pick.policy;
+            build_tasks(h);
+            h->drop_fgraph();
+            h->tuned = true;
         }
-        HIPCHK(launch_sched_init(a, h->ready.p, h->nready, h->nready_hp, h->fact_dep0.p, P.ncblk, s));
-        HIPCHK(hipEventRecord(h->ev[1], s));
-        if (h->total > 0) HIPCHK(launch_sched(a, f32, h->grid, s));
-        HIPCHK(hipEventRecord(h->ev[2], s));
-        int32_t st[4] = {INT_MAX, 0, 0, 0};
-        HIPCHK(hipMemcpyAsync(st, h->status.p, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        float ms0 = 0.f, ms1 = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms0, h->ev[0], h->ev[1]));
-        HIPCHK(hipEventElapsedTime(&ms1, h->ev[1], h->ev[2]));
-        h->assemble_ms = ms0;
-        h->factor_ms = ms1;
-        if (h->total > 0 && (st[1] != 0 || st[2] != h->total)) {
-            char buf[160];
-            std::snprintf(buf, sizeof buf, "device scheduler stopped early (%d of %d items, abort=%d)", st[2], h->total,
-                          st[1]);
-            throw DeviceError(buf);
-        }
-        if (st[0] != INT_MAX) {
-            h->fail_col = (st[0] >= 0 && st[0] < h->n) ? P.perm[st[0]] : st[0];
-            throw StatusError(SPX_ENOTPD, "pivot not positive at column " + std::to_string(h->fail_col));
-        }
+        run_factorization(h, s);
         h->factorized = true;
         return SPX_OK;
     });
@@ -767,6 +910,10 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
         o.logdet = h->logdet_valid ? h->logdet : 0.0;
         o.factor_kernel_ms = h->factor_ms;
         o.assemble_ms = h->assemble_ms;
+        o.tile_rows = h->tile_rows;
+        o.tile_cols = h->tile_cols;
+        o.hp_policy = h->hp_policy;
+        o.nsys = h->nsys;
         *info = o;
         return SPX_OK;
     });

@@ -534,8 +534,9 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // width of k), C_j[rmap(row), rmap(col)] -= W on the lower triangle of j.
 // rmap (precomputed from the symbolic structure) gives, for every panel row
 // of k from the first block facing j on, its row inside panel j; for facing
-// rows that is also the column of j.  ncols <= 64, mrows <= 256: the four
-// waves cover 64 rows each.
+// rows that is also the column of j.  Two tile shapes: ncols <= 64 and
+// mrows <= 256 (the four waves cover 64 rows each), or 64 < ncols <= 128 and
+// mrows <= 128 (the waves form a 2x2 grid of 64x64 wave tiles).
 template <class T>
 __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos, int* cpos)
 {
@@ -550,14 +551,16 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
     if (tid < mrows) rpos[tid] = a.rmap[mbase + row0 + tid];
     if (tid < ncols) cpos[tid] = a.rmap[mbase + col0 + tid];
     __syncthreads();
-    const int r0 = 64 * wave;
-    const int mv = min(64, mrows - r0);
-    if (mv > 0) {
+    const bool square = ncols > 64;
+    const int r0 = square ? 64 * (wave & 1) : 64 * wave;
+    const int c0 = square ? 64 * (wave >> 1) : 0;
+    const int mv = min(64, mrows - r0), nv = min(64, ncols - c0);
+    if (mv > 0 && nv > 0) {
         typename MM<T>::acc acc[4][4];
         zero_acc(acc);
-        wave_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0, 1, ld), make_gop(A, ld * w, col0, 1, ld), w);
-        wave_store<T>(acc, mv, ncols, [&](int r, int c, T v) {
-            const int tr = rpos[r0 + r], tc = cpos[c];
+        wave_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0, 1, ld), make_gop(A, ld * w, col0 + c0, 1, ld), w);
+        wave_store<T>(acc, mv, nv, [&](int r, int c, T v) {
+            const int tr = rpos[r0 + r], tc = cpos[c0 + c];
             if (tr >= tc) __hip_atomic_fetch_add(Cg + (int64_t)tc * ldj + tr, -v, __ATOMIC_RELAXED, AGENT);
         });
     }

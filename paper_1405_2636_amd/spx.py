@@ -41,7 +41,8 @@ class NotConverged(SpxError):
 class Options(C.Structure):
     _fields_ = [("method", C.c_int32), ("leaf_size", C.c_int32), ("amalg_pct", C.c_int32),
                 ("split_width", C.c_int32), ("user_perm", C.c_void_p), ("precision", C.c_int32),
-                ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double), ("trace", C.c_int32)]
+                ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double), ("trace", C.c_int32),
+                ("graph", C.c_int32), ("tune", C.c_int32), ("tile", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -49,7 +50,8 @@ class Info(C.Structure):
                 ("nnz_a", C.c_int64), ("nnz_l", C.c_int64), ("nnz_l_stored", C.c_int64),
                 ("panel_entries", C.c_int64), ("flops_alg", C.c_double), ("flops_exec", C.c_double),
                 ("ntasks", C.c_int64), ("fail_col", C.c_int32), ("factorized", C.c_int32),
-                ("logdet", C.c_double), ("factor_kernel_ms", C.c_double), ("assemble_ms", C.c_double)]
+                ("logdet", C.c_double), ("factor_kernel_ms", C.c_double), ("assemble_ms", C.c_double),
+                ("tile_rows", C.c_int32), ("tile_cols", C.c_int32), ("hp_policy", C.c_int32), ("nsys", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -71,7 +73,7 @@ class SymView(C.Structure):
 
 EXPORTED = ["spx_default_options", "spx_analyze", "spx_factorize", "spx_solve", "spx_get_info",
             "spx_export_symbolic", "spx_copy_factor", "spx_get_trace", "spx_destroy", "spx_strerror",
-            "spx_last_error", "spx_values_grad"]
+            "spx_last_error", "spx_values_grad", "spx_analyze_batch"]
 
 _lib = None
 
@@ -101,6 +103,8 @@ def load_library():
     L.spx_copy_factor.argtypes = [vp, vp, C.c_int32, vp]
     L.spx_get_trace.restype = C.c_int64
     L.spx_get_trace.argtypes = [vp, vp, C.c_int64, vp]
+    L.spx_analyze_batch.restype = C.c_int
+    L.spx_analyze_batch.argtypes = [C.c_int32, vp, vp, vp, vp, vp]
     L.spx_values_grad.restype = C.c_int
     L.spx_values_grad.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, vp, vp]
     L.spx_destroy.restype = None
@@ -133,13 +137,24 @@ class Solver:
     """
 
     def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,
-                 precision="fp64", ir_max_iter=None, ir_tol=1e-14, trace=False):
+                 precision="fp64", ir_max_iter=None, ir_tol=1e-14, trace=False, graph=False, tune=False, tile=0):
         L = load_library()
         self._lib = L
         self.n = int(n)
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int32)
         self.nnz = int(self._colptr[-1]) if len(self._colptr) else 0
+        self.sizes = [self.n]
+        opt, up = self._options(L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol,
+                                trace, graph, tune, tile)
+        h = C.c_void_p()
+        rc = L.spx_analyze(self.n, self._colptr.ctypes.data, self._rowind.ctypes.data, C.byref(opt), C.byref(h))
+        if rc != SPX_OK:
+            raise SpxError(rc, "analyze failed: %s" % L.spx_last_error(None).decode())
+        self._h = h
+
+    def _options(self, L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol, trace,
+                 graph, tune, tile=0):
         opt = Options()
         L.spx_default_options(C.byref(opt))
         opt.leaf_size, opt.amalg_pct, opt.split_width = leaf_size, amalg_pct, split_width
@@ -150,15 +165,50 @@ class Solver:
         opt.ir_max_iter = -1 if ir_max_iter is None else int(ir_max_iter)
         opt.ir_tol = ir_tol
         opt.trace = 1 if trace else 0
+        opt.graph = 1 if graph else 0
+        opt.tune = 1 if tune else 0
+        opt.tile = int(tile)
         up = None
         if user_perm is not None:
             up = np.ascontiguousarray(user_perm, dtype=np.int32)
             opt.user_perm = up.ctypes.data
+        return opt, up
+
+    @classmethod
+    def batch(cls, systems, precision="fp64", ir_max_iter=None, ir_tol=1e-14, graph=True, tune=True, **kw):
+        """Independent systems [(n, colptr, rowind), ...] analysed, factored and
+        solved together (one factorization launch for all, spx_analyze_batch).
+        Values and right-hand sides are the systems' arrays concatenated in
+        order; ``split`` cuts a concatenated vector back into systems."""
+        self = cls.__new__(cls)
+        L = load_library()
+        self._lib = L
+        ns = np.array([int(s[0]) for s in systems], np.int32)
+        cps = [np.ascontiguousarray(s[1], dtype=np.int64) for s in systems]
+        ris = [np.ascontiguousarray(s[2], dtype=np.int32) for s in systems]
+        self.sizes = [int(v) for v in ns]
+        self.n = int(ns.sum())
+        self.nnz = int(sum(int(c[-1]) for c in cps))
+        self._keep = (cps, ris)
+        opt, _ = self._options(L, kw.get("leaf_size", 64), kw.get("amalg_pct", 12), kw.get("split_width", 256),
+                               None, precision, ir_max_iter, ir_tol, kw.get("trace", False), graph, tune)
+        cpp = (C.c_void_p * len(cps))(*[c.ctypes.data for c in cps])
+        rip = (C.c_void_p * len(ris))(*[r.ctypes.data for r in ris])
         h = C.c_void_p()
-        rc = L.spx_analyze(self.n, self._colptr.ctypes.data, self._rowind.ctypes.data, C.byref(opt), C.byref(h))
+        rc = L.spx_analyze_batch(len(systems), ns.ctypes.data, C.cast(cpp, C.c_void_p), C.cast(rip, C.c_void_p),
+                                 C.byref(opt), C.byref(h))
         if rc != SPX_OK:
-            raise SpxError(rc, "analyze failed: %s" % L.spx_last_error(None).decode())
+            raise SpxError(rc, "analyze_batch failed: %s" % L.spx_last_error(None).decode())
         self._h = h
+        return self
+
+    def split(self, v):
+        """A concatenated vector (last axis of length n) cut into the systems."""
+        out, o = [], 0
+        for m in self.sizes:
+            out.append(v[..., o:o + m])
+            o += m
+        return out
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -69,3 +69,29 @@ def test_config2_full_size(orc):
     p = make_config(2)
     sy = _compare(orc, p.n, p.colptr, p.rowind)
     assert sy["ncblk"] > 1000
+
+
+def _block_diagonal(problems):
+    import scipy.sparse as sp
+    mats = [sp.csc_matrix((p.values, p.rowind, p.colptr), shape=(p.n, p.n)) for p in problems]
+    A = sp.block_diag(mats, format="csc")
+    A.sort_indices()
+    return A.shape[0], A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data
+
+
+def test_batch_analysis_is_block_diagonal_analysis(orc):
+    # spx_analyze_batch: the systems' patterns placed on the diagonal, analysed
+    # as one system; bit-exact against the oracle's analysis of that pattern
+    from gen import grid_batch
+    from paper_1405_2636_amd import Solver
+    ps = grid_batch(12, seed=7, lo=5, hi=30)
+    n, cp, ri, _ = _block_diagonal(ps)
+    s = Solver.batch([(p.n, p.colptr, p.rowind) for p in ps], graph=False, tune=False)
+    assert s.n == n and s.nnz == cp[-1] and s.info()["nsys"] == 12
+    sy = s.symbolic()
+    o = orc.analyze(n, cp, ri)
+    for name in ARRAYS:
+        assert np.array_equal(sy[name], o.arrays[name]), name
+    # each system is a separate tree of the elimination forest
+    roots = np.sum(sy["etree"] < 0)
+    assert roots >= 12
