@@ -122,6 +122,7 @@ struct spx_handle {
     DevBuf<int64_t> rowg_off;
     // scheduler tables
     int32_t total = 0, nready = 0, nready_hp = 0, hp_total = 0, total_normal = 0;
+    int32_t ndesc = 0, nsmall = 0;   // descriptors (queued items + update tiles of fused blocks); fused blocks
     DevBuf<int4> desc;
     DevBuf<int32_t> rmap;
     DevBuf<int32_t> trsm_first, trsm_count, upd_first, upd_hp, upd_count, hp_cblk, fact_dep0, fact_dep, trsm_left,
@@ -269,12 +270,48 @@ void build_tasks(spx_handle* h)
         for (int32_t k = 0; k < nc; ++k) ++per_level[lvl[k]];
         for (int32_t k = 0; k < nc; ++k) hp[k] = per_level[lvl[k]] <= 32 ? 1 : 0;
     }
+    const int32_t tr = h->tile_rows, tcl = h->tile_cols;
+    // update tiles of source k into target group [b, b2) (blocks facing one cblk)
+    auto for_tiles = [&](int32_t k, int32_t b, int32_t b2, auto&& fn) {
+        const int32_t ld = P.stride[k];
+        const int32_t rs = P.coefind[b];
+        const int32_t re = P.coefind[b2 - 1] + (P.lrow[b2 - 1] - P.frow[b2 - 1] + 1);
+        for (int32_t r0 = rs; r0 < ld; r0 += tr) {
+            const int32_t mr = std::min(tr, ld - r0);
+            for (int32_t c0 = rs; c0 < re; c0 += tcl) {
+                if (r0 + mr - 1 < c0) continue;   // strictly above the diagonal of j
+                fn(r0, mr, c0, std::min(tcl, re - c0));
+            }
+        }
+    };
+    // fused small blocks: width <= 32, at most 128 panel rows, tables within
+    // the bounds of the item's LDS
+    std::vector<char> small(nc, 0);
+    int32_t nsmall = 0;
+    if (h->opt.fuse_small) {
+        for (int32_t k = 0; k < nc; ++k) {
+            const int32_t w = P.lcol[k] - P.fcol[k] + 1, ld = P.stride[k];
+            if (w > kNB || ld > kSmallRows) continue;
+            int64_t ntiles = 0, nmap = 0;
+            for (int32_t b = P.bptr[k] + 1; b < P.bptr[k + 1];) {
+                int32_t b2 = b;
+                while (b2 < P.bptr[k + 1] && P.fcblk[b2] == P.fcblk[b]) ++b2;
+                nmap += ld - P.coefind[b];
+                for_tiles(k, b, b2, [&](int32_t, int32_t, int32_t, int32_t) { ++ntiles; });
+                b = b2;
+            }
+            if (ntiles <= kSmallMaxUpd && nmap <= kSmallMap) {
+                small[k] = 1;
+                ++nsmall;
+            }
+        }
+    }
     std::vector<int4> desc;
     desc.reserve(static_cast<size_t>(nc) * 2);
     std::vector<int32_t> tf(nc), tc(nc), uf(nc), uh(nc), ucnt(nc), dep(nc, 0);
     std::vector<int32_t> rmap;
     for (int32_t k = 0; k < nc; ++k) {
-        desc.push_back(int4{kFact, k, 0, 0});
+        desc.push_back(int4{small[k] ? kSmall : kFact, k, 0, 0});
         desc.push_back(int4{0, 0, 0, 0});
     }
     int32_t id = nc;
@@ -282,7 +319,7 @@ void build_tasks(spx_handle* h)
     for (int32_t k = 0; k < nc; ++k) {
         const int32_t w = P.lcol[k] - P.fcol[k] + 1, ld = P.stride[k];
         tf[k] = id;
-        for (int32_t r = w; r < ld; r += kTrsmRows) {
+        for (int32_t r = w; r < ld && !small[k]; r += kTrsmRows) {
             desc.push_back(int4{kTrsm, k, r, std::min(kTrsmRows, ld - r)});
             desc.push_back(int4{0, 0, 0, 0});
             ++id;
@@ -290,17 +327,17 @@ void build_tasks(spx_handle* h)
         tc[k] = id - tf[k];
         ntrsm += tc[k];
     }
-    int64_t nhp_upd = 0;
+    int64_t nhp_upd = 0, nfused_upd = 0;
     std::vector<int32_t> grow;
     for (int32_t k = 0; k < nc; ++k) {
-        const int32_t w = P.lcol[k] - P.fcol[k] + 1, ld = P.stride[k];
+        const int32_t ld = P.stride[k];
         // global row of every panel row of k
         grow.assign(static_cast<size_t>(ld), 0);
         for (int32_t b = P.bptr[k]; b < P.bptr[k + 1]; ++b)
             for (int32_t r = P.frow[b]; r <= P.lrow[b]; ++r) grow[P.coefind[b] + (r - P.frow[b])] = r;
-        (void)w;
         uf[k] = id;
         uh[k] = 0;
+        const int64_t mstart = static_cast<int64_t>(rmap.size());
         bool first_pair = true;
         for (int32_t b = P.bptr[k] + 1; b < P.bptr[k + 1];) {
             const int32_t j = P.fcblk[b];
@@ -317,27 +354,27 @@ void build_tasks(spx_handle* h)
                 rmap.push_back(pos);
             }
             const int32_t mbase = static_cast<int32_t>(moff - rs);
-            const int32_t nf = re - rs;
-            const int32_t tr = h->tile_rows, tcl = h->tile_cols;
-            for (int32_t r0 = rs; r0 < ld; r0 += tr) {
-                const int32_t mr = std::min(tr, ld - r0);
-                for (int32_t c0 = rs; c0 < re; c0 += tcl) {
-                    if (r0 + mr - 1 < c0) continue;   // strictly above the diagonal of j
-                    const int32_t ncl = std::min(tcl, re - c0);
-                    desc.push_back(int4{kUpdate, k, j, r0});
-                    desc.push_back(int4{mr, c0, ncl, mbase});
-                    ++dep[j];
-                    ++id;
-                    if (first_pair && hp[k]) ++uh[k];
-                }
-            }
+            for_tiles(k, b, b2, [&](int32_t r0, int32_t mr, int32_t c0, int32_t ncl) {
+                desc.push_back(int4{kUpdate, k, j, r0});
+                desc.push_back(int4{mr, c0, ncl, mbase});
+                ++dep[j];
+                ++id;
+                if (first_pair && hp[k] && !small[k]) ++uh[k];
+            });
             first_pair = false;
             b = b2;
         }
         ucnt[k] = id - uf[k];
         nhp_upd += uh[k];
+        if (small[k]) {
+            desc[2 * static_cast<size_t>(k) + 1] =
+                int4{uf[k], ucnt[k], static_cast<int32_t>(mstart), static_cast<int32_t>(rmap.size() - mstart)};
+            nfused_upd += ucnt[k];
+        }
     }
-    h->total = id;
+    h->ndesc = id;
+    h->nsmall = nsmall;
+    h->total = static_cast<int32_t>(id - nfused_upd);   // items that pass through the queues
     int64_t hp_items = nhp_upd;
     for (int32_t k = 0; k < nc; ++k)
         if (hp[k]) hp_items += 1 + tc[k];
@@ -364,8 +401,8 @@ void build_tasks(spx_handle* h)
     h->queue.alloc(static_cast<size_t>(h->total_normal));
     h->hp_queue.alloc(static_cast<size_t>(h->hp_total));
     h->ready.upload(ready);
-    h->qctr.alloc(4);
-    h->status.alloc(4);
+    h->qctr.alloc(4 * kCtrStride);
+    h->status.alloc(kStatusWords);
 }
 
 // Dependency levels for the sweeps: level(k) = 1 + max level of the cblks
@@ -540,10 +577,10 @@ SchedArgs sched_args(spx_handle* h)
     a.trsm_left = h->trsm_left.p;
     a.queue = h->queue.p;
     a.qhead = h->qctr.p;
-    a.qtail = h->qctr.p + 1;
+    a.qtail = h->qctr.p + kCtrStride;
     a.hp_queue = h->hp_queue.p;
-    a.hp_head = h->qctr.p + 2;
-    a.hp_tail = h->qctr.p + 3;
+    a.hp_head = h->qctr.p + 2 * kCtrStride;
+    a.hp_tail = h->qctr.p + 3 * kCtrStride;
     a.status = h->status.p;
     a.timeout_ticks = h->timeout_ticks;
     a.trace = h->opt.trace ? h->trace.p : nullptr;
@@ -555,7 +592,10 @@ SchedArgs sched_args(spx_handle* h)
 // change of the work decomposition); then the status read-back.
 void run_factorization(spx_handle* h, hipStream_t s)
 {
-    if (h->opt.trace) h->trace.alloc(static_cast<size_t>(h->total) * 4);
+    if (h->opt.trace) {
+        h->trace.alloc(static_cast<size_t>(h->ndesc) * 4);
+        HIPCHK(hipMemsetAsync(h->trace.p, 0, static_cast<size_t>(h->ndesc) * 4 * sizeof(int64_t), s));
+    }
     if (h->opt.graph && !h->fgraph_exec[0]) {
         if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         for (int part = 0; part < 2; ++part) {
@@ -572,9 +612,10 @@ void run_factorization(spx_handle* h, hipStream_t s)
     }
     HIPCHK(hipEventRecord(h->ev[2], s));
     const Plan& P = h->plan;
-    int32_t st[4] = {INT_MAX, 0, 0, 0};
-    HIPCHK(hipMemcpyAsync(st, h->status.p, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t sw[kStatusWords];
+    HIPCHK(hipMemcpyAsync(sw, h->status.p, sizeof sw, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    const int32_t st[3] = {sw[kStFail], sw[kStAbort], sw[kStDone]};
     float ms0 = 0.f, ms1 = 0.f;
     HIPCHK(hipEventElapsedTime(&ms0, h->ev[0], h->ev[1]));
     HIPCHK(hipEventElapsedTime(&ms1, h->ev[1], h->ev[2]));
@@ -622,6 +663,7 @@ void spx_default_options(spx_options* o)
     o->graph = 0;
     o->tune = 0;
     o->tile = 0;
+    o->fuse_small = 1;
 }
 
 int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const spx_options* opt, spx_handle** out)
@@ -904,7 +946,9 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
         o.panel_entries = P.panel_entries;
         o.flops_alg = P.flops_alg;
         o.flops_exec = P.flops_exec;
-        o.ntasks = h->total;
+        o.ntasks = h->ndesc;
+        o.nqueued = h->total;
+        o.nsmall = h->nsmall;
         o.fail_col = h->fail_col;
         o.factorized = h->factorized ? 1 : 0;
         o.logdet = h->logdet_valid ? h->logdet : 0.0;
@@ -980,19 +1024,19 @@ int64_t spx_get_trace(spx_handle* h, int64_t* dst, int64_t cap, int32_t* kinds)
     if (!h) return SPX_EINVAL;
     return guarded(h, [&]() -> int {
         if (!h->opt.trace || !h->trace.p) throw StatusError(SPX_ESTATE, "trace option off or no factorization yet");
-        if (cap < h->total) throw InvalidArgument("trace buffer too small");
-        HIPCHK(hipMemcpy(dst, h->trace.p, static_cast<size_t>(h->total) * 4 * sizeof(int64_t), hipMemcpyDeviceToHost));
+        if (cap < h->ndesc) throw InvalidArgument("trace buffer too small");
+        HIPCHK(hipMemcpy(dst, h->trace.p, static_cast<size_t>(h->ndesc) * 4 * sizeof(int64_t), hipMemcpyDeviceToHost));
         if (kinds) {
-            std::vector<int4> d(static_cast<size_t>(h->total) * 2);
+            std::vector<int4> d(static_cast<size_t>(h->ndesc) * 2);
             HIPCHK(hipMemcpy(d.data(), h->desc.p, d.size() * sizeof(int4), hipMemcpyDeviceToHost));
-            for (int32_t i = 0; i < h->total; ++i) {
+            for (int32_t i = 0; i < h->ndesc; ++i) {
                 kinds[4 * i + 0] = d[2 * i].x;   // kind
                 kinds[4 * i + 1] = d[2 * i].y;   // source cblk
                 kinds[4 * i + 2] = d[2 * i].x == kUpdate ? d[2 * i].z : d[2 * i].y;   // target cblk
                 kinds[4 * i + 3] = d[2 * i].x == kUpdate ? d[2 * i + 1].y * d[2 * i + 1].z : d[2 * i].w;
             }
         }
-        return h->total;
+        return h->ndesc;
     });
 }
 

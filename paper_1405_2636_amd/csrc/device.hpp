@@ -21,13 +21,16 @@ struct DevPlan {
 };
 
 // Work-item kinds of the device scheduler.
-enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2 };
+enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2, kSmall = 3 };
 
 // Two int4 per item: {kind, k, a, b}, {c, d, e, f}
 //   kFact:   k
 //   kTrsm:   k, row0 = first panel row, nrows (<= 64)
 //   kUpdate: k (source), j (target), row0 (first source panel row);
 //            mrows, col0 (first facing panel row), ncols, mbase (row-map base)
+//   kSmall:  k; first update descriptor of k, their count, first row-map
+//            entry of k, row-map entries of k (the update descriptors of a
+//            fused block are carried out by its kSmall item, never queued)
 struct SchedArgs {
     DevPlan pl;
     void* panels;            // double, or float in the FP32 refinement mode
@@ -50,7 +53,7 @@ struct SchedArgs {
     int32_t* hp_queue;
     int32_t* hp_head;
     int32_t* hp_tail;
-    int32_t* status;        // [0] smallest failing column, [1] abort flag, [2] items done
+    int32_t* status;        // [kStFail] smallest failing column, [kStAbort] abort flag, [kStDone] items done
     int64_t timeout_ticks;  // wall-clock ticks a worker may wait for work
     int64_t* trace;         // optional: 4 words per item {claimed, started, finished, hw id}
 };
@@ -70,6 +73,20 @@ struct SweepArgs {
     int32_t n;
     int32_t nrhs;
 };
+
+// Scheduler counters and status words sit 256 bytes apart: every worker
+// polls the queue heads and the abort flag, and a shared line would put the
+// polls in the way of the claims.
+constexpr int kCtrStride = 64;                 // int32 words between counters
+constexpr int kStFail = 0, kStAbort = kCtrStride, kStDone = 2 * kCtrStride;
+constexpr int kStatusWords = 3 * kCtrStride;
+
+// Column blocks factored as one fused item: width <= kNB, at most
+// kSmallRows panel rows, at most kSmallMaxUpd update tiles and kSmallMap
+// row-map entries (bounds of the item's LDS tables).
+constexpr int kSmallRows = 128;
+constexpr int kSmallMaxUpd = 64;
+constexpr int kSmallMap = 2048;
 
 constexpr int kThreads = 256;   // 4 waves of 64
 constexpr int kTile = 64;       // rows/cols of update, triangular-solve tiles

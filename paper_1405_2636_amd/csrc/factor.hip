@@ -575,8 +575,134 @@ __device__ __forceinline__ void push_items(const SchedArgs& a, bool hp, int base
         if (base + i < cap)
             __hip_atomic_store(&q[base + i], first + i, __ATOMIC_RELAXED, AGENT);
         else
-            __hip_atomic_store(&a.status[1], 2, __ATOMIC_RELAXED, AGENT);   // more pushes than slots
+            __hip_atomic_store(&a.status[kStAbort], 2, __ATOMIC_RELAXED, AGENT);   // more pushes than slots
     }
+}
+
+// Count down one update tile of target j (any lane); queue j when it was the
+// last one.
+__device__ __forceinline__ void finish_update(const SchedArgs& a, int j)
+{
+    if (__hip_atomic_fetch_add(&a.fact_dep[j], -1, __ATOMIC_RELAXED, AGENT) != 1) return;
+    const bool hp = a.hp_cblk[j] != 0;
+    const int slot = __hip_atomic_fetch_add(hp ? a.hp_tail : a.qtail, 1, __ATOMIC_RELAXED, AGENT);
+    if (slot < (hp ? a.hp_total : a.total_normal))
+        __hip_atomic_store(&(hp ? a.hp_queue : a.queue)[slot], j, __ATOMIC_RELAXED, AGENT);
+    else
+        __hip_atomic_store(&a.status[kStAbort], 2, __ATOMIC_RELAXED, AGENT);
+}
+
+// ---------------------------------------------------------------- fused small block
+// A column block of width w <= 32 with at most 128 panel rows as one item:
+// the panel is read into LDS once; the diagonal block is factored and
+// inverted (tile_chol_inv); the rows below become A_off D^T; every update
+// tile of the block (descriptors in the table, never queued) is formed from
+// the LDS copy and scattered with the atomics of the update items; then the
+// item counts its targets down.  Blocks at the bottom of the elimination
+// tree of small systems are a few columns wide: as separate factor, solve
+// and update items each paid several queue round trips and chains of
+// dependent metadata loads for a few hundred flops.  Products accumulate in
+// FP64 from the stored (type T) values.
+constexpr int kSLd = kSmallRows + 1;   // leading dimension of the LDS panel copy
+static_assert(kSLd * kNB * sizeof(float) + (kSmallMap + 8 * kSmallMaxUpd) * sizeof(int) +
+                      kSmallMaxUpd * sizeof(int64_t) <= (kPbLd * kNB + 32) * sizeof(float),
+              "small-block tables exceed the LDS row buffer");
+static_assert((kSLd * kNB * sizeof(float) + (kSmallMap + 8 * kSmallMaxUpd) * sizeof(int)) % 8 == 0,
+              "misaligned small-block offset table");
+static_assert(kSmallRows * kNB % kThreads == 0, "rows below per thread");
+
+template <class T>
+__device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const int4 d1, double* Lt, T* Dt, T* Pb)
+{
+    const DevPlan& pl = a.pl;
+    const int k = d0.y;
+    const int ufirst = d1.x, nupd = d1.y, mstart = d1.z, mlen = d1.w;
+    const int f = pl.fcol[k];
+    const int w = pl.lcol[k] - f + 1;
+    const int ld = pl.stride[k];
+    const int R = ld - w;   // rows below the diagonal block
+    T* A = static_cast<T*>(a.panels) + pl.panel_off[k];
+    T* D = static_cast<T*>(a.dinv) + pl.dinv_off[k];
+    T* S = Pb;                                                // S[r + c*kSLd] for panel rows r >= w
+    int* smap = reinterpret_cast<int*>(S + kSLd * kNB);       // row-map entries mstart ..
+    int* dtab = smap + kSmallMap;                             // per tile: j, row0, mrows, col0, ncols, map base, ldj
+    int64_t* dpo = reinterpret_cast<int64_t*>(dtab + 8 * kSmallMaxUpd);   // panel offset of the target
+    double* bc = Lt + kNB * 33;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
+        const int r = idx & 31, c = idx >> 5;
+        Lt[r + c * 33] = (r < w && c < w) ? (c <= r ? (double)A[r + (int64_t)c * ld] : 0.0) : (r == c ? 1.0 : 0.0);
+    }
+    for (int idx = tid; idx < R * w; idx += kThreads) {
+        const int i = idx % R, c = idx / R;
+        S[(w + i) + c * kSLd] = A[(w + i) + (int64_t)c * ld];
+    }
+    for (int idx = tid; idx < mlen; idx += kThreads) smap[idx] = a.rmap[mstart + idx];
+    if (tid < nupd) {
+        const int4 u0 = a.desc[2 * (ufirst + tid)], u1 = a.desc[2 * (ufirst + tid) + 1];
+        int* e = dtab + 8 * tid;
+        e[0] = u0.z;
+        e[1] = u0.w;
+        e[2] = u1.x;
+        e[3] = u1.y;
+        e[4] = u1.z;
+        e[5] = u1.w - mstart;
+        e[6] = pl.stride[u0.z];
+        dpo[tid] = pl.panel_off[u0.z];
+    }
+    __syncthreads();
+    if (wave == 0) tile_chol_inv<T>(Lt, bc, Dt, w, f, a.status);
+    __syncthreads();
+    for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
+        const int r = idx & 31, c = idx >> 5;
+        if (r < w && c <= r) {
+            A[r + (int64_t)c * ld] = (T)Lt[r + c * 33];
+            D[r + (int64_t)c * w] = Dt[r + c * 33];
+        }
+    }
+    // rows below: P = A_off D^T, D lower triangular
+    constexpr int kPer = kSmallRows * kNB / kThreads;
+    double p[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = tid + q * kThreads;
+        double acc = 0.0;
+        if (idx < R * w) {
+            const int i = idx % R, c = idx / R;
+            for (int t = 0; t <= c; ++t) acc += (double)S[(w + i) + t * kSLd] * (double)Dt[c + t * 33];
+        }
+        p[q] = acc;
+    }
+    __syncthreads();   // every product has read its row of S
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = tid + q * kThreads;
+        if (idx < R * w) {
+            const int i = idx % R, c = idx / R;
+            const T v = (T)p[q];
+            S[(w + i) + c * kSLd] = v;
+            A[(w + i) + (int64_t)c * ld] = v;
+        }
+    }
+    __syncthreads();
+    // update tiles: C_j[rmap(r), rmap(c)] -= P_r . P_c on the lower triangle of j
+    for (int u = 0; u < nupd; ++u) {
+        const int* e = dtab + 8 * u;
+        const int row0 = e[1], mrows = e[2], col0 = e[3], ncols = e[4], mb = e[5], ldj = e[6];
+        auto Cg = glob(static_cast<T*>(a.panels) + dpo[u]);
+        for (int idx = tid; idx < mrows * ncols; idx += kThreads) {
+            const int r = row0 + idx % mrows, c = col0 + idx / mrows;
+            const int tr = smap[mb + r], tc = smap[mb + c];
+            if (tr >= tc) {
+                double acc = 0.0;
+                for (int t = 0; t < w; ++t) acc += (double)S[r + t * kSLd] * (double)S[c + t * kSLd];
+                __hip_atomic_fetch_add(Cg + (int64_t)tc * ldj + tr, (T)(-acc), __ATOMIC_RELAXED, AGENT);
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();   // every atomic of the item has completed
+    if (tid < nupd) finish_update(a, dtab[8 * tid]);
 }
 
 // ---------------------------------------------------------------- scheduler
@@ -585,7 +711,7 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 {
     __shared__ double Lt[kNB * 33 + 2 * kNB];
     __shared__ T Dt[kNB * 33];
-    __shared__ T Pb[kPbLd * kNB + 32];   // + padding: tile row indices up to 255
+    __shared__ __align__(16) T Pb[kPbLd * kNB + 32];   // + padding: tile row indices up to 255; small-block tables
     __shared__ int rpos[256], cpos[128];
     __shared__ int s_item;
     __shared__ int s_push[6];   // {hp first, hp count, hp base, normal first, normal count, normal base}
@@ -597,14 +723,19 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
     // next slot is already published, so that an idle worker picks up a
     // released critical item at once; a worker holding one serves whichever
     // of its two items is published first.
-    int my_slot = -1, hp_slot = -1;
+    // Items served by this worker are counted in a register and added to the
+    // done count once, at exit.
+    int my_slot = -1, hp_slot = -1, ndone = 0;
     for (;;) {
         if (tid == 0) {
             int item = -1;
             s_t0 = wall_clock64();
             const int64_t t0 = s_t0;
-            for (;;) {
-                if (__hip_atomic_load(&a.status[1], __ATOMIC_RELAXED, AGENT) != 0) { item = -1; break; }
+            for (int spin = 0;; ++spin) {
+                if ((spin & 15) == 0 && __hip_atomic_load(&a.status[kStAbort], __ATOMIC_RELAXED, AGENT) != 0) {
+                    item = -1;
+                    break;
+                }
                 if (hp_slot < 0) {
                     const int h = __hip_atomic_load(a.hp_head, __ATOMIC_RELAXED, AGENT);
                     if (h < a.hp_total && __hip_atomic_load(&a.hp_queue[h], __ATOMIC_RELAXED, AGENT) >= 0) {
@@ -626,11 +757,12 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
                 }
                 __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - t0 > a.timeout_ticks) {
-                    __hip_atomic_store(&a.status[1], 1, __ATOMIC_RELAXED, AGENT);
+                    __hip_atomic_store(&a.status[kStAbort], 1, __ATOMIC_RELAXED, AGENT);
                     item = -1;
                     break;
                 }
             }
+            if (item < 0) __hip_atomic_fetch_add(&a.status[kStDone], ndone, __ATOMIC_RELAXED, AGENT);
             s_item = item;
             s_t1 = wall_clock64();
         }
@@ -649,15 +781,17 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
             __builtin_amdgcn_s_setprio(2);
             task_trsm<T>(a, d0.y, d0.z, d0.w);
             __builtin_amdgcn_s_setprio(0);
-        } else {
+        } else if (d0.x == kUpdate) {
             task_update<T>(a, d0, d1, rpos, cpos);
+        } else {
+            task_small<T>(a, d0, d1, Lt, Dt, Pb);
         }
         // every wave's stores and atomics have completed before the barrier
         // (FACT and TRSM items ran at raised wave priority: they are on the
         // elimination chain and share their CU with update tiles)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (tid < 64 && d0.x != kUpdate) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (tid < 64 && (d0.x == kFact || d0.x == kTrsm)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (tid == 0) {
             int hf = 0, hc = 0, nf = 0, nc = 0;
             if (d0.x == kFact) {
@@ -675,7 +809,7 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
                     nf = hf + hc;
                     nc = a.upd_count[d0.y] - hc;
                 }
-            } else {
+            } else if (d0.x == kUpdate) {
                 if (__hip_atomic_fetch_add(&a.fact_dep[d0.z], -1, __ATOMIC_RELAXED, AGENT) == 1) {
                     if (a.hp_cblk[d0.z]) { hf = d0.z; hc = 1; }
                     else { nf = d0.z; nc = 1; }
@@ -687,7 +821,7 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
             s_push[3] = nf;
             s_push[4] = nc;
             s_push[5] = nc > 0 ? __hip_atomic_fetch_add(a.qtail, nc, __ATOMIC_RELAXED, AGENT) : 0;
-            __hip_atomic_fetch_add(&a.status[2], 1, __ATOMIC_RELAXED, AGENT);
+            ++ndone;
             if (a.trace) {
                 int64_t* t = a.trace + 4 * (int64_t)item;
                 t[0] = s_t0;
@@ -746,9 +880,9 @@ __global__ void sched_init(SchedArgs a, const int32_t* ready, int32_t nready, in
         *a.qtail = nready_n;
         *a.hp_head = 0;
         *a.hp_tail = nready_hp;
-        a.status[0] = 0x7fffffff;
-        a.status[1] = 0;
-        a.status[2] = 0;
+        a.status[kStFail] = 0x7fffffff;
+        a.status[kStAbort] = 0;
+        a.status[kStDone] = 0;
     }
 }
 

@@ -42,7 +42,7 @@ class Options(C.Structure):
     _fields_ = [("method", C.c_int32), ("leaf_size", C.c_int32), ("amalg_pct", C.c_int32),
                 ("split_width", C.c_int32), ("user_perm", C.c_void_p), ("precision", C.c_int32),
                 ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double), ("trace", C.c_int32),
-                ("graph", C.c_int32), ("tune", C.c_int32), ("tile", C.c_int32)]
+                ("graph", C.c_int32), ("tune", C.c_int32), ("tile", C.c_int32), ("fuse_small", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -51,7 +51,8 @@ class Info(C.Structure):
                 ("panel_entries", C.c_int64), ("flops_alg", C.c_double), ("flops_exec", C.c_double),
                 ("ntasks", C.c_int64), ("fail_col", C.c_int32), ("factorized", C.c_int32),
                 ("logdet", C.c_double), ("factor_kernel_ms", C.c_double), ("assemble_ms", C.c_double),
-                ("tile_rows", C.c_int32), ("tile_cols", C.c_int32), ("hp_policy", C.c_int32), ("nsys", C.c_int32)]
+                ("tile_rows", C.c_int32), ("tile_cols", C.c_int32), ("hp_policy", C.c_int32), ("nsys", C.c_int32),
+                ("nqueued", C.c_int64), ("nsmall", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -137,7 +138,8 @@ class Solver:
     """
 
     def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,
-                 precision="fp64", ir_max_iter=None, ir_tol=1e-14, trace=False, graph=False, tune=False, tile=0):
+                 precision="fp64", ir_max_iter=None, ir_tol=1e-14, trace=False, graph=False, tune=False, tile=0,
+                 fuse_small=True):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -146,7 +148,7 @@ class Solver:
         self.nnz = int(self._colptr[-1]) if len(self._colptr) else 0
         self.sizes = [self.n]
         opt, up = self._options(L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol,
-                                trace, graph, tune, tile)
+                                trace, graph, tune, tile, fuse_small)
         h = C.c_void_p()
         rc = L.spx_analyze(self.n, self._colptr.ctypes.data, self._rowind.ctypes.data, C.byref(opt), C.byref(h))
         if rc != SPX_OK:
@@ -154,7 +156,7 @@ class Solver:
         self._h = h
 
     def _options(self, L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol, trace,
-                 graph, tune, tile=0):
+                 graph, tune, tile=0, fuse_small=True):
         opt = Options()
         L.spx_default_options(C.byref(opt))
         opt.leaf_size, opt.amalg_pct, opt.split_width = leaf_size, amalg_pct, split_width
@@ -168,6 +170,7 @@ class Solver:
         opt.graph = 1 if graph else 0
         opt.tune = 1 if tune else 0
         opt.tile = int(tile)
+        opt.fuse_small = 1 if fuse_small else 0
         up = None
         if user_perm is not None:
             up = np.ascontiguousarray(user_perm, dtype=np.int32)
@@ -191,7 +194,8 @@ class Solver:
         self.nnz = int(sum(int(c[-1]) for c in cps))
         self._keep = (cps, ris)
         opt, _ = self._options(L, kw.get("leaf_size", 64), kw.get("amalg_pct", 12), kw.get("split_width", 256),
-                               None, precision, ir_max_iter, ir_tol, kw.get("trace", False), graph, tune)
+                               None, precision, ir_max_iter, ir_tol, kw.get("trace", False), graph, tune,
+                               kw.get("tile", 0), kw.get("fuse_small", True))
         cpp = (C.c_void_p * len(cps))(*[c.ctypes.data for c in cps])
         rip = (C.c_void_p * len(ris))(*[r.ctypes.data for r in ris])
         h = C.c_void_p()

@@ -276,3 +276,25 @@ def test_fp32_ir_logdet(orc, torch):
     sym = orc.analyze(p.n, p.colptr, p.rowind)
     m = int(np.max(sym.colcount))
     assert abs(s.info()["logdet"] - ref) <= 2 * p.n * (m + 1) * U32
+
+
+@pytest.mark.parametrize("case", ["config1", "grid3", "rand"])
+@pytest.mark.parametrize("fuse", [True, False])
+def test_fused_small_blocks(orc, torch, case, fuse):
+    # column blocks of width <= 32 with at most 128 panel rows run as one
+    # fused item (factor, rows below, update scatter) or as separate factor,
+    # solve and update items: both factors equal the oracle's
+    p = {"config1": lambda: make_config(1), "grid3": lambda: grid_laplacian((14, 12, 11), shift=1e-3),
+         "rand": lambda: random_spd(900, 0.004, 3)}[case]()
+    s, F, sym, P = _check_parity(orc, torch, p, fuse_small=fuse)
+    inf = s.info()
+    if fuse:
+        assert inf["nsmall"] > 0 and inf["nqueued"] < inf["ntasks"]
+    else:
+        assert inf["nsmall"] == 0 and inf["nqueued"] == inf["ntasks"]
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+def test_fp32_ir_fused_small_blocks(orc, torch, fuse):
+    s, info = _check_fp32(orc, torch, grid_laplacian((40, 33)), nrhs=2, fuse_small=fuse)
+    assert (s.info()["nsmall"] > 0) == fuse
