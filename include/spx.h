@@ -95,7 +95,7 @@ typedef struct spx_info {
     int64_t panel_entries;    /* size of the panel storage (diagonal blocks stored square) */
     double flops_alg;         /* sum of squared exact column counts */
     double flops_exec;        /* the same on the amalgamated structure */
-    int64_t ntasks;           /* work-item descriptors per factorization (the trace length) */
+    int64_t ntasks;           /* device scheduler work items per factorization */
     int32_t fail_col;         /* after SPX_ENOTPD: failing column, original numbering */
     int32_t factorized;       /* 1 once a factorization succeeded */
     double logdet;            /* log det A after a factorization */
@@ -105,8 +105,7 @@ typedef struct spx_info {
     int32_t tile_cols;
     int32_t hp_policy;        /* 0: every elimination chain first; 1: only the upper levels */
     int32_t nsys;             /* independent systems of the handle (spx_analyze_batch), 1 otherwise */
-    int64_t nqueued;          /* work items that pass through the device queues; the update
-                               * tiles of fused blocks run inside their block's item */
+    int64_t nfused_tiles;     /* update tiles carried out inside fused items (not in ntasks) */
     int32_t nsmall;           /* column blocks handled as one fused item (fuse_small) */
     int32_t reserved;
 } spx_info;
@@ -215,14 +214,12 @@ int spx_export_symbolic(const spx_handle* h, spx_symbolic_view* view);
 int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip_stream);
 
 /* Task trace of the last factorization (trace option on): 4 int64 per work
- * item descriptor in dst {claimed, started, finished: device wall-clock
- * ticks; hardware id register of the executing wave}, and, if kinds is not
- * NULL, 4 int32 per descriptor {kind 0 factor / 1 triangular solve / 2
- * update / 3 fused small block, source cblk, target cblk, rows*cols of an
- * update tile or rows of a solve tile}.  The update tiles of a fused block
- * run inside its item and keep zero stamps.  cap = number of descriptors dst
- * can hold (info.ntasks).  Returns the descriptor count, or a negative
- * status. */
+ * item in dst {claimed, started, finished: device wall-clock ticks; hardware
+ * id register of the executing wave}, and, if kinds is not NULL, 4 int32 per
+ * item {kind 0 factor / 1 triangular solve / 2 update / 3 fused small block,
+ * source cblk, target cblk, rows*cols of an update tile or rows of a solve
+ * tile}.  cap = number of items dst can hold (info.ntasks).  Returns the
+ * item count, or a negative status. */
 int64_t spx_get_trace(spx_handle* h, int64_t* dst, int64_t cap, int32_t* kinds);
 
 /* Free everything owned by the handle.  NULL is allowed. */

@@ -122,11 +122,12 @@ struct spx_handle {
     DevBuf<int64_t> rowg_off;
     // scheduler tables
     int32_t total = 0, nready = 0, nready_hp = 0, hp_total = 0, total_normal = 0;
-    int32_t ndesc = 0, nsmall = 0;   // descriptors (queued items + update tiles of fused blocks); fused blocks
+    int32_t nsmall = 0, nfused_tiles = 0;   // fused small blocks and their update tiles
     DevBuf<int4> desc;
     DevBuf<int32_t> rmap;
     DevBuf<int32_t> trsm_first, trsm_count, upd_first, upd_hp, upd_count, hp_cblk, fact_dep0, fact_dep, trsm_left,
         queue, hp_queue, ready, qctr, status;
+    DevBuf<int4> ftab;
     DevBuf<int64_t> trace;   // per-item task trace, allocated when the trace option is on
     // levels for the sweeps
     Level lv;
@@ -327,7 +328,8 @@ void build_tasks(spx_handle* h)
         tc[k] = id - tf[k];
         ntrsm += tc[k];
     }
-    int64_t nhp_upd = 0, nfused_upd = 0;
+    int64_t nhp_upd = 0;
+    std::vector<int4> ftab;   // update tiles of the fused blocks
     std::vector<int32_t> grow;
     for (int32_t k = 0; k < nc; ++k) {
         const int32_t ld = P.stride[k];
@@ -338,6 +340,7 @@ void build_tasks(spx_handle* h)
         uf[k] = id;
         uh[k] = 0;
         const int64_t mstart = static_cast<int64_t>(rmap.size());
+        const int32_t ftile0 = static_cast<int32_t>(ftab.size() / 3);
         bool first_pair = true;
         for (int32_t b = P.bptr[k] + 1; b < P.bptr[k + 1];) {
             const int32_t j = P.fcblk[b];
@@ -355,11 +358,18 @@ void build_tasks(spx_handle* h)
             }
             const int32_t mbase = static_cast<int32_t>(moff - rs);
             for_tiles(k, b, b2, [&](int32_t r0, int32_t mr, int32_t c0, int32_t ncl) {
+                ++dep[j];
+                if (small[k]) {
+                    const int64_t po = P.panel_off[j];
+                    ftab.push_back(int4{j, r0, mr, c0});
+                    ftab.push_back(int4{ncl, mbase, P.stride[j], 0});
+                    ftab.push_back(int4{static_cast<int32_t>(po & 0xffffffff), static_cast<int32_t>(po >> 32), 0, 0});
+                    return;
+                }
                 desc.push_back(int4{kUpdate, k, j, r0});
                 desc.push_back(int4{mr, c0, ncl, mbase});
-                ++dep[j];
                 ++id;
-                if (first_pair && hp[k] && !small[k]) ++uh[k];
+                if (first_pair && hp[k]) ++uh[k];
             });
             first_pair = false;
             b = b2;
@@ -367,14 +377,14 @@ void build_tasks(spx_handle* h)
         ucnt[k] = id - uf[k];
         nhp_upd += uh[k];
         if (small[k]) {
+            const int32_t nt = static_cast<int32_t>(ftab.size() / 3) - ftile0;
             desc[2 * static_cast<size_t>(k) + 1] =
-                int4{uf[k], ucnt[k], static_cast<int32_t>(mstart), static_cast<int32_t>(rmap.size() - mstart)};
-            nfused_upd += ucnt[k];
+                int4{ftile0, nt, static_cast<int32_t>(mstart), static_cast<int32_t>(rmap.size() - mstart)};
         }
     }
-    h->ndesc = id;
+    h->total = id;
     h->nsmall = nsmall;
-    h->total = static_cast<int32_t>(id - nfused_upd);   // items that pass through the queues
+    h->nfused_tiles = static_cast<int32_t>(ftab.size() / 3);
     int64_t hp_items = nhp_upd;
     for (int32_t k = 0; k < nc; ++k)
         if (hp[k]) hp_items += 1 + tc[k];
@@ -389,6 +399,8 @@ void build_tasks(spx_handle* h)
     h->nready = static_cast<int32_t>(ready.size());
     h->hp_cblk.upload(hp);
     h->desc.upload(desc);
+    if (ftab.empty()) ftab.push_back(int4{0, 0, 0, 0});
+    h->ftab.upload(ftab);
     h->rmap.upload(rmap);
     h->trsm_first.upload(tf);
     h->trsm_count.upload(tc);
@@ -565,6 +577,7 @@ SchedArgs sched_args(spx_handle* h)
     a.dinv = h->dinv_ptr();
     a.desc = h->desc.p;
     a.rmap = h->rmap.p;
+    a.ftab = h->ftab.p;
     a.hp_total = h->hp_total;
     a.total_normal = h->total_normal;
     a.trsm_first = h->trsm_first.p;
@@ -592,10 +605,7 @@ SchedArgs sched_args(spx_handle* h)
 // change of the work decomposition); then the status read-back.
 void run_factorization(spx_handle* h, hipStream_t s)
 {
-    if (h->opt.trace) {
-        h->trace.alloc(static_cast<size_t>(h->ndesc) * 4);
-        HIPCHK(hipMemsetAsync(h->trace.p, 0, static_cast<size_t>(h->ndesc) * 4 * sizeof(int64_t), s));
-    }
+    if (h->opt.trace) h->trace.alloc(static_cast<size_t>(h->total) * 4);
     if (h->opt.graph && !h->fgraph_exec[0]) {
         if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         for (int part = 0; part < 2; ++part) {
@@ -946,8 +956,8 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
         o.panel_entries = P.panel_entries;
         o.flops_alg = P.flops_alg;
         o.flops_exec = P.flops_exec;
-        o.ntasks = h->ndesc;
-        o.nqueued = h->total;
+        o.ntasks = h->total;
+        o.nfused_tiles = h->nfused_tiles;
         o.nsmall = h->nsmall;
         o.fail_col = h->fail_col;
         o.factorized = h->factorized ? 1 : 0;
@@ -1024,19 +1034,19 @@ int64_t spx_get_trace(spx_handle* h, int64_t* dst, int64_t cap, int32_t* kinds)
     if (!h) return SPX_EINVAL;
     return guarded(h, [&]() -> int {
         if (!h->opt.trace || !h->trace.p) throw StatusError(SPX_ESTATE, "trace option off or no factorization yet");
-        if (cap < h->ndesc) throw InvalidArgument("trace buffer too small");
-        HIPCHK(hipMemcpy(dst, h->trace.p, static_cast<size_t>(h->ndesc) * 4 * sizeof(int64_t), hipMemcpyDeviceToHost));
+        if (cap < h->total) throw InvalidArgument("trace buffer too small");
+        HIPCHK(hipMemcpy(dst, h->trace.p, static_cast<size_t>(h->total) * 4 * sizeof(int64_t), hipMemcpyDeviceToHost));
         if (kinds) {
-            std::vector<int4> d(static_cast<size_t>(h->ndesc) * 2);
+            std::vector<int4> d(static_cast<size_t>(h->total) * 2);
             HIPCHK(hipMemcpy(d.data(), h->desc.p, d.size() * sizeof(int4), hipMemcpyDeviceToHost));
-            for (int32_t i = 0; i < h->ndesc; ++i) {
+            for (int32_t i = 0; i < h->total; ++i) {
                 kinds[4 * i + 0] = d[2 * i].x;   // kind
                 kinds[4 * i + 1] = d[2 * i].y;   // source cblk
                 kinds[4 * i + 2] = d[2 * i].x == kUpdate ? d[2 * i].z : d[2 * i].y;   // target cblk
                 kinds[4 * i + 3] = d[2 * i].x == kUpdate ? d[2 * i + 1].y * d[2 * i + 1].z : d[2 * i].w;
             }
         }
-        return h->ndesc;
+        return h->total;
     });
 }
 

@@ -28,15 +28,18 @@ enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2, kSmall = 3 };
 //   kTrsm:   k, row0 = first panel row, nrows (<= 64)
 //   kUpdate: k (source), j (target), row0 (first source panel row);
 //            mrows, col0 (first facing panel row), ncols, mbase (row-map base)
-//   kSmall:  k; first update descriptor of k, their count, first row-map
-//            entry of k, row-map entries of k (the update descriptors of a
-//            fused block are carried out by its kSmall item, never queued)
+//   kSmall:  k; first tile of k in the fused-tile table, tile count, first
+//            row-map entry of k, row-map entries of k
+// Fused-tile table: three int4 per update tile of a fused block,
+//   {j, row0, mrows, col0}, {ncols, mbase, stride of j, 0},
+//   {panel offset of j: low word, high word, 0, 0}
 struct SchedArgs {
     DevPlan pl;
     void* panels;            // double, or float in the FP32 refinement mode
     void* dinv;              // same element type as the panels
     const int4* desc;
     const int32_t* rmap;     // panel row of k -> row inside panel j, per update pair
+    const int4* ftab;        // update tiles of fused small blocks
     int32_t hp_total;        // items of the high-priority queue (FACT, TRSM, chain updates)
     int32_t total_normal;    // items of the normal queue (other updates)
     const int32_t* trsm_first;

@@ -248,16 +248,20 @@ __device__ __forceinline__ void wave_store(const typename MM<T>::acc (&acc)[NB][
 // forward substitution step x_iq -= l_ic x_cq after x_cq was divided by
 // l_cc.  Entries above the diagonal of the tile rows are not meaningful and
 // never read.  A pivot that is not > 0 records its column with atomicMin
-// (NaN propagates).  Out: L in Lt (upper triangle zero), X in Dt.
-template <class T>
+// (NaN propagates).  Out: L in Lt (upper triangle zero), X in Dt.  NC (8,
+// 16 or 32, >= jb) bounds the columns stepped through: the leading NC x NC
+// part of Lt and Dt is written, the rest of the identity-padded tile is
+// left as it is.
+template <class T, int NC = 32>
 __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb, int col0, int32_t* status)
 {
+    static_assert(NC == 8 || NC == 16 || NC == 32, "tile width");
     const int lane = threadIdx.x & 63;
     const int r = lane & 31;
     const bool upper = lane >= 32;
-    double v[32];
+    double v[NC];
 #pragma unroll
-    for (int c = 0; c < 32; ++c) {
+    for (int c = 0; c < NC; ++c) {
         const double l = Lt[r + c * 33];
         v[c] = upper ? (c == r ? 1.0 : 0.0) : l;
     }
@@ -277,9 +281,9 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
     double s, inv;
     pivot(0, s, inv);
 #pragma unroll
-    for (int c = 0; c < 32; ++c) {
+    for (int c = 0; c < NC; ++c) {
         v[c] = lane == c ? s : v[c] * inv;
-        if (c < 31) {
+        if (c < NC - 1) {
             // column c to bc[0..31] (the upper half writes the unused
             // bc[32..63]); LDS operations of one wave complete in order, so
             // the reads below see it (compiler barrier only)
@@ -290,7 +294,7 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
             double sn, invn;
             pivot(c + 1, sn, invn);
 #pragma unroll
-            for (int i = c + 2; i < 32; ++i) v[i] -= v[c] * bc[i];
+            for (int i = c + 2; i < NC; ++i) v[i] -= v[c] * bc[i];
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
             s = sn;
             inv = invn;
@@ -299,12 +303,14 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
         __builtin_amdgcn_sched_barrier(0);
     }
     if (lane == 0 && fail < jb) atomicMin(status, col0 + fail);
-    if (!upper) {
+    if (r < NC) {
+        if (!upper) {
 #pragma unroll
-        for (int c = 0; c < 32; ++c) Lt[r + c * 33] = c <= r ? v[c] : 0.0;
-    } else {
+            for (int c = 0; c < NC; ++c) Lt[r + c * 33] = c <= r ? v[c] : 0.0;
+        } else {
 #pragma unroll
-        for (int c = 0; c < 32; ++c) Dt[c + r * 33] = c >= r ? (T)v[c] : T(0);
+            for (int c = 0; c < NC; ++c) Dt[c + r * 33] = c >= r ? (T)v[c] : T(0);
+        }
     }
 }
 
@@ -596,9 +602,9 @@ __device__ __forceinline__ void finish_update(const SchedArgs& a, int j)
 // A column block of width w <= 32 with at most 128 panel rows as one item:
 // the panel is read into LDS once; the diagonal block is factored and
 // inverted (tile_chol_inv); the rows below become A_off D^T; every update
-// tile of the block (descriptors in the table, never queued) is formed from
-// the LDS copy and scattered with the atomics of the update items; then the
-// item counts its targets down.  Blocks at the bottom of the elimination
+// tile of the block (fused-tile table) is formed from the LDS copy and
+// scattered with the atomics of the update items; then the item counts its
+// targets down.  Blocks at the bottom of the elimination
 // tree of small systems are a few columns wide: as separate factor, solve
 // and update items each paid several queue round trips and chains of
 // dependent metadata loads for a few hundred flops.  Products accumulate in
@@ -616,7 +622,7 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
 {
     const DevPlan& pl = a.pl;
     const int k = d0.y;
-    const int ufirst = d1.x, nupd = d1.y, mstart = d1.z, mlen = d1.w;
+    const int tfirst = d1.x, nupd = d1.y, mstart = d1.z, mlen = d1.w;
     const int f = pl.fcol[k];
     const int w = pl.lcol[k] - f + 1;
     const int ld = pl.stride[k];
@@ -639,19 +645,27 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
     }
     for (int idx = tid; idx < mlen; idx += kThreads) smap[idx] = a.rmap[mstart + idx];
     if (tid < nupd) {
-        const int4 u0 = a.desc[2 * (ufirst + tid)], u1 = a.desc[2 * (ufirst + tid) + 1];
+        const int4* ft = a.ftab + 3 * (int64_t)(tfirst + tid);
+        const int4 u0 = ft[0], u1 = ft[1], u2 = ft[2];
         int* e = dtab + 8 * tid;
-        e[0] = u0.z;
-        e[1] = u0.w;
-        e[2] = u1.x;
-        e[3] = u1.y;
-        e[4] = u1.z;
-        e[5] = u1.w - mstart;
-        e[6] = pl.stride[u0.z];
-        dpo[tid] = pl.panel_off[u0.z];
+        e[0] = u0.x;
+        e[1] = u0.y;
+        e[2] = u0.z;
+        e[3] = u0.w;
+        e[4] = u1.x;
+        e[5] = u1.y - mstart;
+        e[6] = u1.z;
+        dpo[tid] = (int64_t)(uint32_t)u2.x | ((int64_t)u2.y << 32);
     }
     __syncthreads();
-    if (wave == 0) tile_chol_inv<T>(Lt, bc, Dt, w, f, a.status);
+    if (wave == 0) {
+        if (w <= 8)
+            tile_chol_inv<T, 8>(Lt, bc, Dt, w, f, a.status);
+        else if (w <= 16)
+            tile_chol_inv<T, 16>(Lt, bc, Dt, w, f, a.status);
+        else
+            tile_chol_inv<T, 32>(Lt, bc, Dt, w, f, a.status);
+    }
     __syncthreads();
     for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
         const int r = idx & 31, c = idx >> 5;

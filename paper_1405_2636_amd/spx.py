@@ -52,7 +52,7 @@ class Info(C.Structure):
                 ("ntasks", C.c_int64), ("fail_col", C.c_int32), ("factorized", C.c_int32),
                 ("logdet", C.c_double), ("factor_kernel_ms", C.c_double), ("assemble_ms", C.c_double),
                 ("tile_rows", C.c_int32), ("tile_cols", C.c_int32), ("hp_policy", C.c_int32), ("nsys", C.c_int32),
-                ("nqueued", C.c_int64), ("nsmall", C.c_int32), ("reserved", C.c_int32)]
+                ("nfused_tiles", C.c_int64), ("nsmall", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -289,9 +289,9 @@ def test_fused_small_blocks(orc, torch, case, fuse):
     s, F, sym, P = _check_parity(orc, torch, p, fuse_small=fuse)
     inf = s.info()
     if fuse:
-        assert inf["nsmall"] > 0 and inf["nqueued"] < inf["ntasks"]
+        assert inf["nsmall"] > 0 and inf["nfused_tiles"] > 0
     else:
-        assert inf["nsmall"] == 0 and inf["nqueued"] == inf["ntasks"]
+        assert inf["nsmall"] == 0 and inf["nfused_tiles"] == 0
 
 
 @pytest.mark.parametrize("fuse", [True, False])
