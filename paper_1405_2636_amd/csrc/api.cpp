@@ -34,6 +34,8 @@ hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, 
 hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
 hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
 hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s);
+hipError_t launch_fwd_small(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
+hipError_t launch_bwd_small(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
 hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,
                              hipStream_t s);
 hipError_t launch_permute_out(double* x, int64_t ldx, const double* y, const int32_t* perm, int32_t n, int32_t nrhs,
@@ -96,7 +98,8 @@ struct DevBuf {
 
 struct Level {
     std::vector<int32_t> cptr;   // cblks of level l: cblk[cptr[l]..cptr[l+1])
-    std::vector<int32_t> cblk;
+    std::vector<int32_t> cblk;   // (each level's small blocks first: cblk[cptr[l]..cptr[l]+nsmall[l]))
+    std::vector<int32_t> nsmall; // blocks of width <= 32 with at most 128 panel rows, per level
     std::vector<int32_t> maxw;   // widest cblk of level l
     std::vector<int32_t> kptr;   // chunks of level l
     std::vector<int2> chunk;
@@ -438,12 +441,21 @@ void build_levels(spx_handle* h)
     for (int32_t k = 0; k < nc; ++k) ++L.cptr[lvl[k] + 1];
     for (int32_t l = 0; l < nl; ++l) L.cptr[l + 1] += L.cptr[l];
     L.cblk.resize(nc);
+    // small blocks (one 16-lane group each in the sweeps) first in their level
+    auto small = [&](int32_t k) { return P.lcol[k] - P.fcol[k] + 1 <= kNB && P.stride[k] <= kSmallRows; };
+    L.nsmall.assign(nl, 0);
     std::vector<int32_t> pos(L.cptr.begin(), L.cptr.end() - 1);
-    for (int32_t k = 0; k < nc; ++k) L.cblk[pos[lvl[k]]++] = k;
+    for (int32_t k = 0; k < nc; ++k)
+        if (small(k)) {
+            L.cblk[pos[lvl[k]]++] = k;
+            ++L.nsmall[lvl[k]];
+        }
+    for (int32_t k = 0; k < nc; ++k)
+        if (!small(k)) L.cblk[pos[lvl[k]]++] = k;
     L.kptr.assign(nl + 1, 0);
     L.maxw.assign(nl, 1);
     for (int32_t l = 0; l < nl; ++l) {
-        for (int32_t q = L.cptr[l]; q < L.cptr[l + 1]; ++q) {
+        for (int32_t q = L.cptr[l] + L.nsmall[l]; q < L.cptr[l + 1]; ++q) {
             const int32_t k = L.cblk[q];
             const int32_t w = P.lcol[k] - P.fcol[k] + 1;
             L.maxw[l] = std::max(L.maxw[l], w);
@@ -537,13 +549,19 @@ void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
     const Level& L = h->lv;
     const int nl = static_cast<int>(L.cptr.size()) - 1;
     for (int l = 0; l < nl; ++l) {
-        HIPCHK(launch_fwd_diag(a, h->lv_cblk.p + L.cptr[l], L.cptr[l + 1] - L.cptr[l], L.maxw[l], s));
+        const int32_t* sm = h->lv_cblk.p + L.cptr[l];
+        const int ns = L.nsmall[l], nb = L.cptr[l + 1] - L.cptr[l] - ns;
+        HIPCHK(launch_fwd_small(a, sm, ns, s));
+        HIPCHK(launch_fwd_diag(a, sm + ns, nb, L.maxw[l], s));
         HIPCHK(launch_fwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
     }
     HIPCHK(launch_fill_f64(h->tacc.p, static_cast<int64_t>(h->n) * nrhs, 0.0, s));
     for (int l = nl - 1; l >= 0; --l) {
+        const int32_t* sm = h->lv_cblk.p + L.cptr[l];
+        const int ns = L.nsmall[l], nb = L.cptr[l + 1] - L.cptr[l] - ns;
         HIPCHK(launch_bwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
-        HIPCHK(launch_bwd_diag(a, h->lv_cblk.p + L.cptr[l], L.cptr[l + 1] - L.cptr[l], L.maxw[l], s));
+        HIPCHK(launch_bwd_diag(a, sm + ns, nb, L.maxw[l], s));
+        HIPCHK(launch_bwd_small(a, sm, ns, s));
     }
 }
 
@@ -848,7 +866,7 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
             }
             h->nrhs_cap = nrhs;
         }
-        h->stats.alloc(5);
+        h->stats.alloc(5 * kStatStride);
         if (h->graph_nrhs != nrhs) {
             // one application of A^{-1}: dw = P^T L^{-T} L^{-1} P rw, captured once per nrhs
             h->drop_graph();
@@ -872,14 +890,14 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
         double omega = 0.0, eta = 0.0, prev = INFINITY;
         const double tol = h->opt.ir_tol;
         for (;;) {
-            HIPCHK(launch_zero_u64(h->stats.p, 5, s));
+            HIPCHK(launch_zero_u64(h->stats.p, 5 * kStatStride, s));
             HIPCHK(launch_residual(h->rptr.p, h->rcol.p, h->rv.p, h->xw.p, h->bw.p, n, h->rw.p, n, nrhs,
                                    h->stats.p, s));
-            unsigned long long st[5];
+            unsigned long long st[5 * kStatStride];
             HIPCHK(hipMemcpyAsync(st, h->stats.p, sizeof st, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             double v[5];
-            std::memcpy(v, st, sizeof v);
+            for (int q = 0; q < 5; ++q) std::memcpy(&v[q], &st[q * kStatStride], sizeof(double));
             omega = v[0];
             const double den = v[4] * v[2] + v[3];
             eta = v[1] == 0.0 ? 0.0 : (den == 0.0 ? INFINITY : v[1] / den);

@@ -91,6 +91,11 @@ constexpr int kSmallRows = 128;
 constexpr int kSmallMaxUpd = 64;
 constexpr int kSmallMap = 2048;
 
+// Residual statistics: one 256-byte line per statistic (five of them),
+// filled by a fixed grid of blocks.
+constexpr int kStatStride = 32;   // u64 words between statistics
+constexpr int kResidualBlocks = 1024;
+
 constexpr int kThreads = 256;   // 4 waves of 64
 constexpr int kTile = 64;       // rows/cols of update, triangular-solve tiles
 constexpr int kNB = 32;         // diagonal tile (inverted explicitly)

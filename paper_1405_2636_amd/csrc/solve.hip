@@ -188,6 +188,98 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblk
     }
 }
 
+// ---- small blocks (width <= 32, at most 128 panel rows), both halves of a
+// sweep step in one kernel: a group of 16 lanes per block, 16 blocks per
+// workgroup (the bottom levels of small systems hold tens of thousands of
+// blocks a few columns wide; one workgroup per block would leave most of
+// each workgroup idle and the launch bound by workgroup dispatch).
+constexpr int kSG = 16;                    // lanes per small block
+constexpr int kSGroups = 256 / kSG;        // small blocks per workgroup
+
+// forward: z_k = D y_k, then y[g(r)] -= L[r, :] z_k for the rows below
+template <class T>
+__global__ void __launch_bounds__(256) fwd_small(SweepArgs a, const int32_t* cblks, int count)
+{
+    __shared__ double ys[kSGroups][32];
+    __shared__ double zs[kSGroups][32];
+    const int tid = threadIdx.x, g = tid / kSG, l = tid % kSG;
+    const int idx = blockIdx.x * kSGroups + g;
+    const bool on = idx < count;
+    const int k = cblks[on ? idx : count - 1];
+    const DevPlan& pl = a.pl;
+    const int f = pl.fcol[k];
+    const int w = on ? pl.lcol[k] - f + 1 : 0;
+    const int ld = on ? pl.stride[k] : 0;
+    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
+    const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k];
+    const int32_t* rg = a.rowg + a.rowg_off[k] - w;   // rg[r]: global row of panel row r >= w
+    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
+        const int64_t vo = (int64_t)rhs * a.n;
+        for (int r = l; r < w; r += kSG) ys[g][r] = a.y[vo + f + r];
+        __syncthreads();
+        for (int r = l; r < w; r += kSG) {
+            double v = 0.0;
+            for (int p = 0; p <= r; ++p) v += (double)D[r + p * w] * ys[g][p];
+            zs[g][r] = v;
+            a.z[vo + f + r] = v;
+        }
+        __syncthreads();
+        for (int r = w + l; r < ld; r += kSG) {
+            double v = 0.0;
+#pragma unroll 4
+            for (int c = 0; c < w; ++c) v += (double)L[r + (int64_t)c * ld] * zs[g][c];
+            unsafeAtomicAdd(a.y + vo + rg[r], -v);
+        }
+        __syncthreads();
+    }
+}
+
+// backward: t = L_off^T x[g(rows below)] (sums over the group's lanes),
+// then x_k = D^T (z_k - t)
+template <class T>
+__global__ void __launch_bounds__(256) bwd_small(SweepArgs a, const int32_t* cblks, int count)
+{
+    constexpr int kMaxPass = (128 + kSG - 1) / kSG;   // rows below per lane, at most
+    __shared__ double us[kSGroups][32];
+    const int tid = threadIdx.x, g = tid / kSG, l = tid % kSG;
+    const int idx = blockIdx.x * kSGroups + g;
+    const bool on = idx < count;
+    const int k = cblks[on ? idx : count - 1];
+    const DevPlan& pl = a.pl;
+    const int f = pl.fcol[k];
+    const int w = on ? pl.lcol[k] - f + 1 : 0;
+    const int ld = on ? pl.stride[k] : 0;
+    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
+    const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k];
+    const int32_t* rg = a.rowg + a.rowg_off[k] - w;
+    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
+        const int64_t vo = (int64_t)rhs * a.n;
+        double xr[kMaxPass];
+#pragma unroll
+        for (int i = 0; i < kMaxPass; ++i) {
+            const int r = w + l + kSG * i;
+            xr[i] = r < ld ? a.x[vo + rg[r]] : 0.0;
+        }
+        for (int c = 0; c < w; ++c) {
+            double v = 0.0;
+#pragma unroll
+            for (int i = 0; i < kMaxPass; ++i) {
+                const int r = w + l + kSG * i;
+                if (r < ld) v += (double)L[r + (int64_t)c * ld] * xr[i];
+            }
+            v = group_sum<kSG>(v);
+            if (l == 0) us[g][c] = a.z[vo + f + c] - v;
+        }
+        __syncthreads();
+        for (int c = l; c < w; c += kSG) {
+            double v = 0.0;
+            for (int p = c; p < w; ++p) v += (double)D[p + c * w] * us[g][p];
+            a.x[vo + f + c] = v;
+        }
+        __syncthreads();
+    }
+}
+
 // ---- vector kernels
 __global__ void permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs)
 {
@@ -209,7 +301,7 @@ __global__ void permute_out(double* x, int64_t ldx, const double* y, const int32
 
 __global__ void zero_u64(unsigned long long* p, int n)
 {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
 }
 
 __global__ void axpy_kernel(double* x, const double* d, int64_t n)
@@ -247,6 +339,8 @@ __device__ __forceinline__ unsigned long long block_max(unsigned long long v)
 // factorization by gather_kernel so that the residual reads them in order).
 // stats[0] = max_i |r_i| / (|A||x| + |b|)_i   (0/0 = 0, p/0 = inf)
 // stats[1] = max |r_i|, stats[2] = max |x_i|, stats[3] = max |b_i|, stats[4] = max_i sum_j |a_ij|
+// (stats[q] at word q * kStatStride: every block adds its maxima by atomics,
+// one cache line per statistic; a fixed grid of kResidualBlocks blocks)
 __global__ void __launch_bounds__(256) residual_kernel(const int64_t* rptr, const int32_t* rcol, const double* rv,
                                                        const double* x, const double* b,
                                                        int64_t ldb, double* r, int32_t n, int32_t nrhs,
@@ -283,11 +377,11 @@ __global__ void __launch_bounds__(256) residual_kernel(const int64_t* rptr, cons
     m3 = block_max(m3);
     m4 = block_max(m4);
     if (threadIdx.x == 0) {
-        atomicMax(stats + 0, m0);
-        atomicMax(stats + 1, m1);
-        atomicMax(stats + 2, m2);
-        atomicMax(stats + 3, m3);
-        atomicMax(stats + 4, m4);
+        atomicMax(stats + 0 * kStatStride, m0);
+        atomicMax(stats + 1 * kStatStride, m1);
+        atomicMax(stats + 2 * kStatStride, m2);
+        atomicMax(stats + 3 * kStatStride, m3);
+        atomicMax(stats + 4 * kStatStride, m4);
     }
 }
 
@@ -381,7 +475,25 @@ hipError_t launch_permute_out(double* x, int64_t ldx, const double* y, const int
 }
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s)
 {
-    zero_u64<<<1, 64, 0, s>>>(p, n);
+    zero_u64<<<1, 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_small(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const int blocks = (count + kSGroups - 1) / kSGroups;
+    if (a.f32) fwd_small<float><<<blocks, 256, 0, s>>>(a, cblks, count);
+    else fwd_small<double><<<blocks, 256, 0, s>>>(a, cblks, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_small(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const int blocks = (count + kSGroups - 1) / kSGroups;
+    if (a.f32) bwd_small<float><<<blocks, 256, 0, s>>>(a, cblks, count);
+    else bwd_small<double><<<blocks, 256, 0, s>>>(a, cblks, count);
     return hipGetLastError();
 }
 
@@ -394,7 +506,8 @@ hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const doubl
                            const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
                            unsigned long long* stats, hipStream_t s)
 {
-    residual_kernel<<<grid_for((int64_t)n * nrhs), 256, 0, s>>>(rptr, rcol, rv, x, b, ldb, r, n, nrhs, stats);
+    const int blocks = (int)std::min<int64_t>(kResidualBlocks, std::max<int64_t>(1, ((int64_t)n * nrhs + 255) / 256));
+    residual_kernel<<<blocks, 256, 0, s>>>(rptr, rcol, rv, x, b, ldb, r, n, nrhs, stats);
     return hipGetLastError();
 }
 
