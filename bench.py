@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batch leg")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 512-system batch leg (its JSON object on one line; for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run three plain device copies of 512 MiB (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -209,6 +211,9 @@ def main():
     from gen import make_config
     from paper_1405_2636_amd import Solver
 
+    if args.batch_only:
+        print(json.dumps({"batch": run_batch(torch, np, Solver, args.steps)}), flush=True)
+        return
     p = make_config(args.config)
     vals = torch.tensor(p.values, device="cuda")
     b0 = torch.tensor(np.ascontiguousarray(p.b[:, 0]), device="cuda")

@@ -197,6 +197,8 @@ constexpr int kSG = 16;                    // lanes per small block
 constexpr int kSGroups = 256 / kSG;        // small blocks per workgroup
 
 // forward: z_k = D y_k, then y[g(r)] -= L[r, :] z_k for the rows below
+constexpr int kMaxPass = (128 + kSG - 1) / kSG;   // rows below per lane, at most
+
 template <class T>
 __global__ void __launch_bounds__(256) fwd_small(SweepArgs a, const int32_t* cblks, int count)
 {
@@ -217,18 +219,46 @@ __global__ void __launch_bounds__(256) fwd_small(SweepArgs a, const int32_t* cbl
         const int64_t vo = (int64_t)rhs * a.n;
         for (int r = l; r < w; r += kSG) ys[g][r] = a.y[vo + f + r];
         __syncthreads();
+        // (indices past the triangle or the panel are clamped; their terms
+        // are multiplied by zero, so the loads of a round are unconditional)
         for (int r = l; r < w; r += kSG) {
             double v = 0.0;
-            for (int p = 0; p <= r; ++p) v += (double)D[r + p * w] * ys[g][p];
+#pragma unroll 1
+            for (int p0 = 0; p0 <= r; p0 += 8) {
+                T d[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) d[u] = D[r + min(p0 + u, r) * w];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v += (double)d[u] * (p0 + u <= r ? ys[g][min(p0 + u, 31)] : 0.0);
+            }
             zs[g][r] = v;
             a.z[vo + f + r] = v;
         }
         __syncthreads();
-        for (int r = w + l; r < ld; r += kSG) {
-            double v = 0.0;
-#pragma unroll 4
-            for (int c = 0; c < w; ++c) v += (double)L[r + (int64_t)c * ld] * zs[g][c];
-            unsafeAtomicAdd(a.y + vo + rg[r], -v);
+        if (ld > w) {
+            double v[kMaxPass];
+#pragma unroll
+            for (int i = 0; i < kMaxPass; ++i) v[i] = 0.0;
+#pragma unroll 1
+            for (int c0 = 0; c0 < w; c0 += 4) {
+                T lv[4][kMaxPass];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int i = 0; i < kMaxPass; ++i)
+                        lv[u][i] = L[min(w + l + kSG * i, ld - 1) + (int64_t)min(c0 + u, w - 1) * ld];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double z = c0 + u < w ? zs[g][min(c0 + u, 31)] : 0.0;
+#pragma unroll
+                    for (int i = 0; i < kMaxPass; ++i) v[i] += (double)lv[u][i] * z;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kMaxPass; ++i) {
+                const int r = w + l + kSG * i;
+                if (r < ld) unsafeAtomicAdd(a.y + vo + rg[r], -v[i]);
+            }
         }
         __syncthreads();
     }
@@ -239,7 +269,6 @@ __global__ void __launch_bounds__(256) fwd_small(SweepArgs a, const int32_t* cbl
 template <class T>
 __global__ void __launch_bounds__(256) bwd_small(SweepArgs a, const int32_t* cblks, int count)
 {
-    constexpr int kMaxPass = (128 + kSG - 1) / kSG;   // rows below per lane, at most
     __shared__ double us[kSGroups][32];
     const int tid = threadIdx.x, g = tid / kSG, l = tid % kSG;
     const int idx = blockIdx.x * kSGroups + g;
@@ -260,20 +289,39 @@ __global__ void __launch_bounds__(256) bwd_small(SweepArgs a, const int32_t* cbl
             const int r = w + l + kSG * i;
             xr[i] = r < ld ? a.x[vo + rg[r]] : 0.0;
         }
-        for (int c = 0; c < w; ++c) {
-            double v = 0.0;
+        // (xr is zero for rows past the panel: their clamped loads count zero)
+#pragma unroll 1
+        for (int c0 = 0; c0 < w; c0 += 4) {
+            double v[4];
 #pragma unroll
-            for (int i = 0; i < kMaxPass; ++i) {
-                const int r = w + l + kSG * i;
-                if (r < ld) v += (double)L[r + (int64_t)c * ld] * xr[i];
+            for (int u = 0; u < 4; ++u) {
+                T lv[kMaxPass];
+#pragma unroll
+                for (int i = 0; i < kMaxPass; ++i)
+                    lv[i] = L[min(w + l + kSG * i, ld - 1) + (int64_t)min(c0 + u, w - 1) * ld];
+                double t = 0.0;
+#pragma unroll
+                for (int i = 0; i < kMaxPass; ++i) t += (double)lv[i] * xr[i];
+                v[u] = t;
             }
-            v = group_sum<kSG>(v);
-            if (l == 0) us[g][c] = a.z[vo + f + c] - v;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = group_sum<kSG>(v[u]);
+            if (l < 4 && c0 + l < w) {
+                const double t = l == 0 ? v[0] : l == 1 ? v[1] : l == 2 ? v[2] : v[3];
+                us[g][c0 + l] = a.z[vo + f + c0 + l] - t;
+            }
         }
         __syncthreads();
         for (int c = l; c < w; c += kSG) {
             double v = 0.0;
-            for (int p = c; p < w; ++p) v += (double)D[p + c * w] * us[g][p];
+#pragma unroll 1
+            for (int p0 = c; p0 < w; p0 += 8) {
+                T d[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) d[u] = D[min(p0 + u, w - 1) + c * w];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v += (double)d[u] * (p0 + u < w ? us[g][min(p0 + u, 31)] : 0.0);
+            }
             a.x[vo + f + c] = v;
         }
         __syncthreads();
