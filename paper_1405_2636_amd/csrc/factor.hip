@@ -154,9 +154,12 @@ __device__ __forceinline__ void gstore_s(const GOp& g, int voff, int soff, float
 // Y feeds operand A and X operand B (lane layout in MM), so
 //   acc[bi][bj][v] = C(16*bj + l%16, 16*bi + drow(v, l/16))
 // and the 16 lanes of a result slot cover 16 consecutive rows of C.  The
-// inner dimension advances 8 at a time through three register buffers: the
-// operands of the next 16 are in flight while the products of the current 8
-// are issued.
+// inner dimension advances 8 at a time through register buffers: FP32 uses
+// three (the operands of the next 16 in flight while the products of the
+// current 8 are issued); FP64 two (the next 8 in flight): with a third, the
+// 128 accumulator registers and the operands exceed the 256 registers of a
+// wave at two workgroups per CU, and the spilled operands each cost a wait
+// for every outstanding load.
 template <int NB, class T>
 __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][4], const GOp& X, const GOp& Y, int K)
 {
@@ -191,22 +194,35 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][4], con
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MM<T>::mfma(ys[u][bi], xs[u][bj], acc[bi][bj]);
     };
-    // three register buffers: two chunks in flight while one is multiplied
     // (reads past the last chunk repeat it and are not used)
     const int last = nchunks - 1;
-    load(xa, ya, 0);
-    load(xb, yb, min(1, last));
-    int ch = 0;
-    for (; ch + 3 <= nchunks; ch += 3) {
-        load(xc, yc, min(ch + 2, last));
-        mma(xa, ya);
-        load(xa, ya, min(ch + 3, last));
-        mma(xb, yb);
-        load(xb, yb, min(ch + 4, last));
-        mma(xc, yc);
+    if constexpr (sizeof(T) == 8) {
+        (void)xc;
+        (void)yc;
+        load(xa, ya, 0);
+        int ch = 0;
+        for (; ch + 2 <= nchunks; ch += 2) {
+            load(xb, yb, ch + 1);
+            mma(xa, ya);
+            load(xa, ya, min(ch + 2, last));
+            mma(xb, yb);
+        }
+        if (ch < nchunks) mma(xa, ya);
+    } else {
+        load(xa, ya, 0);
+        load(xb, yb, min(1, last));
+        int ch = 0;
+        for (; ch + 3 <= nchunks; ch += 3) {
+            load(xc, yc, min(ch + 2, last));
+            mma(xa, ya);
+            load(xa, ya, min(ch + 3, last));
+            mma(xb, yb);
+            load(xb, yb, min(ch + 4, last));
+            mma(xc, yc);
+        }
+        if (ch < nchunks) mma(xa, ya);
+        if (ch + 1 < nchunks) mma(xb, yb);
     }
-    if (ch < nchunks) mma(xa, ya);
-    if (ch + 1 < nchunks) mma(xb, yb);
 }
 
 template <int NB, class A>
