@@ -177,6 +177,9 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][4], con
     }
     const int dx = 8 * X.sk, dy = 8 * Y.sk;
     T xa[2][4], ya[2][NB], xb[2][4], yb[2][NB], xc[2][4], yc[2][NB];
+    // (scheduling barriers keep every group of loads ahead of the products
+    // it is meant to overlap; left alone, the compiler sinks the FP32 loads
+    // next to their uses and waits for them)
     auto load = [&](T (&xs)[2][4], T (&ys)[2][NB], int ch) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -185,6 +188,7 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][4], con
 #pragma unroll
             for (int b = 0; b < NB; ++b) ys[u][b] = gload<T>(Y, yo[u][b] + ch * dy);
         }
+        __builtin_amdgcn_sched_barrier(0);
     };
     auto mma = [&](const T (&xs)[2][4], const T (&ys)[2][NB]) {
 #pragma unroll
@@ -193,6 +197,7 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][4], con
             for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MM<T>::mfma(ys[u][bi], xs[u][bj], acc[bi][bj]);
+        __builtin_amdgcn_sched_barrier(0);
     };
     // (reads past the last chunk repeat it and are not used)
     const int last = nchunks - 1;
