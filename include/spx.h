@@ -82,6 +82,9 @@ typedef struct spx_options {
     int32_t fuse_small;       /* 1: a column block of width <= 32 with at most 128 panel rows
                                * (and at most 64 update tiles) is factored, solved and
                                * scattered as one work item (1) */
+    int32_t merge_split;      /* 1..16: the updates of up to this many consecutive pieces of a
+                               * split supernode into a block outside it are one work item
+                               * (inner dimension summed over the pieces, one scatter); 1 = off (4) */
 } spx_options;
 
 typedef struct spx_info {

@@ -310,6 +310,32 @@ void build_tasks(spx_handle* h)
             }
         }
     }
+    // merged updates of split supernodes: the pieces of a supernode are
+    // consecutive column blocks sharing the rows below the supernode, and
+    // piece p's panel rows are the rows of a later piece k shifted by
+    // fcol[k] - fcol[p].  The updates of a group of up to merge_split
+    // consecutive pieces into a block outside their supernode are one item
+    // of the group's last piece (the inner dimension spans the group).
+    std::vector<int32_t> snof(nc), gfirst(nc);
+    std::vector<char> glast(nc, 1);
+    const int32_t G = std::max(1, h->opt.merge_split);
+    for (int32_t k = 0; k < nc; ++k)
+        snof[k] = static_cast<int32_t>(std::upper_bound(P.snptr.begin(), P.snptr.end(), P.fcol[k]) - P.snptr.begin()) - 1;
+    for (int32_t k0 = 0; k0 < nc;) {
+        int32_t k1 = k0;
+        while (k1 + 1 < nc && snof[k1 + 1] == snof[k0]) ++k1;
+        bool any_small = false;
+        for (int32_t k = k0; k <= k1; ++k) any_small = any_small || small[k];
+        for (int32_t k = k0; k <= k1; ++k) {
+            const bool merge = G > 1 && !any_small;
+            gfirst[k] = merge ? k0 + ((k - k0) / G) * G : k;
+            glast[k] = merge ? (k == k1 || (k - k0 + 1) % G == 0) : 1;
+            for (int32_t p = gfirst[k]; p < k && glast[k]; ++p)
+                if (P.stride[p] != P.stride[k] + (P.fcol[k] - P.fcol[p]))
+                    throw std::runtime_error("split pieces without a common row structure");
+        }
+        k0 = k1 + 1;
+    }
     std::vector<int4> desc;
     desc.reserve(static_cast<size_t>(nc) * 2);
     std::vector<int32_t> tf(nc), tc(nc), uf(nc), uh(nc), ucnt(nc), dep(nc, 0);
@@ -349,6 +375,13 @@ void build_tasks(spx_handle* h)
             const int32_t j = P.fcblk[b];
             int32_t b2 = b;
             while (b2 < P.bptr[k + 1] && P.fcblk[b2] == j) ++b2;
+            const bool outside = snof[j] != snof[k];
+            if (outside && !glast[k]) {   // carried by the group's last piece
+                first_pair = false;
+                b = b2;
+                continue;
+            }
+            const int32_t npieces = outside ? k - gfirst[k] + 1 : 1;
             const int32_t rs = P.coefind[b];
             const int32_t re = P.coefind[b2 - 1] + (P.lrow[b2 - 1] - P.frow[b2 - 1] + 1);
             const int64_t moff = static_cast<int64_t>(rmap.size());
@@ -369,7 +402,7 @@ void build_tasks(spx_handle* h)
                     ftab.push_back(int4{static_cast<int32_t>(po & 0xffffffff), static_cast<int32_t>(po >> 32), 0, 0});
                     return;
                 }
-                desc.push_back(int4{kUpdate, k, j, r0});
+                desc.push_back(int4{kUpdate | ((npieces - 1) << 8), k, j, r0});
                 desc.push_back(int4{mr, c0, ncl, mbase});
                 ++id;
                 if (first_pair && hp[k]) ++uh[k];
@@ -692,6 +725,7 @@ void spx_default_options(spx_options* o)
     o->tune = 0;
     o->tile = 0;
     o->fuse_small = 1;
+    o->merge_split = 4;
 }
 
 int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const spx_options* opt, spx_handle** out)
@@ -713,6 +747,7 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
         if (h->opt.ir_max_iter < -1) throw InvalidArgument("ir_max_iter must be >= 0, or -1 for the default");
         if (h->opt.ir_max_iter == -1) h->opt.ir_max_iter = h->opt.precision == SPX_FP32_IR ? 10 : 2;
         if (h->opt.tile != 0 && h->opt.tile != 1) throw InvalidArgument("tile must be 0 or 1");
+        if (h->opt.merge_split < 1 || h->opt.merge_split > 16) throw InvalidArgument("merge_split must be in 1..16");
         h->tile_rows = h->opt.tile == 1 ? 128 : 256;
         h->tile_cols = h->opt.tile == 1 ? 128 : 64;
         Options o;
@@ -1058,10 +1093,11 @@ int64_t spx_get_trace(spx_handle* h, int64_t* dst, int64_t cap, int32_t* kinds)
             std::vector<int4> d(static_cast<size_t>(h->total) * 2);
             HIPCHK(hipMemcpy(d.data(), h->desc.p, d.size() * sizeof(int4), hipMemcpyDeviceToHost));
             for (int32_t i = 0; i < h->total; ++i) {
-                kinds[4 * i + 0] = d[2 * i].x;   // kind
-                kinds[4 * i + 1] = d[2 * i].y;   // source cblk
-                kinds[4 * i + 2] = d[2 * i].x == kUpdate ? d[2 * i].z : d[2 * i].y;   // target cblk
-                kinds[4 * i + 3] = d[2 * i].x == kUpdate ? d[2 * i + 1].y * d[2 * i + 1].z : d[2 * i].w;
+                const int32_t kind = d[2 * i].x & 0xff;
+                kinds[4 * i + 0] = kind;         // kind
+                kinds[4 * i + 1] = d[2 * i].y;   // source cblk (the last piece of a merged update)
+                kinds[4 * i + 2] = kind == kUpdate ? d[2 * i].z : d[2 * i].y;   // target cblk
+                kinds[4 * i + 3] = kind == kUpdate ? d[2 * i + 1].x * d[2 * i + 1].z : d[2 * i].w;
             }
         }
         return h->total;

@@ -563,16 +563,17 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // of k from the first block facing j on, its row inside panel j; for facing
 // rows that is also the column of j.  Two tile shapes: ncols <= 64 and
 // mrows <= 256 (the four waves cover 64 rows each), or 64 < ncols <= 128 and
-// mrows <= 128 (the waves form a 2x2 grid of 64x64 wave tiles).
+// mrows <= 128 (the waves form a 2x2 grid of 64x64 wave tiles).  A merged
+// item (np > 1, kind bits 8..) sums the products of the np consecutive
+// pieces k-np+1 .. k of a split supernode (piece p's rows are k's rows
+// shifted by fcol[k] - fcol[p]) before its one scatter.
 template <class T>
 __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos, int* cpos)
 {
     const DevPlan& pl = a.pl;
-    const int k = d0.y, j = d0.z, row0 = d0.w;
+    const int k = d0.y, j = d0.z, row0 = d0.w, np = (d0.x >> 8) + 1;
     const int mrows = d1.x, col0 = d1.y, ncols = d1.z, mbase = d1.w;
-    const int w = pl.lcol[k] - pl.fcol[k] + 1;
-    const int64_t ld = pl.stride[k], ldj = pl.stride[j];
-    const T* A = static_cast<const T*>(a.panels) + pl.panel_off[k];
+    const int64_t ldj = pl.stride[j];
     auto Cg = glob(static_cast<T*>(a.panels) + pl.panel_off[j]);
     const int tid = threadIdx.x, wave = tid >> 6;
     if (tid < mrows) rpos[tid] = a.rmap[mbase + row0 + tid];
@@ -585,7 +586,14 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
     if (mv > 0 && nv > 0) {
         typename MM<T>::acc acc[4][4];
         zero_acc(acc);
-        wave_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0, 1, ld), make_gop(A, ld * w, col0 + c0, 1, ld), w);
+        const int fk = pl.fcol[k];
+        for (int p = k - np + 1; p <= k; ++p) {
+            const int fp = pl.fcol[p], w = pl.lcol[p] - fp + 1, sh = fk - fp;
+            const int64_t ld = pl.stride[p];
+            const T* A = static_cast<const T*>(a.panels) + pl.panel_off[p];
+            wave_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld), make_gop(A, ld * w, col0 + c0 + sh, 1, ld),
+                            w);
+        }
         wave_store<T>(acc, mv, nv, [&](int r, int c, T v) {
             const int tr = rpos[r0 + r], tc = cpos[c0 + c];
             if (tr >= tc) __hip_atomic_fetch_add(Cg + (int64_t)tc * ldj + tr, -v, __ATOMIC_RELAXED, AGENT);
@@ -808,15 +816,16 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         __syncthreads();
         const int4 d0 = a.desc[2 * item];
         const int4 d1 = a.desc[2 * item + 1];
-        if (d0.x == kFact) {
+        const int kind = d0.x & 0xff;   // (bits 8.. of an update: pieces merged - 1)
+        if (kind == kFact) {
             __builtin_amdgcn_s_setprio(3);
             task_fact<T>(a, d0.y, Lt, Dt, Pb);
             __builtin_amdgcn_s_setprio(0);
-        } else if (d0.x == kTrsm) {
+        } else if (kind == kTrsm) {
             __builtin_amdgcn_s_setprio(2);
             task_trsm<T>(a, d0.y, d0.z, d0.w);
             __builtin_amdgcn_s_setprio(0);
-        } else if (d0.x == kUpdate) {
+        } else if (kind == kUpdate) {
             task_update<T>(a, d0, d1, rpos, cpos);
         } else {
             task_small<T>(a, d0, d1, Lt, Dt, Pb);
@@ -826,10 +835,10 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         // elimination chain and share their CU with update tiles)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (tid < 64 && (d0.x == kFact || d0.x == kTrsm)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (tid < 64 && (kind == kFact || kind == kTrsm)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (tid == 0) {
             int hf = 0, hc = 0, nf = 0, nc = 0;
-            if (d0.x == kFact) {
+            if (kind == kFact) {
                 if (a.hp_cblk[d0.y]) {
                     hf = a.trsm_first[d0.y];
                     hc = a.trsm_count[d0.y];
@@ -837,14 +846,14 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
                     nf = a.trsm_first[d0.y];
                     nc = a.trsm_count[d0.y];
                 }
-            } else if (d0.x == kTrsm) {
+            } else if (kind == kTrsm) {
                 if (__hip_atomic_fetch_add(&a.trsm_left[d0.y], -1, __ATOMIC_RELAXED, AGENT) == 1) {
                     hf = a.upd_first[d0.y];
                     hc = a.upd_hp[d0.y];
                     nf = hf + hc;
                     nc = a.upd_count[d0.y] - hc;
                 }
-            } else if (d0.x == kUpdate) {
+            } else if (kind == kUpdate) {
                 if (__hip_atomic_fetch_add(&a.fact_dep[d0.z], -1, __ATOMIC_RELAXED, AGENT) == 1) {
                     if (a.hp_cblk[d0.z]) { hf = d0.z; hc = 1; }
                     else { nf = d0.z; nc = 1; }

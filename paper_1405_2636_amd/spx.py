@@ -42,7 +42,8 @@ class Options(C.Structure):
     _fields_ = [("method", C.c_int32), ("leaf_size", C.c_int32), ("amalg_pct", C.c_int32),
                 ("split_width", C.c_int32), ("user_perm", C.c_void_p), ("precision", C.c_int32),
                 ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double), ("trace", C.c_int32),
-                ("graph", C.c_int32), ("tune", C.c_int32), ("tile", C.c_int32), ("fuse_small", C.c_int32)]
+                ("graph", C.c_int32), ("tune", C.c_int32), ("tile", C.c_int32), ("fuse_small", C.c_int32),
+                ("merge_split", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -139,7 +140,7 @@ class Solver:
 
     def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,
                  precision="fp64", ir_max_iter=None, ir_tol=1e-14, trace=False, graph=False, tune=False, tile=0,
-                 fuse_small=True):
+                 fuse_small=True, merge_split=4):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -148,7 +149,7 @@ class Solver:
         self.nnz = int(self._colptr[-1]) if len(self._colptr) else 0
         self.sizes = [self.n]
         opt, up = self._options(L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol,
-                                trace, graph, tune, tile, fuse_small)
+                                trace, graph, tune, tile, fuse_small, merge_split)
         h = C.c_void_p()
         rc = L.spx_analyze(self.n, self._colptr.ctypes.data, self._rowind.ctypes.data, C.byref(opt), C.byref(h))
         if rc != SPX_OK:
@@ -156,7 +157,7 @@ class Solver:
         self._h = h
 
     def _options(self, L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol, trace,
-                 graph, tune, tile=0, fuse_small=True):
+                 graph, tune, tile=0, fuse_small=True, merge_split=4):
         opt = Options()
         L.spx_default_options(C.byref(opt))
         opt.leaf_size, opt.amalg_pct, opt.split_width = leaf_size, amalg_pct, split_width
@@ -171,6 +172,7 @@ class Solver:
         opt.tune = 1 if tune else 0
         opt.tile = int(tile)
         opt.fuse_small = 1 if fuse_small else 0
+        opt.merge_split = int(merge_split)
         up = None
         if user_perm is not None:
             up = np.ascontiguousarray(user_perm, dtype=np.int32)
@@ -195,7 +197,7 @@ class Solver:
         self._keep = (cps, ris)
         opt, _ = self._options(L, kw.get("leaf_size", 64), kw.get("amalg_pct", 12), kw.get("split_width", 256),
                                None, precision, ir_max_iter, ir_tol, kw.get("trace", False), graph, tune,
-                               kw.get("tile", 0), kw.get("fuse_small", True))
+                               kw.get("tile", 0), kw.get("fuse_small", True), kw.get("merge_split", 4))
         cpp = (C.c_void_p * len(cps))(*[c.ctypes.data for c in cps])
         rip = (C.c_void_p * len(ris))(*[r.ctypes.data for r in ris])
         h = C.c_void_p()

@@ -298,3 +298,16 @@ def test_fused_small_blocks(orc, torch, case, fuse):
 def test_fp32_ir_fused_small_blocks(orc, torch, fuse):
     s, info = _check_fp32(orc, torch, grid_laplacian((40, 33)), nrhs=2, fuse_small=fuse)
     assert (s.info()["nsmall"] > 0) == fuse
+
+
+@pytest.mark.parametrize("merge", [1, 2, 4])
+def test_merged_split_updates(orc, torch, merge):
+    # split supernodes (width 32) whose updates into blocks outside them are
+    # summed over groups of `merge` pieces in one item: the factor equals the
+    # oracle's for every group size
+    p = grid_laplacian((18, 17, 16), shift=1e-3)
+    _check_parity(orc, torch, p, split_width=32, merge_split=merge)
+
+
+def test_fp32_ir_merged_split_updates(orc, torch):
+    _check_fp32(orc, torch, grid_laplacian((18, 17, 16), shift=1e-3), split_width=32, merge_split=4)
