@@ -83,8 +83,9 @@ typedef struct spx_options {
                                * (and at most 64 update tiles) is factored, solved and
                                * scattered as one work item (1) */
     int32_t merge_split;      /* 1..16: the updates of up to this many consecutive pieces of a
-                               * split supernode into a block outside it are one work item
-                               * (inner dimension summed over the pieces, one scatter); 1 = off (4) */
+                               * split supernode into a block outside it, or into a piece of it
+                               * at least two past the group, are one work item (inner
+                               * dimension summed over the pieces, one scatter); 1 = off (4) */
 } spx_options;
 
 typedef struct spx_info {

@@ -314,9 +314,13 @@ void build_tasks(spx_handle* h)
     // consecutive column blocks sharing the rows below the supernode, and
     // piece p's panel rows are the rows of a later piece k shifted by
     // fcol[k] - fcol[p].  The updates of a group of up to merge_split
-    // consecutive pieces into a block outside their supernode are one item
-    // of the group's last piece (the inner dimension spans the group).
-    std::vector<int32_t> snof(nc), gfirst(nc);
+    // consecutive pieces into a block outside their supernode, or into a
+    // piece at least two past the group, are one item of the group's last
+    // piece (the inner dimension spans the group).  The pieces of the group
+    // and the next one are updated piece by piece: they are factored one
+    // after the other, and the next one's factorization then waits for the
+    // last piece's update only.
+    std::vector<int32_t> snof(nc), gfirst(nc), glid(nc);
     std::vector<char> glast(nc, 1);
     const int32_t G = std::max(1, h->opt.merge_split);
     for (int32_t k = 0; k < nc; ++k)
@@ -330,6 +334,7 @@ void build_tasks(spx_handle* h)
             const bool merge = G > 1 && !any_small;
             gfirst[k] = merge ? k0 + ((k - k0) / G) * G : k;
             glast[k] = merge ? (k == k1 || (k - k0 + 1) % G == 0) : 1;
+            glid[k] = merge ? std::min(k1, gfirst[k] + G - 1) : k;
             for (int32_t p = gfirst[k]; p < k && glast[k]; ++p)
                 if (P.stride[p] != P.stride[k] + (P.fcol[k] - P.fcol[p]))
                     throw std::runtime_error("split pieces without a common row structure");
@@ -375,13 +380,13 @@ void build_tasks(spx_handle* h)
             const int32_t j = P.fcblk[b];
             int32_t b2 = b;
             while (b2 < P.bptr[k + 1] && P.fcblk[b2] == j) ++b2;
-            const bool outside = snof[j] != snof[k];
-            if (outside && !glast[k]) {   // carried by the group's last piece
+            const bool merged = snof[j] != snof[k] || j > glid[k] + 1;
+            if (merged && !glast[k]) {   // carried by the group's last piece
                 first_pair = false;
                 b = b2;
                 continue;
             }
-            const int32_t npieces = outside ? k - gfirst[k] + 1 : 1;
+            const int32_t npieces = merged ? k - gfirst[k] + 1 : 1;
             const int32_t rs = P.coefind[b];
             const int32_t re = P.coefind[b2 - 1] + (P.lrow[b2 - 1] - P.frow[b2 - 1] + 1);
             const int64_t moff = static_cast<int64_t>(rmap.size());
