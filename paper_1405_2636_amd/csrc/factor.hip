@@ -367,9 +367,14 @@ __device__ __forceinline__ void wave_mm(typename MM<T>::acc (&acc)[NB][4], LX ld
 }
 
 // C(r, c) = f(old C(r, c), (X Y^T)(r, c)) for r < mv, c < nv, keep(r, c),
-// with C(r, c) at byte offset C.off + r*C.si + c*C.sk of C's array.  The old
-// values are requested first, so that their latency overlaps the products;
-// each offset is a per-lane part plus a wave-uniform part (scalar offset).
+// with C(r, c) at byte offset C.off + r*C.si + c*C.sk of C's array; each
+// offset is a per-lane part plus a wave-uniform part (scalar offset).  FP32
+// requests the old values first, so that their latency overlaps the
+// products; FP64 requests them all after the products (held across them, the
+// old values and the accumulators exceed the registers and spill).  The
+// stores are unconditional, masked elements going to an offset past the
+// array where the hardware drops them: with a branch there the compiler
+// sinks the loads of the old values into it, one round trip per element.
 template <int NB, class T, class LX, class LY, class Keep, class F>
 __device__ __forceinline__ void wave_mm_rmw(LX ldx, LY ldy, int mv, int nv, const GOp& C, Keep keep, F f)
 {
@@ -377,32 +382,32 @@ __device__ __forceinline__ void wave_mm_rmw(LX ldx, LY ldy, int mv, int nv, cons
     const int li = lane & 15, lk = lane >> 4;
     // drow(v, lk) = MM<T>::drow(0, lk) + MM<T>::drow(v, 0)
     const int vl = C.off + li * C.si + MM<T>::drow(0, lk) * C.sk;
+    auto voff = [&](int bi, int bj, int v) {
+        const int r = 16 * bj + li, c = 16 * bi + MM<T>::drow(v, lk);
+        return (r < mv && c < nv && keep(r, c)) ? vl : kOffNone;
+    };
+    auto soff = [&](int bi, int bj, int v) { return uni(16 * bj * C.si + (16 * bi + MM<T>::drow(v, 0)) * C.sk); };
     T old[NB][4][4];
+    auto load_old = [&]() {
 #pragma unroll
-    for (int bi = 0; bi < NB; ++bi)
+        for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
+            for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * bj + li, c = 16 * bi + MM<T>::drow(v, lk);
-                const int so = uni(16 * bj * C.si + (16 * bi + MM<T>::drow(v, 0)) * C.sk);
-                const bool in = r < mv && c < nv && keep(r, c);
-                const T o = gload_s(C, in ? vl : kOffNone, so, T(0));
-                old[bi][bj][v] = in ? o : T(0);
-            }
+                for (int v = 0; v < 4; ++v) old[bi][bj][v] = gload_s(C, voff(bi, bj, v), soff(bi, bj, v), T(0));
+    };
+    if constexpr (sizeof(T) == 4) load_old();
     typename MM<T>::acc acc[NB][4];
     zero_acc(acc);
     wave_mm<NB, T>(acc, ldx, ldy);
+    if constexpr (sizeof(T) == 8) load_old();
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 16 * bj + li, c = 16 * bi + MM<T>::drow(v, lk);
-                const int so = uni(16 * bj * C.si + (16 * bi + MM<T>::drow(v, 0)) * C.sk);
-                if (r < mv && c < nv && keep(r, c)) gstore_s(C, vl, so, f(old[bi][bj][v], acc[bi][bj][v]));
-            }
+            for (int v = 0; v < 4; ++v)
+                gstore_s(C, voff(bi, bj, v), soff(bi, bj, v), f(old[bi][bj][v], acc[bi][bj][v]));
 }
 
 constexpr int kPbLd = 228;   // leading dimension of the LDS copy of the rows below a tile (<= 224 rows)
