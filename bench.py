@@ -46,7 +46,7 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(p, budget_flops: float = 1.0e10):
+def cpu_baseline(p, budget_flops: float = 4.0e10):
     """The oracle (plain serial C, one core) on a bounded sample of the same
     workload: its own analysis of the full matrix, then the factorization of
     the leading column blocks in elimination order up to a flop budget."""
