@@ -218,8 +218,8 @@ def main():
     vals = torch.tensor(p.values, device="cuda")
     b0 = torch.tensor(np.ascontiguousarray(p.b[:, 0]), device="cuda")
     legs = {prec: run_leg(torch, np, Solver, p, vals, b0, prec, args.steps, args.warmup)
-            for prec in ("fp64", "fp32_ir")}
-    r64, r32 = legs["fp64"], legs["fp32_ir"]
+            for prec in ("fp64", "fp32_ir", "bf16x3_ir")}
+    r64, r32, rbf = legs["fp64"], legs["fp32_ir"], legs["bf16x3_ir"]
     flops = r64["flops"]
     achieved = flops / (r64["kernel_ms"] * 1e-3) / 1e12
     out = {
@@ -246,6 +246,10 @@ def main():
                     "factor_gflops": flops / (r32["factor_ms"] * 1e-3) / 1e9, "omega": r32["omega"],
                     "ir_iters": r32["ir_iters"], "kernel_ms": r32["kernel_ms"],
                     "speedup_vs_fp64": (r64["factor_ms"] + r64["solve_ms"]) / (r32["factor_ms"] + r32["solve_ms"])},
+        "bf16x3_ir": {"factor_ms": rbf["factor_ms"], "solve_ms": rbf["solve_ms"],
+                      "factor_gflops": flops / (rbf["factor_ms"] * 1e-3) / 1e9, "omega": rbf["omega"],
+                      "ir_iters": rbf["ir_iters"], "kernel_ms": rbf["kernel_ms"],
+                      "speedup_vs_fp64": (r64["factor_ms"] + r64["solve_ms"]) / (rbf["factor_ms"] + rbf["solve_ms"])},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "sched_kernel<double>", "kernel_ms": r64["kernel_ms"]},

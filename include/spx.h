@@ -55,11 +55,16 @@ enum spx_method { SPX_LLT = 0 };
 
 enum spx_precision {
     SPX_FP64 = 0,     /* factor stored and computed in FP64 */
-    SPX_FP32_IR = 1   /* factor stored in FP32, products on the FP32 matrix cores
+    SPX_FP32_IR = 1,  /* factor stored in FP32, products on the FP32 matrix cores
                        * (the 32x32 diagonal tiles are factored and inverted in
                        * FP64 and rounded); the solve applies the FP32 factor
                        * in FP64 arithmetic and refines with the FP64 residual
                        * until omega <= ir_tol */
+    SPX_BF16X3_IR = 2 /* as SPX_FP32_IR, but the update and panel-solve products
+                       * split each FP32 operand x into hi = bf16(x) and
+                       * lo = bf16(x - hi) and sum hi*hi + hi*lo + lo*hi on the
+                       * BF16 matrix cores with FP32 accumulation (about 2^-16
+                       * relative per product); refinement as SPX_FP32_IR */
 };
 
 typedef struct spx_options {
@@ -70,7 +75,7 @@ typedef struct spx_options {
     const int32_t* user_perm; /* optional ordering (new -> old) replacing nested dissection */
     int32_t precision;        /* enum spx_precision */
     int32_t ir_max_iter;      /* refinement steps after the first solve; -1 (default):
-                               * 2 for SPX_FP64, 10 for SPX_FP32_IR */
+                               * 2 for SPX_FP64, 10 for the FP32-storage modes */
     double ir_tol;            /* componentwise backward error target (1e-14) */
     int32_t trace;            /* 1: record a per-work-item trace of each factorization (0) */
     int32_t graph;            /* 1: capture the device work of a factorization in a HIP graph

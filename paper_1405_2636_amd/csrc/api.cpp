@@ -196,7 +196,7 @@ struct spx_handle {
         graph_nrhs = 0;
     }
 
-    bool f32() const { return opt.precision == SPX_FP32_IR; }
+    bool f32() const { return opt.precision != SPX_FP64; }   // FP32 panel storage
     void* panel_ptr() { return f32() ? static_cast<void*>(panels_f.p) : static_cast<void*>(panels.p); }
     void* dinv_ptr() { return f32() ? static_cast<void*>(dinv_f.p) : static_cast<void*>(dinv.p); }
 
@@ -631,6 +631,7 @@ SchedArgs sched_args(spx_handle* h)
     a.pl = h->devplan();
     a.panels = h->panel_ptr();
     a.dinv = h->dinv_ptr();
+    a.split = h->opt.precision == SPX_BF16X3_IR ? 1 : 0;
     a.desc = h->desc.p;
     a.rmap = h->rmap.p;
     a.ftab = h->ftab.p;
@@ -747,10 +748,10 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
     if (opt) h->opt = *opt; else spx_default_options(&h->opt);
     int rc = guarded(h, [&]() -> int {
         if (h->opt.method != SPX_LLT) throw InvalidArgument("only SPX_LLT is supported");
-        if (h->opt.precision != SPX_FP64 && h->opt.precision != SPX_FP32_IR)
+        if (h->opt.precision != SPX_FP64 && h->opt.precision != SPX_FP32_IR && h->opt.precision != SPX_BF16X3_IR)
             throw InvalidArgument("unsupported precision");
         if (h->opt.ir_max_iter < -1) throw InvalidArgument("ir_max_iter must be >= 0, or -1 for the default");
-        if (h->opt.ir_max_iter == -1) h->opt.ir_max_iter = h->opt.precision == SPX_FP32_IR ? 10 : 2;
+        if (h->opt.ir_max_iter == -1) h->opt.ir_max_iter = h->opt.precision == SPX_FP64 ? 2 : 10;
         if (h->opt.tile != 0 && h->opt.tile != 1) throw InvalidArgument("tile must be 0 or 1");
         if (h->opt.merge_split < 1 || h->opt.merge_split > 16) throw InvalidArgument("merge_split must be in 1..16");
         h->tile_rows = h->opt.tile == 1 ? 128 : 256;

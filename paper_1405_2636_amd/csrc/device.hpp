@@ -35,8 +35,9 @@ enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2, kSmall = 3 };
 //   {panel offset of j: low word, high word, 0, 0}
 struct SchedArgs {
     DevPlan pl;
-    void* panels;            // double, or float in the FP32 refinement mode
+    void* panels;            // double, or float in the FP32 refinement modes
     void* dinv;              // same element type as the panels
+    int32_t split;           // FP32 panels: update and TRSM products as split-BF16 products
     const int4* desc;
     const int32_t* rmap;     // panel row of k -> row inside panel j, per update pair
     const int4* ftab;        // update tiles of fused small blocks

@@ -230,6 +230,101 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][4], con
     }
 }
 
+// Split-BF16 products (FP32 panels): each FP32 operand x is split into
+// hi = bf16(x) (round to nearest) and lo = bf16(x - hi); the product is
+// hi*hi + hi*lo + lo*hi on the BF16 matrix cores with FP32 accumulation
+// (lo*lo is dropped: relative error about 2^-16 per product).  The inner
+// dimension advances 16 at a time; lane (l%16, l/16) loads its FP32 operands
+// at inner indices 4s + l/16 (s < 4), the order of the FP32 products, and
+// packs them as the 4 BF16 values the 16x16x16 instruction takes from it at
+// 4*(l/16) + s: the same permutation of the inner index for both operands,
+// so the sum is unchanged.  Two raw buffers: the next 16 in flight while the
+// current 16 are split and multiplied (with 32 per step, the 16x16x32 form,
+// the buffers and accumulators exceed the registers and spill).
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16(const float (&v)[4], s16x4& hi, s16x4& lo)
+{
+    bf16x4 h, l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const __bf16 t = (__bf16)v[j];
+        h[j] = t;
+        l[j] = (__bf16)(v[j] - (float)t);
+    }
+    hi = __builtin_bit_cast(s16x4, h);
+    lo = __builtin_bit_cast(s16x4, l);
+}
+
+template <int NB>
+__device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][4], const GOp& X, const GOp& Y, int K)
+{
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nchunks = (K + 15) >> 4;
+    if (nchunks <= 0) return;
+    int xo[4], yo[NB];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) xo[b] = X.off + (16 * b + li) * X.si + lk * X.sk;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) yo[b] = Y.off + (16 * b + li) * Y.si + lk * Y.sk;
+    const int dx = 4 * X.sk, dy = 4 * Y.sk;
+    float xa[4][4], ya[NB][4], xb[4][4], yb[NB][4];
+    auto load = [&](float (&xs)[4][4], float (&ys)[NB][4], int ch) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) xs[b][s] = gload<float>(X, xo[b] + (4 * ch + s) * dx);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) ys[b][s] = gload<float>(Y, yo[b] + (4 * ch + s) * dy);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto mma = [&](const float (&xs)[4][4], const float (&ys)[NB][4]) {
+        s16x4 xh[4], xl[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) split_bf16(xs[b], xh[b], xl[b]);
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            s16x4 yh, yl;
+            split_bf16(ys[bi], yh, yl);
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yh, xh[bj], acc[bi][bj], 0, 0, 0);
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yh, xl[bj], acc[bi][bj], 0, 0, 0);
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yl, xh[bj], acc[bi][bj], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // (reads past the last chunk repeat it and are not used)
+    const int last = nchunks - 1;
+    load(xa, ya, 0);
+    int ch = 0;
+    for (; ch + 2 <= nchunks; ch += 2) {
+        load(xb, yb, ch + 1);
+        mma(xa, ya);
+        load(xa, ya, min(ch + 2, last));
+        mma(xb, yb);
+    }
+    if (ch < nchunks) mma(xa, ya);
+}
+
+// acc += X Y^T over K inner indices: FP64 or FP32 products, or (FP32 panels
+// with the split option) split-BF16 products
+template <int NB, class T>
+__device__ __forceinline__ void tile_gemm(typename MM<T>::acc (&acc)[NB][4], const GOp& X, const GOp& Y, int K, bool split)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (split) {
+            wave_gemm_split<NB>(acc, X, Y, K);
+            return;
+        }
+    }
+    wave_gemm<NB, T>(acc, X, Y, K);
+}
+
 template <int NB, class A>
 __device__ __forceinline__ void zero_acc(A (&acc)[NB][4])
 {
@@ -556,7 +651,8 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
     const int c0 = 64 * wave;
     const int nv = min(64, w - c0);
     if (nv > 0)
-        wave_gemm<4, T>(acc, make_gop(P, ld * w, row0, 1, ld), make_gop(D, (int64_t)w * w, c0, 1, w), min(w, c0 + 64));
+        tile_gemm<4, T>(acc, make_gop(P, ld * w, row0, 1, ld), make_gop(D, (int64_t)w * w, c0, 1, w), min(w, c0 + 64),
+                        a.split != 0);
     __syncthreads();   // every wave has read all of B before any result is written
     if (nv > 0) wave_store<T>(acc, nrows, nv, [&](int r, int c, T v) { B[r + (int64_t)(c0 + c) * ld] = v; });
 }
@@ -596,8 +692,8 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
             const int fp = pl.fcol[p], w = pl.lcol[p] - fp + 1, sh = fk - fp;
             const int64_t ld = pl.stride[p];
             const T* A = static_cast<const T*>(a.panels) + pl.panel_off[p];
-            wave_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld), make_gop(A, ld * w, col0 + c0 + sh, 1, ld),
-                            w);
+            tile_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld), make_gop(A, ld * w, col0 + c0 + sh, 1, ld),
+                            w, a.split != 0);
         }
         wave_store<T>(acc, mv, nv, [&](int r, int c, T v) {
             const int tr = rpos[r0 + r], tc = cpos[c0 + c];

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspx.so")
 
 SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ESTATE, SPX_ENOTPD, SPX_ENOCONV = 0, -1, -2, -3, -4, -5, -6
-PRECISIONS = {"fp64": 0, "fp32_ir": 1}   # enum spx_precision
+PRECISIONS = {"fp64": 0, "fp32_ir": 1, "bf16x3_ir": 2}   # enum spx_precision
 
 
 class SpxError(RuntimeError):
@@ -133,9 +133,10 @@ class Solver:
 
     colptr/rowind: CSC pattern (host arrays, full symmetric pattern or its lower
     triangle).  values passed to factorize are aligned with the pattern.
-    precision: "fp64" (FP64 factor) or "fp32_ir" (FP32 factor, FP64 residual
-    and refinement).  ir_max_iter None: the library's default for the
-    precision (2 for fp64, 10 for fp32_ir).
+    precision: "fp64" (FP64 factor), "fp32_ir" (FP32 factor, FP64 residual
+    and refinement) or "bf16x3_ir" (FP32 factor whose update products are
+    split-BF16 products, FP64 refinement).  ir_max_iter None: the library's
+    default for the precision (2 for fp64, 10 otherwise).
     """
 
     def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,

@@ -194,20 +194,21 @@ def test_solve_before_factorize(torch):
 # oracle's FP64 solution to within kappa * omega.
 
 U32 = 2.0 ** -24
+USPLIT = 2.0 ** -16   # split-BF16 products: hi*hi + hi*lo + lo*hi
 
 
-def _fp32_bound(orc, sym, F, p):
+def _fp32_bound(orc, sym, F, p, u=U32):
     ri, ci, v = orc.unpack(sym, F)
     L = sp.csc_matrix((v, (ri, ci)), shape=(p.n, p.n))
     m = int(np.max(np.diff(L.indptr)))
-    g = (m + 1) * U32 / (1 - (m + 1) * U32)
+    g = (m + 1) * u / (1 - (m + 1) * u)
     absL = abs(L)
     return g * sp.linalg.norm(absL @ absL.T)
 
 
-def _check_fp32(orc, torch, p, nrhs=1, **kw):
-    print("fp32 case n=%d nnz=%d opts=%s" % (p.n, p.nnz, kw), flush=True)
-    s, F = _gpu_factor(torch, p, precision="fp32_ir", **kw)
+def _check_fp32(orc, torch, p, nrhs=1, precision="fp32_ir", **kw):
+    print("%s case n=%d nnz=%d opts=%s" % (precision, p.n, p.nnz, kw), flush=True)
+    s, F = _gpu_factor(torch, p, precision=precision, **kw)
     sym, P = _oracle(orc, p, **kw)
     ri, ci, v = orc.unpack(sym, F)
     L = sp.csc_matrix((v, (ri, ci)), shape=(p.n, p.n))
@@ -215,7 +216,7 @@ def _check_fp32(orc, torch, p, nrhs=1, **kw):
     PA = A[sym.perm][:, sym.perm]
     # the stored factor is FP32: every entry is exactly a float
     assert np.array_equal(F, F.astype(np.float32).astype(np.float64))
-    assert sp.linalg.norm(PA - L @ L.T) <= _fp32_bound(orc, sym, F, p)
+    assert sp.linalg.norm(PA - L @ L.T) <= _fp32_bound(orc, sym, F, p, USPLIT if precision == "bf16x3_ir" else U32)
     B = rhs(p.n, nrhs, 77)
     b = torch.tensor(np.ascontiguousarray(B.T), device="cuda")
     if nrhs == 1:
@@ -311,3 +312,20 @@ def test_merged_split_updates(orc, torch, merge):
 
 def test_fp32_ir_merged_split_updates(orc, torch):
     _check_fp32(orc, torch, grid_laplacian((18, 17, 16), shift=1e-3), split_width=32, merge_split=4)
+
+
+@pytest.mark.parametrize("case", ["config1", "grid3", "rand", "merged"])
+def test_bf16x3_ir_parity(orc, torch, case):
+    # FP32 factor with split-BF16 update and panel-solve products: the factor
+    # residual within the Cholesky bound at u = 2^-16, the refined solution
+    # at omega <= 1e-14 and equal to the oracle's to 1e-10
+    if case == "config1":
+        _check_fp32(orc, torch, make_config(1), precision="bf16x3_ir")
+    elif case == "grid3":
+        _check_fp32(orc, torch, grid_laplacian((20, 20, 20), shift=1e-3), nrhs=2, precision="bf16x3_ir")
+    elif case == "rand":
+        _check_fp32(orc, torch, random_spd(1500, 0.003, 7), nrhs=3, precision="bf16x3_ir", amalg_pct=40,
+                    split_width=64)
+    else:
+        _check_fp32(orc, torch, grid_laplacian((18, 17, 16), shift=1e-3), precision="bf16x3_ir", split_width=32,
+                    merge_split=4)
