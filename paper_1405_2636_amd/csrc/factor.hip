@@ -470,8 +470,8 @@ __device__ __forceinline__ void wave_mm(typename MM<T>::acc (&acc)[NB][4], LX ld
 // stores are unconditional, masked elements going to an offset past the
 // array where the hardware drops them: with a branch there the compiler
 // sinks the loads of the old values into it, one round trip per element.
-template <int NB, class T, class LX, class LY, class Keep, class F>
-__device__ __forceinline__ void wave_mm_rmw(LX ldx, LY ldy, int mv, int nv, const GOp& C, Keep keep, F f)
+template <int NB, class T, class LX, class LY, class Keep, class F, class Also>
+__device__ __forceinline__ void wave_mm_rmw(LX ldx, LY ldy, int mv, int nv, const GOp& C, Keep keep, F f, Also also)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -501,8 +501,11 @@ __device__ __forceinline__ void wave_mm_rmw(LX ldx, LY ldy, int mv, int nv, cons
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                gstore_s(C, voff(bi, bj, v), soff(bi, bj, v), f(old[bi][bj][v], acc[bi][bj][v]));
+            for (int v = 0; v < 4; ++v) {
+                const T nv_ = f(old[bi][bj][v], acc[bi][bj][v]);
+                gstore_s(C, voff(bi, bj, v), soff(bi, bj, v), nv_);
+                also(16 * bj + li, 16 * bi + MM<T>::drow(v, lk), nv_);
+            }
 }
 
 constexpr int kPbLd = 228;   // leading dimension of the LDS copy of the rows below a tile (<= 224 rows)
@@ -533,19 +536,25 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
     const int64_t nA = ld * w, nD = (int64_t)w * w;
     const GOp gA = make_gop(A, nA, 0, 1, ld);   // A(i, p) at i + p*ld
     const GOp gD = make_gop(D, nD, 0, 1, w);
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     double* bc = Lt + kNB * 33;
+    __shared__ int s_next;   // next trailing tile to deal
+    bool ready = false;      // Lt/Dt already hold this step's factored tile
     for (int J = 0; J < w; J += kNB) {
         const int jb = min(kNB, w - J);
         const int R = w - J - jb;   // rows below the tile inside the block
-        // 1. tile (identity padded) -> Lt; factor and invert
-        for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
-            const int r = idx & 31, c = idx >> 5;
-            Lt[r + c * 33] = (r < jb && c < jb) ? (c <= r ? (double)A[(J + r) + (int64_t)(J + c) * ld] : 0.0)
-                                                : (r == c ? 1.0 : 0.0);
+        // 1. tile (identity padded) -> Lt; factor and invert (done ahead,
+        // during the previous step's trailing updates, from the second step on)
+        if (!ready) {
+            for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
+                const int r = idx & 31, c = idx >> 5;
+                Lt[r + c * 33] = (r < jb && c < jb) ? (c <= r ? (double)A[(J + r) + (int64_t)(J + c) * ld] : 0.0)
+                                                    : (r == c ? 1.0 : 0.0);
+            }
+            __syncthreads();
+            if (wave == 0) tile_chol_inv<T>(Lt, bc, Dt, jb, f + J, a.status);
         }
-        __syncthreads();
-        if (wave == 0) tile_chol_inv<T>(Lt, bc, Dt, jb, f + J, a.status);
+        if (tid == 0) s_next = 0;
         __syncthreads();
         for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
             const int r = idx & 31, c = idx >> 5;
@@ -584,12 +593,21 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
         __syncthreads();
         if (R == 0) break;
         // 3. trailing updates: syrk tiles (rt, ct) with ct*32 < rt*64 + 64,
-        // then inverse tiles (rt, ct), ct*32 < J + jb
+        // then inverse tiles (rt, ct), ct*32 < J + jb, dealt to the waves one
+        // at a time.  Tile 0 holds the whole next diagonal tile: the wave that
+        // takes it also writes the tile's new lower entries (identity padded)
+        // to Lt and then factors and inverts it, while the other waves go on
+        // with the remaining tiles.
         const int nrt = (R + 63) >> 6, ncs = (R + 31) >> 5, nci = (J + jb + 31) >> 5;
         int nsyrk = 0;
         for (int rt = 0; rt < nrt; ++rt) nsyrk += min(ncs, 2 * rt + 2);
         const int ntiles = nsyrk + nrt * nci;
-        for (int t = wave; t < ntiles; t += kThreads / 64) {
+        const int jn = min(kNB, R);   // width of the next tile
+        for (;;) {
+            int t = 0;
+            if (lane == 0) t = atomicAdd(&s_next, 1);
+            t = __shfl(t, 0);
+            if (t >= ntiles) break;
             int rt = 0, ct = t;
             const bool syrk = t < nsyrk;
             if (syrk) {
@@ -608,9 +626,22 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                 const int nv = min(32, R - c0);
                 GOp cA = gA;
                 cA.off = uni(gA.off + (J + jb + i0) * gA.si + (J + jb + c0) * gA.sk);
-                wave_mm_rmw<2, T>(
-                    ldx, [&](int c, int p) { return Pb[(c0 + c) + p * kPbLd]; }, mv, nv, cA,
-                    [&](int r, int c) { return i0 + r >= c0 + c; }, sub);
+                if (t == 0) {
+                    for (int idx = lane; idx < kNB * kNB; idx += 64) {
+                        const int r = idx & 31, c = idx >> 5;
+                        Lt[r + c * 33] = r == c && r >= jn ? 1.0 : 0.0;
+                    }
+                    wave_mm_rmw<2, T>(
+                        ldx, [&](int c, int p) { return Pb[(c0 + c) + p * kPbLd]; }, mv, nv, cA,
+                        [&](int r, int c) { return r >= c; }, sub, [&](int r, int c, T v) {
+                            if (r < jn && c < jn && c <= r) Lt[r + c * 33] = (double)v;
+                        });
+                    tile_chol_inv<T>(Lt, bc, Dt, jn, f + J + jb, a.status);
+                } else {
+                    wave_mm_rmw<2, T>(
+                        ldx, [&](int c, int p) { return Pb[(c0 + c) + p * kPbLd]; }, mv, nv, cA,
+                        [&](int r, int c) { return i0 + r >= c0 + c; }, sub, [](int, int, T) {});
+                }
             } else {
                 const int nv = min(32, J + jb - c0);
                 auto ldy = [&](int c, int p) { return gload<T>(gD, gD.off + (J + p) * gD.si + (c0 + c) * gD.sk); };
@@ -623,11 +654,12 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                 } else {
                     GOp cD = gD;
                     cD.off = uni(gD.off + (J + jb + i0) * gD.si + c0 * gD.sk);
-                    wave_mm_rmw<2, T>(ldx, ldy, mv, nv, cD, [](int, int) { return true; }, sub);
+                    wave_mm_rmw<2, T>(ldx, ldy, mv, nv, cD, [](int, int) { return true; }, sub, [](int, int, T) {});
                 }
             }
         }
         __syncthreads();
+        ready = true;
     }
 }
 
