@@ -354,8 +354,10 @@ void build_tasks(spx_handle* h)
     for (int32_t k = 0; k < nc; ++k) {
         const int32_t w = P.lcol[k] - P.fcol[k] + 1, ld = P.stride[k];
         tf[k] = id;
-        for (int32_t r = w; r < ld && !small[k]; r += kTrsmRows) {
-            desc.push_back(int4{kTrsm, k, r, std::min(kTrsmRows, ld - r)});
+        // 64 rows per wave tile; panels narrower than 256 columns stack 4/ceil(w/64) of them
+        const int32_t trows = kTrsmRows * (4 / ((w + 63) / 64));
+        for (int32_t r = w; r < ld && !small[k]; r += trows) {
+            desc.push_back(int4{kTrsm, k, r, std::min(trows, ld - r)});
             desc.push_back(int4{0, 0, 0, 0});
             ++id;
         }

@@ -25,7 +25,7 @@ enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2, kSmall = 3 };
 
 // Two int4 per item: {kind, k, a, b}, {c, d, e, f}
 //   kFact:   k
-//   kTrsm:   k, row0 = first panel row, nrows (<= 64)
+//   kTrsm:   k, row0 = first panel row, nrows (<= 64 * (4 / ceil(w / 64)))
 //   kUpdate: k (source), j (target), row0 (first source panel row);
 //            mrows, col0 (first facing panel row), ncols, mbase (row-map base)
 //   kSmall:  k; first tile of k in the fused-tile table, tile count, first

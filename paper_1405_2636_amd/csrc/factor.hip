@@ -664,7 +664,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
 }
 
 // ---------------------------------------------------------------- TRSM(k, rows)
-// Rows [row0, row0+nrows) (nrows <= 64) of panel k below its diagonal block
+// Rows [row0, row0+nrows) (nrows <= 64 * (4 / ceil(w / 64))) of panel k below its diagonal block
 // are replaced by B L_kk^{-T} = B D^T.  Wave v computes the 64 output columns
 // starting at 64v; the inner range stops at the diagonal of the lower
 // triangular D.
@@ -680,13 +680,21 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
     const int wave = threadIdx.x >> 6;
     typename MM<T>::acc acc[4][4];
     zero_acc(acc);
-    const int c0 = 64 * wave;
+    // 64x64 wave tiles: ncb column blocks of the output, and 4/ncb blocks of
+    // 64 rows (a chunk has 64 * (4/ncb) rows), so narrow panels keep all four
+    // waves busy
+    const int ncb = (w + 63) >> 6, nrb = 4 / ncb;
+    const int cb = wave % ncb, rb = wave / ncb;
+    const int c0 = 64 * cb, r0 = 64 * rb;
     const int nv = min(64, w - c0);
-    if (nv > 0)
-        tile_gemm<4, T>(acc, make_gop(P, ld * w, row0, 1, ld), make_gop(D, (int64_t)w * w, c0, 1, w), min(w, c0 + 64),
-                        a.split != 0);
+    const bool on = rb < nrb && nv > 0 && r0 < nrows;
+    if (on)
+        tile_gemm<4, T>(acc, make_gop(P, ld * w, row0 + r0, 1, ld), make_gop(D, (int64_t)w * w, c0, 1, w),
+                        min(w, c0 + 64), a.split != 0);
     __syncthreads();   // every wave has read all of B before any result is written
-    if (nv > 0) wave_store<T>(acc, nrows, nv, [&](int r, int c, T v) { B[r + (int64_t)(c0 + c) * ld] = v; });
+    if (on)
+        wave_store<T>(acc, min(64, nrows - r0), nv,
+                      [&](int r, int c, T v) { B[(r0 + r) + (int64_t)(c0 + c) * ld] = v; });
 }
 
 // ---------------------------------------------------------------- UPDATE

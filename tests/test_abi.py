@@ -57,6 +57,14 @@ def test_bad_options():
         Solver(p.n, p.colptr, p.rowind, split_width=300)
     with pytest.raises(SpxError):
         Solver(p.n, p.colptr, p.rowind, user_perm=np.zeros(p.n, np.int32))
+    for kw in [dict(merge_split=0), dict(merge_split=17), dict(tile=2)]:
+        with pytest.raises(SpxError):
+            Solver(p.n, p.colptr, p.rowind, **kw)
+    with pytest.raises(ValueError):
+        Solver(p.n, p.colptr, p.rowind, precision="bf16")
+    # every precision mode and option set in range is accepted at analysis
+    for prec in ["fp64", "fp32_ir", "bf16x3_ir"]:
+        Solver(p.n, p.colptr, p.rowind, precision=prec, merge_split=16, fuse_small=False, tile=1)
 
 
 def test_null_safety():

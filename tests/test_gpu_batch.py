@@ -25,7 +25,7 @@ def _oracle_x(orc, p, values, b):
     return x[:, 0]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir", "bf16x3_ir"])
 def test_batch_parity_with_graph_replays(orc, torch, precision):
     ps = grid_batch(40, seed=11, lo=6, hi=48)
     print("batch of %d systems, n=%d, %s" % (len(ps), sum(p.n for p in ps), precision), flush=True)
