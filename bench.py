@@ -202,7 +202,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the build is single-GPU (see DESIGN.md on sharding)", file=sys.stderr)
+        print("bench.py runs on one GPU only (no multi-GPU path: the factorization and its queue live on one device)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
