@@ -166,6 +166,33 @@ def test_not_positive_definite(orc, torch, seed):
     s.factorize(torch.tensor(p.values, device="cuda"))
 
 
+@pytest.mark.parametrize("pos", [40, 150, 199])
+def test_not_positive_definite_late_column(orc, torch, pos):
+    # one dense column block of width 200 (seven 32-column steps; from the
+    # second step on each tile is factored ahead, during the previous step):
+    # the pivot that fails at elimination position `pos` is the one reported
+    from gen.stencils import Problem
+    from paper_1405_2636_amd import NotPositiveDefinite, Solver
+    rng = np.random.default_rng(pos)
+    n = 200
+    M = rng.uniform(-1, 1, (n, n))
+    Ac = sp.csc_matrix(M @ M.T / n + np.eye(n))
+    p = Problem(n, Ac.indptr.astype(np.int64), Ac.indices.astype(np.int32), Ac.data.copy())
+    sym = orc.analyze(p.n, p.colptr, p.rowind)
+    victim = int(sym.perm[pos])
+    vals = p.values.copy()
+    cols = np.repeat(np.arange(n), np.diff(p.colptr))
+    vals[(p.rowind == victim) & (cols == victim)] = -5.0
+    with pytest.raises(orc.NotPositiveDefinite) as eo:
+        orc.factor(sym, p.colptr, p.rowind, vals)
+    assert eo.value.col_orig == victim
+    for prec in ["fp64", "fp32_ir"]:
+        s = Solver(p.n, p.colptr, p.rowind, precision=prec)
+        with pytest.raises(NotPositiveDefinite) as eg:
+            s.factorize(torch.tensor(vals, device="cuda"))
+        assert eg.value.col == victim, prec
+
+
 def test_nan_input(torch):
     p = grid_laplacian((10, 10))
     vals = p.values.copy()
