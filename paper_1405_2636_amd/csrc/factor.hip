@@ -10,16 +10,21 @@
 // tiled, and all of them are scheduled by one persistent kernel that pulls
 // work items from device-side ready queues:
 //   FACT(k)          Cholesky of the diagonal block and its inverse L_kk^{-1}
-//   TRSM(k, rows)    64 off-diagonal rows of panel k times L_kk^{-T}
-//   UPDATE(k,j,r,c)  a 128x128 (or 256x64) tile of the outer product of panel
-//                    k, subtracted into panel j with FP64 atomics
+//   TRSM(k, rows)    64, 128 or 256 off-diagonal rows of panel k times
+//                    L_kk^{-T}
+//   UPDATE(k,j,r,c)  a 256x64 (or 128x128) tile of the outer product of panel
+//                    k, subtracted into panel j with atomics; for a group of
+//                    pieces of a split supernode, the sum of their products
+//   SMALL(k)         a narrow column block (width <= 32, <= 128 rows): all
+//                    three steps and every update tile of the block at once
 // Dependencies are counters: FACT(j) becomes ready when every UPDATE tile
 // into j is done, the TRSM tiles of k when FACT(k) is done, the UPDATE tiles
 // of k when its last TRSM tile is done.  FACT, TRSM and the updates into the
 // first facing block go to a high-priority queue that workers poll first.
 // Products run on the matrix cores: v_mfma_f64_16x16x4f64 for the FP64
 // factor, v_mfma_f32_16x16x4f32 for the FP32 factor of the refinement mode
-// (whose 32x32 diagonal tiles are still factored and inverted in FP64).
+// (whose 32x32 diagonal tiles are still factored and inverted in FP64), and
+// split-BF16 products (v_mfma_f32_16x16x16_bf16) in the split mode.
 #include "device.hpp"
 
 namespace spx {

@@ -9,6 +9,9 @@
 //   t_k  = L_k,off^T x[rows of k]         (64-row chunks)
 //   x_k  = L_kk^{-T} (z_k - t_k)
 // Both use the inverse of each diagonal block kept by the factorization.
+// Column blocks of width <= 32 with at most 128 panel rows take both halves
+// of a step in one kernel per level, a group of 16 lanes per block
+// (fwd_small, bwd_small).
 // Every sweep step writes a different vector than it reads (y -> z -> x), so
 // a diagonal block can be spread over several workgroups.  Every dot product
 // is split over four lanes (interleaved inner indices) and combined by two
