@@ -79,6 +79,12 @@ def _load():
     L.orc_logdet.argtypes = [vp, vp]
     L.orc_unpack.restype = i64
     L.orc_unpack.argtypes = [vp, vp, vp, vp, vp]
+    L.orc_factor_ldlt.restype = C.c_int
+    L.orc_factor_ldlt.argtypes = [vp, vp, C.POINTER(i32)]
+    L.orc_solve_ldlt.restype = C.c_int
+    L.orc_solve_ldlt.argtypes = [vp, vp, i32, vp, i64, vp, i64]
+    L.orc_logabsdet_ldlt.restype = dbl
+    L.orc_logabsdet_ldlt.argtypes = [vp, vp, C.POINTER(i32)]
     _lib = L
     return L
 
@@ -246,6 +252,44 @@ def factor_upto(sym: Symbolic, colptr, rowind, values, kend):
     if rc != 0:
         raise RuntimeError("orc_factor_upto failed %d" % rc)
     return P
+
+
+class ZeroPivot(RuntimeError):
+    def __init__(self, col_new, col_orig):
+        super().__init__("zero or non-finite pivot at column %d (original %d)" % (col_new, col_orig))
+        self.col_new = col_new
+        self.col_orig = col_orig
+
+
+def factor_ldlt(sym: Symbolic, colptr, rowind, values):
+    """Assemble and factor as L D L^T (static pivoting: the analysis' order);
+    returns the panel array: D on the diagonal of each diagonal block, the
+    strictly lower entries of the unit lower L elsewhere."""
+    L = _load()
+    P = assemble(sym, colptr, rowind, values)
+    fc = C.c_int32(-1)
+    rc = L.orc_factor_ldlt(C.c_void_p(sym.handle), _p(P), C.byref(fc))
+    if rc == ENOTPD:
+        raise ZeroPivot(fc.value, int(sym.perm[fc.value]))
+    if rc != 0:
+        raise RuntimeError("orc_factor_ldlt failed %d" % rc)
+    return P
+
+
+def solve_ldlt(sym: Symbolic, P, b):
+    L = _load()
+    b = np.asfortranarray(np.asarray(b, np.float64).reshape(sym.n, -1))
+    x = np.zeros_like(b, order="F")
+    L.orc_solve_ldlt(C.c_void_p(sym.handle), _p(P), b.shape[1], _p(b), sym.n, _p(x), sym.n)
+    return x
+
+
+def logabsdet_ldlt(sym: Symbolic, P):
+    """(log |det A|, number of negative pivots) of an L D L^T factor."""
+    L = _load()
+    nneg = C.c_int32(0)
+    v = L.orc_logabsdet_ldlt(C.c_void_p(sym.handle), _p(P), C.byref(nneg))
+    return v, nneg.value
 
 
 def solve(sym: Symbolic, P, b):

@@ -908,6 +908,157 @@ int orc_factor_upto(const orc_sym* s, double* P, i32 kend, i32* fail_col)
 }
 
 /*
+ * Right-looking supernodal L D L^T, the symmetric-indefinite variant of the
+ * same method (static pivoting: the elimination order is the analysis'
+ * order, no pivoting at factorization time).  Same steps and order as the
+ * LL^T factorization above:
+ *   1. L D L^T of the diagonal block, column by column:
+ *        d_c  = a_cc - sum_{p<c} l_cp d_p l_cp,
+ *        l_rc = (a_rc - sum_{p<c} l_rp d_p l_cp) / d_c   (r > c);
+ *      breakdown when a pivot is zero or not finite;
+ *   2. the off-diagonal rows by the same formula for l_rc;
+ *   3. every facing panel j gets W = L_rows D L_facing^T subtracted.
+ * Storage: D on the diagonal of each diagonal block, the strictly lower
+ * entries of L (unit diagonal implied) below it and in the off-diagonal
+ * rows.  Returns ORC_ENOTPD and the failing column on breakdown.
+ */
+int orc_factor_ldlt(const orc_sym* s, double* P, i32* fail_col)
+{
+    *fail_col = -1;
+    i32 maxs = 0;
+    for (i32 k = 0; k < s->ncblk; k++) if (s->stride[k] > maxs) maxs = s->stride[k];
+    double* W = (double*)malloc(sizeof(double) * (size_t)maxs * (size_t)maxs + 8);
+    i32* grow = (i32*)malloc(sizeof(i32) * ((size_t)maxs + 1));
+    if (!W || !grow) return ORC_ENOMEM;
+    for (i32 k = 0; k < s->ncblk; k++) {
+        i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k];
+        double* L = P + s->panel_off[k];
+        for (i32 b = s->bptr[k]; b < s->bptr[k + 1]; b++)
+            for (i32 r = s->frow[b]; r <= s->lrow[b]; r++) grow[s->coefind[b] + r - s->frow[b]] = r;
+        /* 1. diagonal block; 2. the rows below use the same formula */
+        for (i32 c = 0; c < wd; c++) {
+            double d = L[c + (i64)c * ld];
+            for (i32 p = 0; p < c; p++) d -= L[c + (i64)p * ld] * L[p + (i64)p * ld] * L[c + (i64)p * ld];
+            if (!(d != 0.0) || !isfinite(d)) { *fail_col = s->fcol[k] + c; free(W); free(grow); return ORC_ENOTPD; }
+            L[c + (i64)c * ld] = d;
+            for (i32 r = c + 1; r < ld; r++) {
+                double v = L[r + (i64)c * ld];
+                for (i32 p = 0; p < c; p++) v -= L[r + (i64)p * ld] * L[p + (i64)p * ld] * L[c + (i64)p * ld];
+                L[r + (i64)c * ld] = v / d;
+            }
+        }
+        /* 3. updates of the facing panels: W = L_rows D L_facing^T */
+        for (i32 b = s->bptr[k] + 1; b < s->bptr[k + 1];) {
+            i32 j = s->fcblk[b];
+            i32 b2 = b;
+            while (b2 < s->bptr[k + 1] && s->fcblk[b2] == j) b2++;
+            i32 rs = s->coefind[b];
+            i32 nf = s->coefind[b2 - 1] + (s->lrow[b2 - 1] - s->frow[b2 - 1] + 1) - rs;
+            i32 m = ld - rs;
+            for (i32 q = 0; q < nf; q++)
+                for (i32 i = 0; i < m; i++) {
+                    double acc = 0.0;
+                    for (i32 p = 0; p < wd; p++)
+                        acc += L[rs + i + (i64)p * ld] * L[p + (i64)p * ld] * L[rs + q + (i64)p * ld];
+                    W[i + (i64)q * m] = acc;
+                }
+            double* T = P + s->panel_off[j];
+            i32 ldj = s->stride[j];
+            for (i32 q = 0; q < nf; q++) {
+                i32 gc = grow[rs + q];
+                i32 tc = gc - s->fcol[j];
+                for (i32 i = 0; i < m; i++) {
+                    i32 gr = grow[rs + i];
+                    if (gr < gc) continue;
+                    i32 pos = row_pos(s, j, gr);
+                    if (pos < 0) { free(W); free(grow); return ORC_EINVAL; }
+                    T[(i64)tc * ldj + pos] -= W[i + (i64)q * m];
+                }
+            }
+            b = b2;
+        }
+    }
+    free(W);
+    free(grow);
+    return ORC_OK;
+}
+
+/*
+ * x = A^{-1} b with an L D L^T factor: permute, forward sweep with the unit
+ * lower L, division by D, backward sweep with L^T, permute back.
+ */
+int orc_solve_ldlt(const orc_sym* s, const double* P, i32 nrhs, const double* B, i64 ldb, double* X, i64 ldx)
+{
+    double* Y = (double*)malloc(sizeof(double) * (size_t)s->n * (size_t)(nrhs > 0 ? nrhs : 1) + 8);
+    if (!Y) return ORC_ENOMEM;
+    for (i32 r = 0; r < nrhs; r++)
+        for (i32 i = 0; i < s->n; i++) Y[(i64)r * s->n + i] = B[(i64)r * ldb + s->perm[i]];
+    for (i32 rhs = 0; rhs < nrhs; rhs++) {
+        double* y = Y + (i64)rhs * s->n;
+        for (i32 k = 0; k < s->ncblk; k++) {
+            i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k], f = s->fcol[k];
+            const double* L = P + s->panel_off[k];
+            for (i32 c = 0; c < wd; c++) {
+                double v = y[f + c];
+                for (i32 p = 0; p < c; p++) v -= L[c + (i64)p * ld] * y[f + p];
+                y[f + c] = v;
+            }
+            for (i32 b = s->bptr[k] + 1; b < s->bptr[k + 1]; b++)
+                for (i32 r = s->frow[b]; r <= s->lrow[b]; r++) {
+                    i32 pr = s->coefind[b] + r - s->frow[b];
+                    double acc = 0.0;
+                    for (i32 c = 0; c < wd; c++) acc += L[pr + (i64)c * ld] * y[f + c];
+                    y[r] -= acc;
+                }
+        }
+        for (i32 k = 0; k < s->ncblk; k++) {
+            i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k], f = s->fcol[k];
+            const double* L = P + s->panel_off[k];
+            for (i32 c = 0; c < wd; c++) y[f + c] /= L[c + (i64)c * ld];
+        }
+        for (i32 k = s->ncblk - 1; k >= 0; k--) {
+            i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k], f = s->fcol[k];
+            const double* L = P + s->panel_off[k];
+            for (i32 c = 0; c < wd; c++) {
+                double acc = 0.0;
+                for (i32 b = s->bptr[k] + 1; b < s->bptr[k + 1]; b++)
+                    for (i32 r = s->frow[b]; r <= s->lrow[b]; r++)
+                        acc += L[s->coefind[b] + r - s->frow[b] + (i64)c * ld] * y[r];
+                y[f + c] -= acc;
+            }
+            for (i32 c = wd - 1; c >= 0; c--) {
+                double v = y[f + c];
+                for (i32 p = c + 1; p < wd; p++) v -= L[p + (i64)c * ld] * y[f + p];
+                y[f + c] = v;
+            }
+        }
+    }
+    for (i32 r = 0; r < nrhs; r++)
+        for (i32 i = 0; i < s->n; i++) X[(i64)r * ldx + s->perm[i]] = Y[(i64)r * s->n + i];
+    free(Y);
+    return ORC_OK;
+}
+
+/* log |det A| = sum log |d_j| (pairwise) and the number of negative pivots. */
+static double pairwise(const double* v, i64 n);
+double orc_logabsdet_ldlt(const orc_sym* s, const double* P, i32* nneg)
+{
+    double* t = (double*)malloc(sizeof(double) * ((size_t)s->n + 1));
+    *nneg = 0;
+    for (i32 k = 0; k < s->ncblk; k++) {
+        i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k];
+        for (i32 c = 0; c < wd; c++) {
+            double d = P[s->panel_off[k] + c + (i64)c * ld];
+            if (d < 0.0) (*nneg)++;
+            t[s->fcol[k] + c] = log(fabs(d));
+        }
+    }
+    double r = pairwise(t, s->n);
+    free(t);
+    return r;
+}
+
+/*
  * Solve L L^T y = c in the final numbering, in place, for nrhs columns of
  * length n with leading dimension ldy.  Forward sweep in ascending block
  * order (diagonal solve, then subtract the off-diagonal products from the
