@@ -908,10 +908,11 @@ int orc_factor_upto(const orc_sym* s, double* P, i32 kend, i32* fail_col)
 }
 
 /*
- * Right-looking supernodal L D L^T, the symmetric-indefinite variant of the
- * same method (static pivoting: the elimination order is the analysis'
- * order, no pivoting at factorization time).  Same steps and order as the
- * LL^T factorization above:
+ * Right-looking supernodal L D L^T, the variant of the same method that
+ * Section III names (no dynamic pivoting: the elimination order is the
+ * analysis' order).  Same steps and order as the LL^T factorization above,
+ * with D applied inside each update product (one of the two update forms
+ * Section V compares):
  *   1. L D L^T of the diagonal block, column by column:
  *        d_c  = a_cc - sum_{p<c} l_cp d_p l_cp,
  *        l_rc = (a_rc - sum_{p<c} l_rp d_p l_cp) / d_c   (r > c);
