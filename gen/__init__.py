@@ -12,5 +12,6 @@ from .stencils import (  # noqa: F401
     rhs,
     weighted_grid,
     grid_batch,
+    convection_diffusion,
     CONFIG_NAMES,
 )

@@ -93,6 +93,37 @@ def grid_laplacian(dims, diag: float | None = None, shift: float = 0.0, offdiag:
                    meta={"dims": dims, "diag": diag, "offdiag": offdiag, "shift": shift})
 
 
+def convection_diffusion(dims, seed: int, cmax: float = 0.5) -> Problem:
+    """Unsymmetric 7-point (3-D) or 5-point (2-D) convection-diffusion
+    stencil: for every cell i and axis d a convection coefficient
+    b ~ uniform[-cmax, cmax] (drawn per cell, axis by axis), a_{i,i+e_d} =
+    -1 + b/2, a_{i,i-e_d} = -1 - b/2 (central differences), a_ii = 2 * ndim;
+    out-of-grid neighbours are dropped.  With cmax <= 2 every interior row
+    is weakly diagonally dominant (sum of the off-diagonal magnitudes equal
+    to a_ii) and every boundary row strictly, so the matrix is irreducibly
+    diagonally dominant; the pattern is symmetric, the values are not."""
+    dims = tuple(int(d) for d in dims)
+    nd = len(dims)
+    n = int(np.prod(dims))
+    rng = np.random.default_rng(seed)
+    coords = np.indices(dims[::-1]).reshape(nd, -1)[::-1]
+    idx = np.arange(n, dtype=np.int64)
+    rows, cols, vals = [idx], [idx], [np.full(n, 2.0 * nd)]
+    stride = 1
+    for d in range(nd):
+        bconv = rng.uniform(-cmax, cmax, n)
+        up = coords[d] < dims[d] - 1
+        dn = coords[d] > 0
+        a = idx[up]
+        rows.append(a); cols.append(a + stride); vals.append(-1.0 + 0.5 * bconv[up])
+        a = idx[dn]
+        rows.append(a); cols.append(a - stride); vals.append(-1.0 - 0.5 * bconv[dn])
+        stride *= dims[d]
+    colptr, rowind, values = _coo_to_csc(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+    return Problem(n, colptr, rowind, values, name="convdiff%dd_%s" % (nd, "x".join(map(str, dims))),
+                   meta={"dims": dims, "cmax": cmax, "seed": seed})
+
+
 def random_pattern(n: int, density: float, seed: int):
     """Random symmetric pattern (with the full diagonal) as CSC index arrays."""
     rng = np.random.default_rng(seed)

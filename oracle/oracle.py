@@ -85,6 +85,14 @@ def _load():
     L.orc_solve_ldlt.argtypes = [vp, vp, i32, vp, i64, vp, i64]
     L.orc_logabsdet_ldlt.restype = dbl
     L.orc_logabsdet_ldlt.argtypes = [vp, vp, C.POINTER(i32)]
+    L.orc_assemble_lu.restype = C.c_int
+    L.orc_assemble_lu.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.orc_factor_lu.restype = C.c_int
+    L.orc_factor_lu.argtypes = [vp, vp, vp, C.POINTER(i32)]
+    L.orc_solve_lu.restype = C.c_int
+    L.orc_solve_lu.argtypes = [vp, vp, vp, i32, vp, i64, vp, i64]
+    L.orc_logabsdet_lu.restype = dbl
+    L.orc_logabsdet_lu.argtypes = [vp, vp, C.POINTER(i32)]
     _lib = L
     return L
 
@@ -289,6 +297,43 @@ def logabsdet_ldlt(sym: Symbolic, P):
     L = _load()
     nneg = C.c_int32(0)
     v = L.orc_logabsdet_ldlt(C.c_void_p(sym.handle), _p(P), C.byref(nneg))
+    return v, nneg.value
+
+
+def factor_lu(sym: Symbolic, colptr, rowind, values):
+    """Assemble both triangles and factor as L U (static pivoting: the
+    analysis' order on the pattern of A + A^T); returns (PL, PU): PL holds
+    the diagonal blocks' L (strictly lower) and U (upper) and L below them,
+    PU holds U^T below the diagonal blocks."""
+    L = _load()
+    PL = np.zeros(max(int(sym.stats["panel_size"]), 1), np.float64)
+    PU = np.zeros_like(PL)
+    rc = L.orc_assemble_lu(C.c_void_p(sym.handle), _p(_c(colptr, np.int64)), _p(_c(rowind, np.int32)),
+                           _p(_c(values, np.float64)), _p(PL), _p(PU))
+    if rc != 0:
+        raise ValueError("assemble_lu failed")
+    fc = C.c_int32(-1)
+    rc = L.orc_factor_lu(C.c_void_p(sym.handle), _p(PL), _p(PU), C.byref(fc))
+    if rc == ENOTPD:
+        raise ZeroPivot(fc.value, int(sym.perm[fc.value]))
+    if rc != 0:
+        raise RuntimeError("orc_factor_lu failed %d" % rc)
+    return PL, PU
+
+
+def solve_lu(sym: Symbolic, PL, PU, b):
+    L = _load()
+    b = np.asfortranarray(np.asarray(b, np.float64).reshape(sym.n, -1))
+    x = np.zeros_like(b, order="F")
+    L.orc_solve_lu(C.c_void_p(sym.handle), _p(PL), _p(PU), b.shape[1], _p(b), sym.n, _p(x), sym.n)
+    return x
+
+
+def logabsdet_lu(sym: Symbolic, PL):
+    """(log |det A|, number of negative pivots u_jj) of an L U factor."""
+    L = _load()
+    nneg = C.c_int32(0)
+    v = L.orc_logabsdet_lu(C.c_void_p(sym.handle), _p(PL), C.byref(nneg))
     return v, nneg.value
 
 

@@ -1060,6 +1060,201 @@ double orc_logabsdet_ldlt(const orc_sym* s, const double* P, i32* nneg)
 }
 
 /*
+ * L U with static pivoting (Section III: the solver works on the pattern of
+ * A + A^T and, for a non-symmetric matrix, duplicates steps 2 and 3 for L
+ * and U; no dynamic pivoting).  Two panel arrays with the layout of the
+ * Cholesky factor:
+ *   PL: the square diagonal block holds L_kk (strictly lower, unit diagonal
+ *       implied) and U_kk (upper, diagonal included); the rows below hold
+ *       L_off;
+ *   PU: the rows below the diagonal block hold U_off^T (row r, column c is
+ *       U(c, r)); its diagonal block is not used.
+ * Assembly: an entry a_ij (permuted a, b) with a >= b goes to PL (column b,
+ * row a); with a < b to PL's diagonal block (row a, column b) when both are
+ * in one column block, else to PU (column a, row b).
+ */
+int orc_assemble_lu(const orc_sym* s, const i64* colptr, const i32* rowind, const double* val, double* PL,
+                    double* PU)
+{
+    memset(PL, 0, sizeof(double) * (size_t)s->panel_size);
+    memset(PU, 0, sizeof(double) * (size_t)s->panel_size);
+    i32* col2cblk = (i32*)malloc(sizeof(i32) * ((size_t)s->n + 1));
+    for (i32 k = 0; k < s->ncblk; k++) for (i32 j = s->fcol[k]; j <= s->lcol[k]; j++) col2cblk[j] = k;
+    for (i32 j = 0; j < s->n; j++)
+        for (i64 p = colptr[j]; p < colptr[j + 1]; p++) {
+            i32 a = s->iperm[rowind[p]], b = s->iperm[j];
+            if (a >= b) {
+                i32 k = col2cblk[b], pos = row_pos(s, k, a);
+                if (pos < 0) { free(col2cblk); return ORC_EINVAL; }
+                PL[s->panel_off[k] + (i64)(b - s->fcol[k]) * s->stride[k] + pos] += val[p];
+            } else {
+                i32 k = col2cblk[a];
+                if (b <= s->lcol[k]) {
+                    PL[s->panel_off[k] + (i64)(b - s->fcol[k]) * s->stride[k] + (a - s->fcol[k])] += val[p];
+                } else {
+                    i32 pos = row_pos(s, k, b);
+                    if (pos < 0) { free(col2cblk); return ORC_EINVAL; }
+                    PU[s->panel_off[k] + (i64)(a - s->fcol[k]) * s->stride[k] + pos] += val[p];
+                }
+            }
+        }
+    free(col2cblk);
+    return ORC_OK;
+}
+
+/*
+ * Right-looking supernodal L U in ascending column-block order:
+ *   1. L U of the square diagonal block (no pivoting); breakdown when a
+ *      pivot is zero or not finite;
+ *   2. L_off = A_off U_kk^{-1} (rows of PL below the block) and
+ *      U_off = L_kk^{-1} A_upper (rows of PU: columns of U to the right);
+ *   3. for every facing column block j: the rows of k from the first block
+ *      facing j on (i) and the facing rows (q): W_L = L_rows U_facing and
+ *      W_U = U_rows^T L_facing^T; the square part (both in j's diagonal
+ *      block) is subtracted from PL's diagonal block of j in full, the rows
+ *      beyond it from PL (W_L) and PU (W_U) of j.
+ */
+int orc_factor_lu(const orc_sym* s, double* PL, double* PU, i32* fail_col)
+{
+    *fail_col = -1;
+    i32 maxs = 0;
+    for (i32 k = 0; k < s->ncblk; k++) if (s->stride[k] > maxs) maxs = s->stride[k];
+    double* WL = (double*)malloc(sizeof(double) * (size_t)maxs * (size_t)maxs + 8);
+    double* WU = (double*)malloc(sizeof(double) * (size_t)maxs * (size_t)maxs + 8);
+    i32* grow = (i32*)malloc(sizeof(i32) * ((size_t)maxs + 1));
+    if (!WL || !WU || !grow) return ORC_ENOMEM;
+    for (i32 k = 0; k < s->ncblk; k++) {
+        i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k];
+        double* L = PL + s->panel_off[k];
+        double* U = PU + s->panel_off[k];
+        for (i32 b = s->bptr[k]; b < s->bptr[k + 1]; b++)
+            for (i32 r = s->frow[b]; r <= s->lrow[b]; r++) grow[s->coefind[b] + r - s->frow[b]] = r;
+        /* 1. diagonal block, in place (B(r, c) at L[r + c*ld]) */
+        for (i32 c = 0; c < wd; c++) {
+            double d = L[c + (i64)c * ld];
+            if (!(d != 0.0) || !isfinite(d)) {
+                *fail_col = s->fcol[k] + c;
+                free(WL); free(WU); free(grow);
+                return ORC_ENOTPD;
+            }
+            for (i32 r = c + 1; r < wd; r++) L[r + (i64)c * ld] /= d;
+            for (i32 q = c + 1; q < wd; q++)
+                for (i32 r = c + 1; r < wd; r++) L[r + (i64)q * ld] -= L[r + (i64)c * ld] * L[c + (i64)q * ld];
+        }
+        /* 2. rows below: L_off against U_kk (upper), U_off^T against L_kk (unit lower) */
+        for (i32 r = wd; r < ld; r++)
+            for (i32 c = 0; c < wd; c++) {
+                double v = L[r + (i64)c * ld];
+                for (i32 p = 0; p < c; p++) v -= L[r + (i64)p * ld] * L[p + (i64)c * ld];
+                L[r + (i64)c * ld] = v / L[c + (i64)c * ld];
+                double u = U[r + (i64)c * ld];
+                for (i32 p = 0; p < c; p++) u -= L[c + (i64)p * ld] * U[r + (i64)p * ld];
+                U[r + (i64)c * ld] = u;
+            }
+        /* 3. updates of the facing panels */
+        for (i32 b = s->bptr[k] + 1; b < s->bptr[k + 1];) {
+            i32 j = s->fcblk[b];
+            i32 b2 = b;
+            while (b2 < s->bptr[k + 1] && s->fcblk[b2] == j) b2++;
+            i32 rs = s->coefind[b];
+            i32 nf = s->coefind[b2 - 1] + (s->lrow[b2 - 1] - s->frow[b2 - 1] + 1) - rs;
+            i32 m = ld - rs;
+            for (i32 q = 0; q < nf; q++)
+                for (i32 i = 0; i < m; i++) {
+                    double al = 0.0, au = 0.0;
+                    for (i32 p = 0; p < wd; p++) {
+                        al += L[rs + i + (i64)p * ld] * U[rs + q + (i64)p * ld];
+                        au += U[rs + i + (i64)p * ld] * L[rs + q + (i64)p * ld];
+                    }
+                    WL[i + (i64)q * m] = al;
+                    WU[i + (i64)q * m] = au;
+                }
+            double* TL = PL + s->panel_off[j];
+            double* TU = PU + s->panel_off[j];
+            i32 ldj = s->stride[j];
+            for (i32 q = 0; q < nf; q++) {
+                i32 gc = grow[rs + q];
+                i32 tc = gc - s->fcol[j];
+                for (i32 i = 0; i < m; i++) {
+                    i32 gr = grow[rs + i];
+                    if (gr <= s->lcol[j]) {   /* both in j's diagonal block: (row gr, column gc) */
+                        TL[(i64)tc * ldj + (gr - s->fcol[j])] -= WL[i + (i64)q * m];
+                        continue;
+                    }
+                    i32 pos = row_pos(s, j, gr);
+                    if (pos < 0) { free(WL); free(WU); free(grow); return ORC_EINVAL; }
+                    TL[(i64)tc * ldj + pos] -= WL[i + (i64)q * m];
+                    TU[(i64)tc * ldj + pos] -= WU[i + (i64)q * m];
+                }
+            }
+            b = b2;
+        }
+    }
+    free(WL);
+    free(WU);
+    free(grow);
+    return ORC_OK;
+}
+
+/* x = A^{-1} b with an L U factor: permute, forward sweep with the unit lower
+ * L, backward sweep with U (diagonal blocks in PL, the rest in PU),
+ * permute back. */
+int orc_solve_lu(const orc_sym* s, const double* PL, const double* PU, i32 nrhs, const double* B, i64 ldb,
+                 double* X, i64 ldx)
+{
+    double* Y = (double*)malloc(sizeof(double) * (size_t)s->n * (size_t)(nrhs > 0 ? nrhs : 1) + 8);
+    if (!Y) return ORC_ENOMEM;
+    for (i32 r = 0; r < nrhs; r++)
+        for (i32 i = 0; i < s->n; i++) Y[(i64)r * s->n + i] = B[(i64)r * ldb + s->perm[i]];
+    for (i32 rhs = 0; rhs < nrhs; rhs++) {
+        double* y = Y + (i64)rhs * s->n;
+        for (i32 k = 0; k < s->ncblk; k++) {
+            i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k], f = s->fcol[k];
+            const double* L = PL + s->panel_off[k];
+            for (i32 c = 0; c < wd; c++) {
+                double v = y[f + c];
+                for (i32 p = 0; p < c; p++) v -= L[c + (i64)p * ld] * y[f + p];
+                y[f + c] = v;
+            }
+            for (i32 b = s->bptr[k] + 1; b < s->bptr[k + 1]; b++)
+                for (i32 r = s->frow[b]; r <= s->lrow[b]; r++) {
+                    i32 pr = s->coefind[b] + r - s->frow[b];
+                    double acc = 0.0;
+                    for (i32 c = 0; c < wd; c++) acc += L[pr + (i64)c * ld] * y[f + c];
+                    y[r] -= acc;
+                }
+        }
+        for (i32 k = s->ncblk - 1; k >= 0; k--) {
+            i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k], f = s->fcol[k];
+            const double* L = PL + s->panel_off[k];
+            const double* U = PU + s->panel_off[k];
+            for (i32 c = 0; c < wd; c++) {
+                double acc = 0.0;
+                for (i32 b = s->bptr[k] + 1; b < s->bptr[k + 1]; b++)
+                    for (i32 r = s->frow[b]; r <= s->lrow[b]; r++)
+                        acc += U[s->coefind[b] + r - s->frow[b] + (i64)c * ld] * y[r];
+                y[f + c] -= acc;
+            }
+            for (i32 c = wd - 1; c >= 0; c--) {
+                double v = y[f + c];
+                for (i32 q = c + 1; q < wd; q++) v -= L[c + (i64)q * ld] * y[f + q];
+                y[f + c] = v / L[c + (i64)c * ld];
+            }
+        }
+    }
+    for (i32 r = 0; r < nrhs; r++)
+        for (i32 i = 0; i < s->n; i++) X[(i64)r * ldx + s->perm[i]] = Y[(i64)r * s->n + i];
+    free(Y);
+    return ORC_OK;
+}
+
+/* log |det A| = sum log |u_jj| (pairwise) and the number of negative u_jj. */
+double orc_logabsdet_lu(const orc_sym* s, const double* PL, i32* nneg)
+{
+    return orc_logabsdet_ldlt(s, PL, nneg);
+}
+
+/*
  * Solve L L^T y = c in the final numbering, in place, for nrhs columns of
  * length n with leading dimension ldy.  Forward sweep in ascending block
  * order (diagonal solve, then subtract the off-diagonal products from the
