@@ -252,7 +252,7 @@ def main():
                       "speedup_vs_fp64": (r64["factor_ms"] + r64["solve_ms"]) / (rbf["factor_ms"] + rbf["solve_ms"])},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "sched_kernel<double>", "kernel_ms": r64["kernel_ms"]},
+                     "kernel": "sched_kernel<double, false>", "kernel_ms": r64["kernel_ms"]},
     }
     if not args.no_batch:
         out["batch"] = run_batch(torch, np, Solver, args.steps)

@@ -1,5 +1,5 @@
 /*
- * spx.h - C ABI of an MI355X (gfx950) supernodal sparse Cholesky solver.
+ * spx.h - C ABI of an MI355X (gfx950) supernodal sparse Cholesky (and L D L^T) solver.
  *
  * The operation is the one of "Taking advantage of hybrid systems for sparse
  * direct solvers via task-based runtimes" (Lacoste et al.), Section III:
@@ -47,11 +47,19 @@ enum spx_status {
     SPX_ENOMEM = -2,   /* host or device allocation failed */
     SPX_EDEVICE = -3,  /* a HIP runtime call failed, or the device scheduler stopped early */
     SPX_ESTATE = -4,   /* call out of order (e.g. solve before factorize) */
-    SPX_ENOTPD = -5,   /* a pivot was not > 0 (or NaN): matrix not positive definite */
+    SPX_ENOTPD = -5,   /* a pivot was not > 0 (or NaN): matrix not positive definite;
+                        * SPX_LDLT: a pivot was zero or not finite */
     SPX_ENOCONV = -6   /* refinement did not reach the tolerance; x is still returned */
 };
 
-enum spx_method { SPX_LLT = 0 };
+enum spx_method {
+    SPX_LLT = 0,   /* P A P^T = L L^T, A symmetric positive definite */
+    SPX_LDLT = 1   /* P A P^T = L D L^T with unit L and diagonal D, A symmetric with
+                    * non-zero pivots in the computed order (static pivoting,
+                    * Section III: the structure is the one of L L^T); e.g.
+                    * quasi-definite matrices.  SPX_FP64 only; fuse_small and
+                    * merge_split are ignored (treated as 0 and 1) */
+};
 
 enum spx_precision {
     SPX_FP64 = 0,     /* factor stored and computed in FP64 */
@@ -68,7 +76,7 @@ enum spx_precision {
 };
 
 typedef struct spx_options {
-    int32_t method;           /* SPX_LLT */
+    int32_t method;           /* enum spx_method (SPX_LLT) */
     int32_t leaf_size;        /* nested dissection stops at components of this size (64) */
     int32_t amalg_pct;        /* extra fill allowed by amalgamation, percent of nnz(L) (12) */
     int32_t split_width;      /* column blocks wider than this are split (256, at most 256) */
@@ -107,7 +115,7 @@ typedef struct spx_info {
     int64_t ntasks;           /* device scheduler work items per factorization */
     int32_t fail_col;         /* after SPX_ENOTPD: failing column, original numbering */
     int32_t factorized;       /* 1 once a factorization succeeded */
-    double logdet;            /* log det A after a factorization */
+    double logdet;            /* log det A after a factorization (SPX_LDLT: log |det A|) */
     double factor_kernel_ms;  /* last factorization: scheduler kernel time (HIP events) */
     double assemble_ms;       /* last factorization: assembly kernel time */
     int32_t tile_rows;        /* update tile in use: 256 x 64 or 128 x 128 */
@@ -116,7 +124,8 @@ typedef struct spx_info {
     int32_t nsys;             /* independent systems of the handle (spx_analyze_batch), 1 otherwise */
     int64_t nfused_tiles;     /* update tiles carried out inside fused items (not in ntasks) */
     int32_t nsmall;           /* column blocks handled as one fused item (fuse_small) */
-    int32_t reserved;
+    int32_t nneg;             /* SPX_LDLT: negative pivots (the inertia's negative count;
+                               * sign det A = (-1)^nneg); 0 for SPX_LLT */
 } spx_info;
 
 typedef struct spx_solve_info {

@@ -28,7 +28,7 @@ hipError_t launch_assemble(void* panels, bool f32, const int64_t* amap, const do
 hipError_t launch_widen(double* dst, const float* src, int64_t n, hipStream_t s);
 hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, int32_t nready_hp,
                              const int32_t* fact_dep0, int32_t ncblk, hipStream_t s);
-int sched_blocks_per_cu(bool f32);
+int sched_blocks_per_cu(bool f32, bool ldlt);
 hipError_t launch_sched(const SchedArgs& a, bool f32, int grid, hipStream_t s);
 hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s);
 hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
@@ -144,6 +144,7 @@ struct spx_handle {
     int32_t fail_col = -1;
     bool logdet_valid = false;
     double logdet = 0.0;
+    int32_t nneg = 0;   // L D L^T: negative pivots
     double factor_ms = 0.0, assemble_ms = 0.0;
     // solve work (internal buffers, n x nrhs_cap) and the captured sweep graph
     DevBuf<double> y, zv, xv, tacc, xw, rw, dw, bw;
@@ -197,6 +198,7 @@ struct spx_handle {
     }
 
     bool f32() const { return opt.precision != SPX_FP64; }   // FP32 panel storage
+    bool ldlt() const { return opt.method == SPX_LDLT; }     // L D L^T (D on the panel diagonals)
     void* panel_ptr() { return f32() ? static_cast<void*>(panels_f.p) : static_cast<void*>(panels.p); }
     void* dinv_ptr() { return f32() ? static_cast<void*>(dinv_f.p) : static_cast<void*>(dinv.p); }
 
@@ -565,7 +567,7 @@ void upload_plan(spx_handle* h)
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
     if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess || clk_khz <= 0)
         clk_khz = 100000;
-    h->grid = std::max(1, ncu * sched_blocks_per_cu(h->f32()));
+    h->grid = std::max(1, ncu * sched_blocks_per_cu(h->f32(), h->ldlt()));
     h->timeout_ticks = static_cast<int64_t>(clk_khz) * 1000 * 20;   // 20 s per wait
 }
 
@@ -578,6 +580,7 @@ void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
     a.panels = h->panel_ptr();
     a.dinv = h->dinv_ptr();
     a.f32 = h->f32() ? 1 : 0;
+    a.ldlt = h->ldlt() ? 1 : 0;
     a.rowg = h->rowg.p;
     a.rowg_off = h->rowg_off.p;
     a.y = y;
@@ -634,6 +637,7 @@ SchedArgs sched_args(spx_handle* h)
     a.panels = h->panel_ptr();
     a.dinv = h->dinv_ptr();
     a.split = h->opt.precision == SPX_BF16X3_IR ? 1 : 0;
+    a.ldlt = h->ldlt() ? 1 : 0;
     a.desc = h->desc.p;
     a.rmap = h->rmap.p;
     a.ftab = h->ftab.p;
@@ -698,7 +702,8 @@ void run_factorization(spx_handle* h, hipStream_t s)
     }
     if (st[0] != INT_MAX) {
         h->fail_col = (st[0] >= 0 && st[0] < h->n) ? P.perm[st[0]] : st[0];
-        throw StatusError(SPX_ENOTPD, "pivot not positive at column " + std::to_string(h->fail_col));
+        throw StatusError(SPX_ENOTPD, std::string(h->ldlt() ? "zero or non-finite pivot" : "pivot not positive") +
+                                          " at column " + std::to_string(h->fail_col));
     }
 }
 
@@ -749,7 +754,14 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
     }
     if (opt) h->opt = *opt; else spx_default_options(&h->opt);
     int rc = guarded(h, [&]() -> int {
-        if (h->opt.method != SPX_LLT) throw InvalidArgument("only SPX_LLT is supported");
+        if (h->opt.method != SPX_LLT && h->opt.method != SPX_LDLT) throw InvalidArgument("unsupported method");
+        if (h->opt.method == SPX_LDLT) {
+            // L D L^T: FP64 factor; every column block is a FACT / TRSM /
+            // UPDATE sequence (no fused small items, no merged updates)
+            if (h->opt.precision != SPX_FP64) throw InvalidArgument("SPX_LDLT requires SPX_FP64");
+            h->opt.fuse_small = 0;
+            h->opt.merge_split = 1;
+        }
         if (h->opt.precision != SPX_FP64 && h->opt.precision != SPX_FP32_IR && h->opt.precision != SPX_BF16X3_IR)
             throw InvalidArgument("unsupported precision");
         if (h->opt.ir_max_iter < -1) throw InvalidArgument("ir_max_iter must be >= 0, or -1 for the default");
@@ -987,7 +999,8 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
     return guarded(h, [&]() -> int {
         const Plan& P = h->plan;
         if (h->factorized && !h->logdet_valid) {
-            // 2 * sum log l_jj with pairwise summation, from the diagonal of each panel
+            // 2 * sum log l_jj (L D L^T: sum log |d_j| and the count of d_j < 0)
+            // with pairwise summation, from the diagonal of each panel
             std::vector<double> diag(static_cast<size_t>(P.n));
             std::vector<float> diag_f(h->f32() ? static_cast<size_t>(P.n) : 0);
             for (int32_t k = 0; k < P.ncblk; ++k) {
@@ -1001,7 +1014,15 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
                                        pitch * sizeof(double), sizeof(double), w, hipMemcpyDeviceToHost));
             }
             if (h->f32()) std::copy(diag_f.begin(), diag_f.end(), diag.begin());
-            for (auto& d : diag) d = 2.0 * std::log(d);
+            h->nneg = 0;
+            if (h->ldlt()) {
+                for (auto& d : diag) {
+                    h->nneg += d < 0.0;
+                    d = std::log(std::fabs(d));
+                }
+            } else {
+                for (auto& d : diag) d = 2.0 * std::log(d);
+            }
             h->logdet = pairwise_sum(diag.data(), P.n);
             h->logdet_valid = true;
         }
@@ -1023,6 +1044,7 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
         o.fail_col = h->fail_col;
         o.factorized = h->factorized ? 1 : 0;
         o.logdet = h->logdet_valid ? h->logdet : 0.0;
+        o.nneg = h->logdet_valid ? h->nneg : 0;
         o.factor_kernel_ms = h->factor_ms;
         o.assemble_ms = h->assemble_ms;
         o.tile_rows = h->tile_rows;
@@ -1122,7 +1144,7 @@ const char* spx_strerror(int status)
     case SPX_ENOMEM: return "out of memory";
     case SPX_EDEVICE: return "device error";
     case SPX_ESTATE: return "call out of order";
-    case SPX_ENOTPD: return "matrix is not positive definite";
+    case SPX_ENOTPD: return "matrix is not positive definite (L D L^T: a zero pivot)";
     case SPX_ENOCONV: return "refinement did not converge";
     default: return "unknown status";
     }

@@ -38,6 +38,7 @@ struct SchedArgs {
     void* panels;            // double, or float in the FP32 refinement modes
     void* dinv;              // same element type as the panels
     int32_t split;           // FP32 panels: update and TRSM products as split-BF16 products
+    int32_t ldlt;            // L D L^T (FP64): D on the panels' diagonals, inverse D^{-1} L^{-1}
     const int4* desc;
     const int32_t* rmap;     // panel row of k -> row inside panel j, per update pair
     const int4* ftab;        // update tiles of fused small blocks
@@ -68,6 +69,7 @@ struct SweepArgs {
     const void* panels;       // double, or float in the FP32 refinement mode
     const void* dinv;
     int32_t f32;              // 1: panels and inverses are float
+    int32_t ldlt;             // 1: L D L^T factor (D on the panel diagonals, inverses D^{-1} L^{-1})
     const int32_t* rowg;      // global row of every off-diagonal panel row
     const int64_t* rowg_off;  // [ncblk] start of cblk k's rows in rowg
     double* y;                // permuted right-hand side, accumulates the forward updates (n x nrhs, ld n)

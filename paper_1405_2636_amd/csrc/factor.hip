@@ -316,6 +316,60 @@ __device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][4], const GOp& X, 
     if (ch < nchunks) mma(xa, ya);
 }
 
+// L D L^T update products (FP64): acc += X (Y D)^T, the facing operand Y
+// scaled by d_p (read through Dg: element p at p * Dg.sk, the diagonal of the
+// source panel) just before the products, so its loads stay in flight; two
+// register buffers of 8 inner indices as in wave_gemm.
+template <int NB>
+__device__ __forceinline__ void wave_gemm_d(d4 (&acc)[NB][4], const GOp& X, const GOp& Y, const GOp& Dg, int K)
+{
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nchunks = (K + 7) >> 3;
+    if (nchunks <= 0) return;
+    int xo[2][4], yo[2][NB];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) xo[u][b] = X.off + (16 * b + li) * X.si + (4 * u + lk) * X.sk;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) yo[u][b] = Y.off + (16 * b + li) * Y.si + (4 * u + lk) * Y.sk;
+    }
+    const int dx = 8 * X.sk, dy = 8 * Y.sk;
+    double xa[2][4], ya[2][NB], da[2], xb[2][4], yb[2][NB], db[2];
+    auto load = [&](double (&xs)[2][4], double (&ys)[2][NB], double (&ds)[2], int ch) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) xs[u][b] = gload<double>(X, xo[u][b] + ch * dx);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) ys[u][b] = gload<double>(Y, yo[u][b] + ch * dy);
+            ds[u] = gload<double>(Dg, Dg.off + (8 * ch + 4 * u + lk) * Dg.sk);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto mma = [&](const double (&xs)[2][4], const double (&ys)[2][NB], const double (&ds)[2]) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj)
+                    acc[bi][bj] = MM<double>::mfma(ys[u][bi] * ds[u], xs[u][bj], acc[bi][bj]);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    const int last = nchunks - 1;
+    load(xa, ya, da, 0);
+    int ch = 0;
+    for (; ch + 2 <= nchunks; ch += 2) {
+        load(xb, yb, db, ch + 1);
+        mma(xa, ya, da);
+        load(xa, ya, da, min(ch + 2, last));
+        mma(xb, yb, db);
+    }
+    if (ch < nchunks) mma(xa, ya, da);
+}
+
 // acc += X Y^T over K inner indices: FP64 or FP32 products, or (FP32 panels
 // with the split option) split-BF16 products
 template <int NB, class T>
@@ -373,7 +427,14 @@ __device__ __forceinline__ void wave_store(const typename MM<T>::acc (&acc)[NB][
 // 16 or 32, >= jb) bounds the columns stepped through: the leading NC x NC
 // part of Lt and Dt is written, the rest of the identity-padded tile is
 // left as it is.
-template <class T, int NC = 32>
+//
+// LDL = true: the L D L^T form of the same loop (unit L): the pivot d is
+// not square-rooted (a breakdown is a zero or non-finite d, found from the
+// diagonal after the loop), a row keeps the
+// unscaled value t of column c for its update (a_ri -= t l_ic) and stores
+// t / d (d itself on the diagonal); on the identity rows the same steps give
+// Y = D^{-1} L^{-1}.  Out: L (unit, d on the diagonal) in Lt, Y in Dt.
+template <class T, int NC = 32, bool LDL = false>
 __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb, int col0, int32_t* status)
 {
     static_assert(NC == 8 || NC == 16 || NC == 32, "tile width");
@@ -392,18 +453,32 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
     int fail = 32;
     auto pivot = [&](int c, double& s, double& inv) {
         const double d = readlane_d(v[c], c);
-        fail = (c < jb && !(d > 0.0) && fail == 32) ? c : fail;
-        double y = __builtin_amdgcn_rsq(d);
-        y = y * __builtin_fma(-0.5 * d, y * y, 1.5);
-        y = y * __builtin_fma(-0.5 * d, y * y, 1.5);
-        inv = y;
-        s = d * y;
+        if constexpr (LDL) {
+            // 1/d from the hardware estimate and two Newton-Raphson steps
+            double y = __builtin_amdgcn_rcp(d);
+            y = y * __builtin_fma(-d, y, 2.0);
+            y = y * __builtin_fma(-d, y, 2.0);
+            inv = y;
+            s = d;
+        } else {
+            fail = (c < jb && !(d > 0.0) && fail == 32) ? c : fail;
+            double y = __builtin_amdgcn_rsq(d);
+            y = y * __builtin_fma(-0.5 * d, y * y, 1.5);
+            y = y * __builtin_fma(-0.5 * d, y * y, 1.5);
+            inv = y;
+            s = d * y;
+        }
     };
     double s, inv;
     pivot(0, s, inv);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        v[c] = lane == c ? s : v[c] * inv;
+        // L D L^T: every row is scaled by 1/d_c but updated with its unscaled
+        // value, so the factor rows hold unit L (d_c on the diagonal) and the
+        // identity rows end as rows of L^{-T} D^{-1}
+        const double t = v[c];
+        v[c] = lane == c ? s : t * inv;
+        const double tu = LDL ? t : v[c];   // the factor of this column's update
         if (c < NC - 1) {
             // column c to bc[0..31] (the upper half writes the unused
             // bc[32..63]); LDS operations of one wave complete in order, so
@@ -411,11 +486,11 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
             bc[lane] = v[c];
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
             // column c+1 first: its pivot overlaps the rest of the update
-            v[c + 1] -= v[c] * bc[c + 1];
+            v[c + 1] -= tu * bc[c + 1];
             double sn, invn;
             pivot(c + 1, sn, invn);
 #pragma unroll
-            for (int i = c + 2; i < NC; ++i) v[i] -= v[c] * bc[i];
+            for (int i = c + 2; i < NC; ++i) v[i] -= tu * bc[i];
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
             s = sn;
             inv = invn;
@@ -423,15 +498,22 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
         // keep the scheduler from interleaving column steps (register pressure)
         __builtin_amdgcn_sched_barrier(0);
     }
+    if constexpr (LDL) {   // breakdown: a zero or non-finite pivot among the first jb
+        double dd = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) dd = lane == c ? v[c] : dd;
+        const bool bad = !upper && r < jb && !(dd != 0.0 && dd - dd == 0.0);
+        const uint64_t m = __ballot(bad);
+        fail = m ? __builtin_ctzll(m) : 32;
+    }
     if (lane == 0 && fail < jb) atomicMin(status, col0 + fail);
-    if (r < NC) {
-        if (!upper) {
+    if (r < NC && !upper) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) Lt[r + c * 33] = c <= r ? v[c] : 0.0;
-        } else {
+        for (int c = 0; c < NC; ++c) Lt[r + c * 33] = c <= r ? v[c] : 0.0;
+    }
+    if (r < NC && upper) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) Dt[c + r * 33] = c >= r ? (T)v[c] : T(0);
-        }
+        for (int c = 0; c < NC; ++c) Dt[c + r * 33] = c >= r ? (T)v[c] : T(0);
     }
 }
 
@@ -528,7 +610,13 @@ constexpr int kPbLd = 228;   // leading dimension of the LDS copy of the rows be
 //      A[J+jb:, J+jb:] -= P P^T (lower triangle) and
 //      X[J+jb:, 0:J+jb] -= P D_J (columns J .. J+jb written for the first time).
 // Products run on the matrix cores; P and D_JJ are read from LDS.
-template <class T>
+//
+// LDL = true: L D L^T of the diagonal block (unit L with D on its diagonal,
+// and Y = D^{-1} L^{-1} as the stored inverse, so that the panel solve and
+// the rows below stay one product A_rows Y^T): the tile step is the L D L^T
+// form of tile_chol_inv, the trailing update is A -= L (D L^T) and the rows
+// of the running inverse take (L D) Y_J.
+template <class T, bool LDL = false>
 __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T* Dt, T* Pb)
 {
     typedef typename MM<T>::acc acc_t;
@@ -544,6 +632,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     double* bc = Lt + kNB * 33;
     __shared__ int s_next;   // next trailing tile to deal
+    __shared__ double dcur[kNB];   // (L D L^T) this step's pivots
     bool ready = false;      // Lt/Dt already hold this step's factored tile
     for (int J = 0; J < w; J += kNB) {
         const int jb = min(kNB, w - J);
@@ -557,7 +646,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                                                     : (r == c ? 1.0 : 0.0);
             }
             __syncthreads();
-            if (wave == 0) tile_chol_inv<T>(Lt, bc, Dt, jb, f + J, a.status);
+            if (wave == 0) tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jb, f + J, a.status);
         }
         if (tid == 0) s_next = 0;
         __syncthreads();
@@ -568,6 +657,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                 D[(J + r) + (int64_t)(J + c) * w] = Dt[r + c * 33];
             }
         }
+        if (LDL && tid < kNB) dcur[tid] = Lt[tid + tid * 33];
         // 2a. rows below: P = A_rows D_JJ^T (wave v: rows 64v ..)
         const int r0 = 64 * wave;
         if (r0 < R) {
@@ -626,6 +716,10 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
             // rows i >= mv (and columns c >= nv below) only reach results
             // that are not stored; Pb is padded for their indices
             auto ldx = [&](int i, int p) { return Pb[(i0 + i) + p * kPbLd]; };
+            // (L D L^T) the facing rows of the syrk tiles and the rows of the
+            // inverse tiles carry D
+            auto ldxd = [&](int i, int p) { return LDL ? (T)(Pb[(i0 + i) + p * kPbLd] * dcur[p]) : Pb[(i0 + i) + p * kPbLd]; };
+            auto ldyd = [&](int c, int p) { return LDL ? (T)(Pb[(c0 + c) + p * kPbLd] * dcur[p]) : Pb[(c0 + c) + p * kPbLd]; };
             auto sub = [](T o, T v) { return o - v; };
             if (syrk) {
                 const int nv = min(32, R - c0);
@@ -637,15 +731,14 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                         Lt[r + c * 33] = r == c && r >= jn ? 1.0 : 0.0;
                     }
                     wave_mm_rmw<2, T>(
-                        ldx, [&](int c, int p) { return Pb[(c0 + c) + p * kPbLd]; }, mv, nv, cA,
-                        [&](int r, int c) { return r >= c; }, sub, [&](int r, int c, T v) {
+                        ldx, ldyd, mv, nv, cA, [&](int r, int c) { return r >= c; }, sub, [&](int r, int c, T v) {
                             if (r < jn && c < jn && c <= r) Lt[r + c * 33] = (double)v;
                         });
-                    tile_chol_inv<T>(Lt, bc, Dt, jn, f + J + jb, a.status);
+                    tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jn, f + J + jb, a.status);
                 } else {
                     wave_mm_rmw<2, T>(
-                        ldx, [&](int c, int p) { return Pb[(c0 + c) + p * kPbLd]; }, mv, nv, cA,
-                        [&](int r, int c) { return i0 + r >= c0 + c; }, sub, [](int, int, T) {});
+                        ldx, ldyd, mv, nv, cA, [&](int r, int c) { return i0 + r >= c0 + c; }, sub,
+                        [](int, int, T) {});
                 }
             } else {
                 const int nv = min(32, J + jb - c0);
@@ -653,13 +746,13 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                 if (c0 >= J) {   // columns written for the first time
                     acc_t acc[2][4];
                     zero_acc(acc);
-                    wave_mm<2, T>(acc, ldx, ldy);
+                    wave_mm<2, T>(acc, ldxd, ldy);
                     wave_store<T>(acc, mv, nv,
                                   [&](int r, int c, T v) { D[(J + jb + i0 + r) + (int64_t)(c0 + c) * w] = -v; });
                 } else {
                     GOp cD = gD;
                     cD.off = uni(gD.off + (J + jb + i0) * gD.si + c0 * gD.sk);
-                    wave_mm_rmw<2, T>(ldx, ldy, mv, nv, cD, [](int, int) { return true; }, sub, [](int, int, T) {});
+                    wave_mm_rmw<2, T>(ldxd, ldy, mv, nv, cD, [](int, int) { return true; }, sub, [](int, int, T) {});
                 }
             }
         }
@@ -712,8 +805,9 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // mrows <= 128 (the waves form a 2x2 grid of 64x64 wave tiles).  A merged
 // item (np > 1, kind bits 8..) sums the products of the np consecutive
 // pieces k-np+1 .. k of a split supernode (piece p's rows are k's rows
-// shifted by fcol[k] - fcol[p]) before its one scatter.
-template <class T>
+// shifted by fcol[k] - fcol[p]) before its one scatter.  LDL (FP64, one
+// piece): W = L_k[rows] D_k L_k[cols]^T, D_k on the diagonal of panel k.
+template <class T, bool LDL = false>
 __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos, int* cpos)
 {
     const DevPlan& pl = a.pl;
@@ -737,8 +831,12 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
             const int fp = pl.fcol[p], w = pl.lcol[p] - fp + 1, sh = fk - fp;
             const int64_t ld = pl.stride[p];
             const T* A = static_cast<const T*>(a.panels) + pl.panel_off[p];
-            tile_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld), make_gop(A, ld * w, col0 + c0 + sh, 1, ld),
-                            w, a.split != 0);
+            if constexpr (LDL)
+                wave_gemm_d<4>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld),
+                               make_gop(A, ld * w, col0 + c0 + sh, 1, ld), make_gop(A, ld * w, 0, 0, ld + 1), w);
+            else
+                tile_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld),
+                                make_gop(A, ld * w, col0 + c0 + sh, 1, ld), w, a.split != 0);
         }
         wave_store<T>(acc, mv, nv, [&](int r, int c, T v) {
             const int tr = rpos[r0 + r], tc = cpos[c0 + c];
@@ -895,7 +993,8 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
 }
 
 // ---------------------------------------------------------------- scheduler
-template <class T>
+// LDL: the L D L^T factor (FP64; no fused small items, no merged updates).
+template <class T, bool LDL = false>
 __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 {
     __shared__ double Lt[kNB * 33 + 2 * kNB];
@@ -965,15 +1064,15 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         const int kind = d0.x & 0xff;   // (bits 8.. of an update: pieces merged - 1)
         if (kind == kFact) {
             __builtin_amdgcn_s_setprio(3);
-            task_fact<T>(a, d0.y, Lt, Dt, Pb);
+            task_fact<T, LDL>(a, d0.y, Lt, Dt, Pb);
             __builtin_amdgcn_s_setprio(0);
         } else if (kind == kTrsm) {
             __builtin_amdgcn_s_setprio(2);
             task_trsm<T>(a, d0.y, d0.z, d0.w);
             __builtin_amdgcn_s_setprio(0);
         } else if (kind == kUpdate) {
-            task_update<T>(a, d0, d1, rpos, cpos);
-        } else {
+            task_update<T, LDL>(a, d0, d1, rpos, cpos);
+        } else if constexpr (!LDL) {
             task_small<T>(a, d0, d1, Lt, Dt, Pb);
         }
         // every wave's stores and atomics have completed before the barrier
@@ -1135,11 +1234,13 @@ hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t n
     return hipGetLastError();
 }
 
-int sched_blocks_per_cu(bool f32)
+int sched_blocks_per_cu(bool f32, bool ldlt)
 {
     int nb = 0;
-    const hipError_t e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<float>, kThreads, 0)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double>, kThreads, 0);
+    const hipError_t e =
+        f32    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<float>, kThreads, 0)
+        : ldlt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double, true>, kThreads, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double>, kThreads, 0);
     if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
@@ -1147,6 +1248,7 @@ int sched_blocks_per_cu(bool f32)
 hipError_t launch_sched(const SchedArgs& a, bool f32, int grid, hipStream_t s)
 {
     if (f32) sched_kernel<float><<<grid, kThreads, 0, s>>>(a);
+    else if (a.ldlt) sched_kernel<double, true><<<grid, kThreads, 0, s>>>(a);
     else sched_kernel<double><<<grid, kThreads, 0, s>>>(a);
     return hipGetLastError();
 }

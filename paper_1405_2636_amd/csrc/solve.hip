@@ -20,6 +20,11 @@
 // HBM bandwidth and, on the narrow top levels, by load latency.
 // The factor is read in its storage type T (double, or float in the FP32
 // refinement mode); vectors and arithmetic are FP64 in both cases.
+// L D L^T (unit L, d_j on the panel diagonal, kept inverse Y = D^{-1} L^{-1}):
+// the same steps give w_k = Y_kk y_k = D_k^{-1} z_k in z, so the forward rows
+// below take D_k w_k, and the backward step x_k = L_kk^{-T} (w_k - t_k) is
+// Y_kk^T applied to D_k (w_k - t_k); the scaling by d is applied where z_k
+// and z_k - t_k are staged.
 #include "device.hpp"
 
 namespace spx {
@@ -94,8 +99,9 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
     const int r = min(lane, nr - 1);
     const int qw = (w + 3) >> 2, cb = wave * qw, ce = min(w, cb + qw);
     const T* Lr = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0 + r;
+    const T* Pd = static_cast<const T*>(a.panels) + pl.panel_off[k];   // d_c at c * (ld + 1) (L D L^T)
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        if (tid < w) zk[tid] = a.z[(int64_t)rhs * a.n + f + tid];
+        if (tid < w) zk[tid] = a.z[(int64_t)rhs * a.n + f + tid] * (a.ldlt ? (double)Pd[tid * (ld + 1)] : 1.0);
         __syncthreads();
         double v = 0.0;
         for (int c = cb; c < ce; c += 16) {
@@ -169,10 +175,12 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblk
     const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
     const int tid = threadIdx.x, q = tid % LANES, col = min(c0 + tid / LANES, w - 1);
     const T* Dc = D + (int64_t)col * w;
+    const T* Pd = static_cast<const T*>(a.panels) + pl.panel_off[k];   // d_c at c * (ld + 1) (L D L^T)
+    const int64_t ld = pl.stride[k];
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
         const double* z = a.z + (int64_t)rhs * a.n + f;
         const double* t = a.tacc + (int64_t)rhs * a.n + f;
-        if (tid < w) zs[tid] = z[tid] - t[tid];
+        if (tid < w) zs[tid] = (z[tid] - t[tid]) * (a.ldlt ? (double)Pd[tid * (ld + 1)] : 1.0);
         __syncthreads();
         double v = 0.0;
         for (int pb = col; pb < w; pb += 16 * LANES) {
@@ -234,7 +242,7 @@ __global__ void __launch_bounds__(256) fwd_small(SweepArgs a, const int32_t* cbl
 #pragma unroll
                 for (int u = 0; u < 8; ++u) v += (double)d[u] * (p0 + u <= r ? ys[g][min(p0 + u, 31)] : 0.0);
             }
-            zs[g][r] = v;
+            zs[g][r] = a.ldlt ? v * (double)L[r * (ld + 1)] : v;
             a.z[vo + f + r] = v;
         }
         __syncthreads();
@@ -311,7 +319,8 @@ __global__ void __launch_bounds__(256) bwd_small(SweepArgs a, const int32_t* cbl
             for (int u = 0; u < 4; ++u) v[u] = group_sum<kSG>(v[u]);
             if (l < 4 && c0 + l < w) {
                 const double t = l == 0 ? v[0] : l == 1 ? v[1] : l == 2 ? v[2] : v[3];
-                us[g][c0 + l] = a.z[vo + f + c0 + l] - t;
+                const double u = a.z[vo + f + c0 + l] - t;
+                us[g][c0 + l] = a.ldlt ? u * (double)L[(c0 + l) * (ld + 1)] : u;
             }
         }
         __syncthreads();

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libspx.so")
 
 SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ESTATE, SPX_ENOTPD, SPX_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 PRECISIONS = {"fp64": 0, "fp32_ir": 1, "bf16x3_ir": 2}   # enum spx_precision
+METHODS = {"llt": 0, "ldlt": 1}                          # enum spx_method
 
 
 class SpxError(RuntimeError):
@@ -53,7 +54,7 @@ class Info(C.Structure):
                 ("ntasks", C.c_int64), ("fail_col", C.c_int32), ("factorized", C.c_int32),
                 ("logdet", C.c_double), ("factor_kernel_ms", C.c_double), ("assemble_ms", C.c_double),
                 ("tile_rows", C.c_int32), ("tile_cols", C.c_int32), ("hp_policy", C.c_int32), ("nsys", C.c_int32),
-                ("nfused_tiles", C.c_int64), ("nsmall", C.c_int32), ("reserved", C.c_int32)]
+                ("nfused_tiles", C.c_int64), ("nsmall", C.c_int32), ("nneg", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -136,12 +137,16 @@ class Solver:
     precision: "fp64" (FP64 factor), "fp32_ir" (FP32 factor, FP64 residual
     and refinement) or "bf16x3_ir" (FP32 factor whose update products are
     split-BF16 products, FP64 refinement).  ir_max_iter None: the library's
-    default for the precision (2 for fp64, 10 otherwise).
+    default for the precision (2 for fp64, 10 otherwise).  method: "llt"
+    (P A P^T = L L^T, A positive definite) or "ldlt" (L D L^T with static
+    pivoting, A symmetric with non-zero pivots, e.g. quasi-definite; fp64
+    only; info()["logdet"] is then log |det A| and info()["nneg"] the number
+    of negative pivots).
     """
 
     def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,
                  precision="fp64", ir_max_iter=None, ir_tol=1e-14, trace=False, graph=False, tune=False, tile=0,
-                 fuse_small=True, merge_split=4):
+                 fuse_small=True, merge_split=4, method="llt"):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -150,7 +155,7 @@ class Solver:
         self.nnz = int(self._colptr[-1]) if len(self._colptr) else 0
         self.sizes = [self.n]
         opt, up = self._options(L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol,
-                                trace, graph, tune, tile, fuse_small, merge_split)
+                                trace, graph, tune, tile, fuse_small, merge_split, method)
         h = C.c_void_p()
         rc = L.spx_analyze(self.n, self._colptr.ctypes.data, self._rowind.ctypes.data, C.byref(opt), C.byref(h))
         if rc != SPX_OK:
@@ -158,9 +163,13 @@ class Solver:
         self._h = h
 
     def _options(self, L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol, trace,
-                 graph, tune, tile=0, fuse_small=True, merge_split=4):
+                 graph, tune, tile=0, fuse_small=True, merge_split=4, method="llt"):
         opt = Options()
         L.spx_default_options(C.byref(opt))
+        if method not in METHODS:
+            raise ValueError("method must be one of %s" % sorted(METHODS))
+        self.method = method
+        opt.method = METHODS[method]
         opt.leaf_size, opt.amalg_pct, opt.split_width = leaf_size, amalg_pct, split_width
         if precision not in PRECISIONS:
             raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
@@ -198,7 +207,8 @@ class Solver:
         self._keep = (cps, ris)
         opt, _ = self._options(L, kw.get("leaf_size", 64), kw.get("amalg_pct", 12), kw.get("split_width", 256),
                                None, precision, ir_max_iter, ir_tol, kw.get("trace", False), graph, tune,
-                               kw.get("tile", 0), kw.get("fuse_small", True), kw.get("merge_split", 4))
+                               kw.get("tile", 0), kw.get("fuse_small", True), kw.get("merge_split", 4),
+                               kw.get("method", "llt"))
         cpp = (C.c_void_p * len(cps))(*[c.ctypes.data for c in cps])
         rip = (C.c_void_p * len(ris))(*[r.ctypes.data for r in ris])
         h = C.c_void_p()

@@ -65,6 +65,21 @@ def test_bad_options():
     # every precision mode and option set in range is accepted at analysis
     for prec in ["fp64", "fp32_ir", "bf16x3_ir"]:
         Solver(p.n, p.colptr, p.rowind, precision=prec, merge_split=16, fuse_small=False, tile=1)
+    # L D L^T: FP64 only; an unknown method code is rejected by the library
+    Solver(p.n, p.colptr, p.rowind, method="ldlt", merge_split=16)
+    for prec in ["fp32_ir", "bf16x3_ir"]:
+        with pytest.raises(SpxError):
+            Solver(p.n, p.colptr, p.rowind, method="ldlt", precision=prec)
+    with pytest.raises(ValueError):
+        Solver(p.n, p.colptr, p.rowind, method="lu")
+    from paper_1405_2636_amd import spx
+    L = spx.load_library()
+    opt = spx.Options()
+    L.spx_default_options(C.byref(opt))
+    assert opt.method == 0
+    opt.method = 2
+    h = C.c_void_p()
+    assert L.spx_analyze(p.n, p.colptr.ctypes.data, p.rowind.ctypes.data, C.byref(opt), C.byref(h)) == -1
 
 
 def test_null_safety():
