@@ -84,13 +84,14 @@ def copy_probe():
     print("copied 3 x %d bytes" % (n * 8), flush=True)
 
 
-def run_leg(torch, np, Solver, p, vals, b0, precision, steps, warmup):
+def run_leg(torch, np, Solver, p, vals, b0, precision, steps, warmup, method="llt"):
     """Warm-up, then `steps` timed passes of factorize + refined solve in one
-    precision mode.  Times are HIP events on the torch stream the library is
-    called on; the kernel time is the library's own event pair around the
-    scheduler kernel."""
+    precision mode (and method: L L^T, or L D L^T).  Times are HIP events on
+    the torch stream the library is called on; the kernel time is the
+    library's own event pair around the scheduler kernel."""
     t0 = time.perf_counter()
-    s = Solver(p.n, p.colptr, p.rowind, precision=precision)
+    s = Solver(p.n, p.colptr, p.rowind, precision=precision, method=method)
+    precision = precision if method == "llt" else precision + " " + method
     t_an = time.perf_counter() - t0
     info = s.info()
     print("[%s] analyze %.1f s: ncblk %d nnz(L) %d flops %.3e tasks %d"
@@ -220,6 +221,7 @@ def main():
     legs = {prec: run_leg(torch, np, Solver, p, vals, b0, prec, args.steps, args.warmup)
             for prec in ("fp64", "fp32_ir", "bf16x3_ir")}
     r64, r32, rbf = legs["fp64"], legs["fp32_ir"], legs["bf16x3_ir"]
+    rld = run_leg(torch, np, Solver, p, vals, b0, "fp64", args.steps, args.warmup, method="ldlt")
     flops = r64["flops"]
     achieved = flops / (r64["kernel_ms"] * 1e-3) / 1e12
     out = {
@@ -250,6 +252,10 @@ def main():
                       "factor_gflops": flops / (rbf["factor_ms"] * 1e-3) / 1e9, "omega": rbf["omega"],
                       "ir_iters": rbf["ir_iters"], "kernel_ms": rbf["kernel_ms"],
                       "speedup_vs_fp64": (r64["factor_ms"] + r64["solve_ms"]) / (rbf["factor_ms"] + rbf["solve_ms"])},
+        "ldlt_fp64": {"factor_ms": rld["factor_ms"], "solve_ms": rld["solve_ms"],
+                      "factor_gflops": flops / (rld["factor_ms"] * 1e-3) / 1e9, "omega": rld["omega"],
+                      "ir_iters": rld["ir_iters"], "kernel_ms": rld["kernel_ms"],
+                      "kernel_frac_of_fp64_peak": flops / (rld["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "sched_kernel<double, false>", "kernel_ms": r64["kernel_ms"]},

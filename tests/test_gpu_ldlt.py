@@ -147,3 +147,26 @@ def test_ldlt_equals_scaled_llt(orc, torch):
     expect = np.where(ri == ci, vc ** 2, vc / dc[ci])
     assert np.max(np.abs(vl - expect) / np.maximum(np.abs(expect), 1e-300)) <= 1e-11
     assert abs(s1.info()["logdet"] - s2.info()["logdet"]) <= 1e-12 * abs(s1.info()["logdet"])
+
+
+def test_ldlt_batch(orc, torch):
+    # independent quasi-definite systems in one graph-replayed, tuned launch:
+    # each member's solution against the oracle's, inertia summed
+    from paper_1405_2636_amd import Solver
+    ps = [_quasi_definite(120 + 40 * q, 50 + 10 * q, 20 + q) for q in range(4)] + [_dense_quasi_definite(40, 25, 9)]
+    s = Solver.batch([(p.n, p.colptr, p.rowind) for p in ps], method="ldlt", graph=True, tune=True)
+    vals = torch.tensor(np.concatenate([p.values for p in ps]), device="cuda")
+    rng = np.random.default_rng(3)
+    B = [rng.uniform(-1, 1, p.n) for p in ps]
+    for rep in range(2):   # tuning run, then a graph replay
+        s.factorize(vals)
+        x, si = s.solve(torch.tensor(np.concatenate(B), device="cuda"))
+        assert si["omega"] <= 1e-14 and si["converged"]
+        nneg = 0
+        for p, xq, bq in zip(ps, s.split(x.cpu().numpy()), B):
+            sym = orc.analyze(p.n, p.colptr, p.rowind)
+            P = orc.factor_ldlt(sym, p.colptr, p.rowind, p.values)
+            xo = orc.solve_ldlt(sym, P, bq[:, None])[:, 0]
+            assert np.max(np.abs(xq - xo)) <= 1e-9 * np.max(np.abs(xo))
+            nneg += orc.logabsdet_ldlt(sym, P)[1]
+        assert s.info()["nneg"] == nneg
