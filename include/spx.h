@@ -57,8 +57,8 @@ enum spx_method {
     SPX_LDLT = 1   /* P A P^T = L D L^T with unit L and diagonal D, A symmetric with
                     * non-zero pivots in the computed order (static pivoting,
                     * Section III: the structure is the one of L L^T); e.g.
-                    * quasi-definite matrices.  SPX_FP64 only; fuse_small and
-                    * merge_split are ignored (treated as 0 and 1) */
+                    * quasi-definite matrices.  SPX_FP64 only; fuse_small is
+                    * ignored (treated as 0) */
 };
 
 enum spx_precision {

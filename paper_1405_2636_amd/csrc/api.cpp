@@ -757,10 +757,10 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
         if (h->opt.method != SPX_LLT && h->opt.method != SPX_LDLT) throw InvalidArgument("unsupported method");
         if (h->opt.method == SPX_LDLT) {
             // L D L^T: FP64 factor; every column block is a FACT / TRSM /
-            // UPDATE sequence (no fused small items, no merged updates)
+            // UPDATE sequence (no fused small items; merged updates apply
+            // each piece's own D)
             if (h->opt.precision != SPX_FP64) throw InvalidArgument("SPX_LDLT requires SPX_FP64");
             h->opt.fuse_small = 0;
-            h->opt.merge_split = 1;
         }
         if (h->opt.precision != SPX_FP64 && h->opt.precision != SPX_FP32_IR && h->opt.precision != SPX_BF16X3_IR)
             throw InvalidArgument("unsupported precision");

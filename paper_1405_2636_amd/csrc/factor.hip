@@ -805,8 +805,8 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // mrows <= 128 (the waves form a 2x2 grid of 64x64 wave tiles).  A merged
 // item (np > 1, kind bits 8..) sums the products of the np consecutive
 // pieces k-np+1 .. k of a split supernode (piece p's rows are k's rows
-// shifted by fcol[k] - fcol[p]) before its one scatter.  LDL (FP64, one
-// piece): W = L_k[rows] D_k L_k[cols]^T, D_k on the diagonal of panel k.
+// shifted by fcol[k] - fcol[p]) before its one scatter.  LDL (FP64):
+// each piece's product is L_p[rows] D_p L_p[cols]^T, D_p on the diagonal of panel p.
 template <class T, bool LDL = false>
 __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos, int* cpos)
 {
@@ -993,7 +993,7 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
 }
 
 // ---------------------------------------------------------------- scheduler
-// LDL: the L D L^T factor (FP64; no fused small items, no merged updates).
+// LDL: the L D L^T factor (FP64; no fused small items).
 template <class T, bool LDL = false>
 __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 {

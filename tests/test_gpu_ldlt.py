@@ -85,19 +85,25 @@ def _check(orc, torch, p, nrhs=1, **kw):
     return s, nneg
 
 
-@pytest.mark.parametrize("case", ["spd_rand", "grid3", "grid3_split", "qd", "qd_split", "qd_wide"])
+@pytest.mark.parametrize("case", ["spd_rand", "grid3", "grid3_split", "grid3_split_nomerge", "qd", "qd_split",
+                                  "qd_split_merge2", "qd_wide"])
 def test_ldlt_parity(orc, torch, case):
     if case == "spd_rand":
         _check(orc, torch, random_spd(400, 0.01, 4))
     elif case == "grid3":
         _check(orc, torch, grid_laplacian((12, 11, 10), shift=1e-3), nrhs=2)
-    elif case == "grid3_split":
+    elif case == "grid3_split":   # many pieces; their updates merged in groups of 4 (the default)
         _check(orc, torch, grid_laplacian((12, 11, 10), shift=1e-3), split_width=7, leaf_size=16)
+    elif case == "grid3_split_nomerge":
+        _check(orc, torch, grid_laplacian((12, 11, 10), shift=1e-3), split_width=7, leaf_size=16, merge_split=1)
     elif case == "qd":
         _, nneg = _check(orc, torch, _quasi_definite(300, 150, 5))
         assert nneg == 150
     elif case == "qd_split":
         _, nneg = _check(orc, torch, _quasi_definite(500, 200, 6), split_width=33, amalg_pct=40)
+        assert nneg == 200
+    elif case == "qd_split_merge2":
+        _, nneg = _check(orc, torch, _quasi_definite(500, 200, 6), split_width=16, merge_split=2)
         assert nneg == 200
     else:
         _, nneg = _check(orc, torch, _quasi_definite(800, 400, 7, 0.02, 0.02, 0.01))
