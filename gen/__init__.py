@@ -15,3 +15,4 @@ from .stencils import (  # noqa: F401
     convection_diffusion,
     CONFIG_NAMES,
 )
+from .elasticity import elasticity3d, element_stiffness, material_matrix, strain_matrix  # noqa: F401
