@@ -21,6 +21,7 @@ import numpy as np
 CONFIG_NAMES = {
     1: "laplace2d_5pt_64x64",
     2: "laplace3d_7pt_100^3_shift1e-3",
+    3: "convdiff3d_7pt_80^3",
     4: "batch512_wgrid2d_16-96",
     5: "elasticity3d_q1_40^3_3dof",
 }
@@ -226,6 +227,9 @@ def make_config(i: int, seed: int | None = None) -> Problem:
 
     1: 2-D 5-point Laplacian on a 64x64 grid, a_ii = 4, a_ij = -1, one RHS.
     2: 3-D 7-point Laplacian on a 100^3 grid plus a diagonal shift 1e-3, one RHS.
+    3: 3-D convection-diffusion 7-point stencil on an 80^3 grid (N = 512,000,
+       unsymmetric values on a symmetric pattern; the L U workload),
+       convection coefficients drawn with the config's seed, four RHS.
     5: clamped Q1 elasticity on a 42^3-node mesh (40^3 free nodes, 3 dof
        each, N = 192,000, 27-point 3-dof stencil), element moduli
        lognormal(0, 0.5) drawn with the config's seed, eight RHS.
@@ -239,6 +243,9 @@ def make_config(i: int, seed: int | None = None) -> Problem:
     elif i == 2:
         p = grid_laplacian((100, 100, 100), shift=1e-3)
         nrhs = 1
+    elif i == 3:
+        p = convection_diffusion((80, 80, 80), seed)
+        nrhs = 4
     elif i == 5:
         from .elasticity import elasticity3d
         p = elasticity3d(42, seed)

@@ -2,9 +2,11 @@
 clamped) pinned by what mechanics fixes, and the oracle's L D L^T and
 adjoint on it.
 
-Element: symmetric, rank 18, the six rigid-body motions in its null space;
-a uniform strain field stores exactly eps^T D eps per unit volume (Q1
-elements represent linear displacements exactly).  Assembly: symmetric,
+Material: the inverse of the textbook compliance matrix.  Element:
+symmetric, rank 18, the six rigid-body motions in its null space; a uniform
+strain field stores exactly eps^T D eps per unit volume (Q1 elements
+represent linear displacements exactly); a 3-point Gauss rule gives the same
+matrix.  Assembly: equal to a brute-force element loop; symmetric,
 positive definite, 81 entries in an interior row, and the entry count
 9 (3m - 2)^3 for m free nodes per side (14,787,288 at m = 40)."""
 import numpy as np
@@ -120,3 +122,62 @@ def test_ldlt_adjoint_finite_differences(orc):
         assert abs(fd - g[q]) <= 1e-6 * max(1.0, abs(fd)), (q, fd, g[q])
         lower += p.rowind[q] >= col[q]
     assert lower > p.n
+
+
+def test_material_matrix_is_the_inverse_compliance():
+    # Hooke's law in compliance form: strains from stresses with 1/E on the
+    # normal diagonal, -nu/E between normal components, 1/G = 2 (1 + nu)/E
+    # on the (engineering) shear diagonal
+    for E, nu in [(1.0, 0.3), (2.5, 0.2), (0.7, 0.45)]:
+        S = np.zeros((6, 6))
+        S[:3, :3] = -nu / E
+        S[[0, 1, 2], [0, 1, 2]] = 1.0 / E
+        S[[3, 4, 5], [3, 4, 5]] = 2.0 * (1.0 + nu) / E
+        assert np.allclose(material_matrix(nu, E) @ S, np.eye(6), atol=1e-12)
+
+
+def test_element_quadrature_is_exact():
+    # the integrand is of degree <= 2 in each coordinate, so a 3-point
+    # Gauss-Legendre rule gives the same stiffness as the element's 2-point one
+    from gen import strain_matrix
+    t, w = np.polynomial.legendre.leggauss(3)
+    t, w = 0.5 * (t + 1.0), 0.5 * w
+    D = material_matrix(0.3)
+    K3 = np.zeros((24, 24))
+    for i in range(3):
+        for j in range(3):
+            for k in range(3):
+                B = strain_matrix(t[i], t[j], t[k])
+                K3 += w[i] * w[j] * w[k] * B.T @ D @ B
+    assert np.max(np.abs(K3 - element_stiffness(0.3))) <= 1e-14 * np.max(np.abs(K3))
+
+
+@pytest.mark.parametrize("n", [4, 5])
+def test_assembly_brute_force(n):
+    # element by element into a dense matrix, nodes addressed by their
+    # coordinates: free node (x, y, z), 1 <= x, y, z <= n-2, has index
+    # (x-1) + m (y-1) + m^2 (z-1); moduli drawn in element order, x fastest
+    seed, sigma = 11, 0.5
+    p = elasticity3d(n, seed=seed, sigma=sigma)
+    m = n - 2
+    E = np.random.default_rng(seed).lognormal(0.0, sigma, (n - 1) ** 3)
+    Ke = element_stiffness(0.3)
+    A = np.zeros((p.n, p.n))
+    e = 0
+    for z in range(n - 1):
+        for y in range(n - 1):
+            for x in range(n - 1):
+                dofs = []
+                for a in range(8):
+                    cx, cy, cz = a & 1, (a >> 1) & 1, (a >> 2) & 1
+                    X, Y, Z = x + cx, y + cy, z + cz
+                    inner = all(1 <= c <= n - 2 for c in (X, Y, Z))
+                    node = (X - 1) + m * (Y - 1) + m * m * (Z - 1)
+                    dofs += [3 * node + comp if inner else -1 for comp in range(3)]
+                for i, gi in enumerate(dofs):
+                    for j, gj in enumerate(dofs):
+                        if gi >= 0 and gj >= 0:
+                            A[gi, gj] += E[e] * Ke[i, j]
+                e += 1
+    G = sp.csc_matrix((p.values, p.rowind, p.colptr), shape=(p.n, p.n)).toarray()
+    assert np.max(np.abs(G - A)) <= 1e-14 * np.max(np.abs(A))

@@ -134,3 +134,16 @@ def test_lu_zero_pivot(orc):
         with pytest.raises(orc.ZeroPivot) as e:
             orc.factor_lu(sym, colptr, rowind, vals)
         assert e.value.col_new == col
+
+
+def test_convection_diffusion_workload_size():
+    # 7-point pattern: n + 2 * (sum over axes of the edges along that axis);
+    # checked on a small grid by the generator, then the stated size of the
+    # 80^3 workload (512,000 unknowns, 3,545,600 entries) from the same count
+    def count(d):
+        return d ** 3 + 2 * 3 * d * d * (d - 1)
+    p = convection_diffusion((9, 9, 9), seed=1)
+    assert p.n == 729 and p.nnz == count(9)
+    assert count(80) == 3545600
+    from gen import make_config, CONFIG_NAMES
+    assert CONFIG_NAMES[3] == "convdiff3d_7pt_80^3"
