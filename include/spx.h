@@ -8,7 +8,8 @@
  *      tree, predicted nonzero pattern of the factor grouped into column
  *      blocks, amalgamation allowing extra fill, vertical splitting of wide
  *      supernodes)                                   -> spx_analyze
- *   2. the numerical supernodal factorization P A P^T = L L^T: per column
+ *   2. the numerical supernodal factorization P A P^T = L L^T (or L D L^T,
+ *      SPX_LDLT, the paper's symmetric-indefinite variant): per column
  *      block, dense factorization of the diagonal block, triangular solve of
  *      the off-diagonal rows, and right-looking updates of the facing column
  *      blocks (Section III, the "1D task" and its split into one task per
