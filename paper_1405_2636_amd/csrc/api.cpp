@@ -352,7 +352,6 @@ void build_tasks(spx_handle* h)
         desc.push_back(int4{0, 0, 0, 0});
     }
     int32_t id = nc;
-    int64_t ntrsm = 0;
     for (int32_t k = 0; k < nc; ++k) {
         const int32_t w = P.lcol[k] - P.fcol[k] + 1, ld = P.stride[k];
         tf[k] = id;
@@ -364,7 +363,6 @@ void build_tasks(spx_handle* h)
             ++id;
         }
         tc[k] = id - tf[k];
-        ntrsm += tc[k];
     }
     int64_t nhp_upd = 0;
     std::vector<int4> ftab;   // update tiles of the fused blocks
