@@ -71,6 +71,16 @@ def test_config2_full_size(orc):
     assert sy["ncblk"] > 1000
 
 
+@pytest.mark.parametrize("config", [3, 5])
+def test_other_workloads_full_size(orc, config):
+    """The 80^3 convection-diffusion pattern (L U workload) and the 40^3
+    Q1 elasticity pattern (L D L^T workload, 192,000 unknowns): identical
+    plans."""
+    p = make_config(config)
+    sy = _compare(orc, p.n, p.colptr, p.rowind)
+    assert sy["ncblk"] > 500
+
+
 def _block_diagonal(problems):
     import scipy.sparse as sp
     mats = [sp.csc_matrix((p.values, p.rowind, p.colptr), shape=(p.n, p.n)) for p in problems]
@@ -95,3 +105,20 @@ def test_batch_analysis_is_block_diagonal_analysis(orc):
     # each system is a separate tree of the elimination forest
     roots = np.sum(sy["etree"] < 0)
     assert roots >= 12
+
+
+@pytest.mark.parametrize("n", [5, 12])
+def test_elasticity_patterns(orc, n):
+    # 27-point, 3-dof coupling (dense 3x3 node blocks): supernodes follow
+    # the node blocks
+    from gen import elasticity3d
+    p = elasticity3d(n, seed=1)
+    _compare(orc, p.n, p.colptr, p.rowind)
+    _compare(orc, p.n, p.colptr, p.rowind, leaf_size=8, amalg_pct=30, split_width=33)
+
+
+def test_convection_diffusion_pattern(orc):
+    # unsymmetric values on a symmetric pattern: the analysis reads the pattern only
+    from gen import convection_diffusion
+    p = convection_diffusion((14, 13, 12), seed=5)
+    _compare(orc, p.n, p.colptr, p.rowind)
