@@ -11,6 +11,13 @@ same way and reported as a speedup over it (factor + solve time).
 
 value = algorithmic factorization flops (sum of squared exact column counts)
         / FP64 factorization time (HIP events around the factorize call).
+
+Order of the run: the FP64 headline leg, then the oracle's CPU baseline,
+then the other legs (FP32 + refinement, split-BF16 + refinement, L D L^T,
+the 512-system batch) while the wall-clock budget (--budget-s, counted from
+the start of the process) leaves room for them; a leg that does not fit is
+listed under "skipped".  Progress lines with the elapsed time go to stderr;
+the one JSON line goes to stdout at the end.
 """
 from __future__ import annotations
 
@@ -20,10 +27,15 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+
+
+def log(msg):
+    print("[%7.1f s] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
 
 
 def measured_traffic():
@@ -46,29 +58,50 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(p, budget_flops: float = 4.0e10):
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(p, budget_flops: float = 2.0e10):
     """The oracle (plain serial C, one core) on a bounded sample of the same
     workload: its own analysis of the full matrix, then the factorization of
-    the leading column blocks in elimination order up to a flop budget."""
+    the largest subtree of the block elimination tree whose algorithmic flops
+    fit the budget (leaves up to a separator block of that subtree: small and
+    large blocks alike).  Only the factorization is timed; the subtree's
+    assembly is timed apart and reported, not counted."""
     import numpy as np
 
     from oracle import oracle as O
-    sym = O.analyze(p.n, p.colptr, p.rowind)
-    cc = sym.colcount.astype(np.float64)
-    per_col = cc * cc
-    csum = np.concatenate([[0.0], np.cumsum(per_col)])
-    lcol = sym.lcol
-    flops_upto = csum[lcol + 1]   # flops of cblks 0..k
-    kend = int(np.searchsorted(flops_upto, budget_flops, side="right"))
-    kend = max(1, min(kend, len(lcol)))
-    fl = float(flops_upto[kend - 1])
     t0 = time.perf_counter()
-    O.factor_upto(sym, p.colptr, p.rowind, p.values, kend)
-    dt = time.perf_counter() - t0
-    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle factorization of the first %d of %d column blocks of the same matrix in "
-                      "elimination order (%.2e of %.2e algorithmic flops, %.1f s, assembly included)"
-                      % (kend, len(lcol), fl, sym.stats["flops_alg"], dt)}
+    sym = O.analyze(p.n, p.colptr, p.rowind)
+    t_an = time.perf_counter() - t0
+    cc = sym.colcount.astype(np.float64)
+    csum = np.concatenate([[0.0], np.cumsum(cc * cc)])
+    first = O.subtree_first(sym)
+    fcol, lcol = sym.fcol.astype(np.int64), sym.lcol.astype(np.int64)
+    sub_flops = csum[lcol + 1] - csum[fcol[first]]
+    fits = np.where(sub_flops <= budget_flops)[0]
+    root = int(fits[np.argmax(sub_flops[fits])]) if len(fits) else 0
+    k0 = int(first[root])
+    fl = float(sub_flops[root])
+    widths = lcol[k0:root + 1] - fcol[k0:root + 1] + 1
+    _, t_asm, t_fac = O.factor_subtree(sym, p.colptr, p.rowind, p.values, root)
+    return {"value": fl / t_fac / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle factorization of one subtree of the block elimination tree of the same matrix: "
+                      "column blocks %d..%d of %d (widths 1..%d, %d columns), %.3e of %.3e algorithmic flops "
+                      "in %.1f s; its assembly (%.1f s) and the oracle's analysis (%.1f s) not counted"
+                      % (k0, root, len(lcol), int(widths.max()), int(widths.sum()), fl, sym.stats["flops_alg"],
+                         t_fac, t_asm, t_an),
+            "host": host_cpu()}
 
 
 def copy_probe():
@@ -84,28 +117,29 @@ def copy_probe():
     print("copied 3 x %d bytes" % (n * 8), flush=True)
 
 
-def run_leg(torch, np, Solver, p, vals, b0, precision, steps, warmup, method="llt"):
+def run_leg(torch, np, Solver, p, vals, b0, precision, steps, warmup, method="llt", adjoint=True):
     """Warm-up, then `steps` timed passes of factorize + refined solve in one
     precision mode (and method: L L^T, or L D L^T).  Times are HIP events on
     the torch stream the library is called on; the kernel time is the
-    library's own event pair around the scheduler kernel."""
+    library's own event pair around the scheduler kernel, on the same stream."""
+    name = precision if method == "llt" else precision + " " + method
     t0 = time.perf_counter()
     s = Solver(p.n, p.colptr, p.rowind, precision=precision, method=method)
-    precision = precision if method == "llt" else precision + " " + method
     t_an = time.perf_counter() - t0
     info = s.info()
-    print("[%s] analyze %.1f s: ncblk %d nnz(L) %d flops %.3e tasks %d"
-          % (precision, t_an, info["ncblk"], info["nnz_l"], info["flops_alg"], info["ntasks"]), flush=True)
+    log("[%s] analyze %.1f s: ncblk %d nnz(L) %d flops %.3e tasks %d"
+        % (name, t_an, info["ncblk"], info["nnz_l"], info["flops_alg"], info["ntasks"]))
     stream = torch.cuda.current_stream()
+    nrhs = 1 if b0.dim() == 1 else b0.shape[0]
     b = torch.empty_like(b0)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     for i in range(warmup):
         s.factorize(vals)
         b.copy_(b0)
         s.solve(b)
-        print("[%s] warmup %d done" % (precision, i), flush=True)
-    fac_ms, sol_ms, ker_ms, oms, its = [], [], [], [], []
     torch.cuda.synchronize()
+    log("[%s] %d warm-up steps done" % (name, warmup))
+    fac_ms, sol_ms, ker_ms, oms, its = [], [], [], [], []
     for i in range(steps):
         ev[0].record(stream)
         s.factorize(vals)
@@ -119,25 +153,30 @@ def run_leg(torch, np, Solver, p, vals, b0, precision, steps, warmup, method="ll
         ker_ms.append(s.info()["factor_kernel_ms"])
         oms.append(si["omega"])
         its.append(si["ir_iters"])
-        print("[%s] step %d: factorize %.2f ms (kernel %.2f) solve %.2f ms omega %.2e ir %d"
-              % (precision, i, fac_ms[-1], ker_ms[-1], sol_ms[-1], oms[-1], its[-1]), flush=True)
-    # adjoint of the solve (backward pass of solve_autograd): db = A^{-1} xbar
-    # with the same factor, then the value gradient on the pattern
-    xbar = torch.ones_like(b0)
-    adj_ms = []
-    for i in range(3):
-        ev[0].record(stream)
-        db = xbar.clone()
-        s.solve(db)
-        s.values_grad(b, db)
-        ev[1].record(stream)
-        torch.cuda.synchronize()
-        adj_ms.append(ev[0].elapsed_time(ev[1]))
+    log("[%s] %d steps: factorize %.2f ms (kernel %.2f) solve %.2f ms omega %.2e ir %d"
+        % (name, steps, float(np.median(fac_ms)), float(np.mean(ker_ms)), float(np.median(sol_ms)), max(oms),
+           max(its)))
+    out = {"factor_ms": float(np.median(fac_ms)), "solve_ms": float(np.median(sol_ms)),
+           "kernel_ms": float(np.mean(ker_ms)), "omega": float(max(oms)), "ir_iters": int(max(its)),
+           "flops": info["flops_alg"], "nnz_l": info["nnz_l"], "nrhs": nrhs, "analyze_s": t_an}
+    if adjoint:
+        # adjoint of the solve (backward pass of solve_autograd): db = A^{-1} xbar
+        # with the same factor, then the value gradient on the pattern
+        xbar = torch.ones_like(b0)
+        adj_ms = []
+        for i in range(3):
+            ev[0].record(stream)
+            db = xbar.clone()
+            s.solve(db)
+            s.values_grad(b, db)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            adj_ms.append(ev[0].elapsed_time(ev[1]))
+        out["adjoint_ms"] = float(np.median(adj_ms))
+    out["logdet"] = s.info()["logdet"]
     del s
     torch.cuda.synchronize()
-    return {"factor_ms": float(np.median(fac_ms)), "solve_ms": float(np.median(sol_ms)),
-            "kernel_ms": float(np.mean(ker_ms)), "omega": float(max(oms)), "ir_iters": int(max(its)),
-            "flops": info["flops_alg"], "nnz_l": info["nnz_l"], "adjoint_ms": float(np.median(adj_ms))}
+    return out
 
 
 def run_batch(torch, np, Solver, steps):
@@ -177,9 +216,9 @@ def run_batch(torch, np, Solver, steps):
                      "factor_gflops": fl / (float(np.median(fac)) * 1e-3) / 1e9, "omega": float(max(om)),
                      "ir_iters": int(max(its)), "flops_alg": fl,
                      "tuned": {"tile": [inf["tile_rows"], inf["tile_cols"]], "hp_policy": inf["hp_policy"]}}
-        print("[batch %s] factorize %.2f ms solve %.2f ms omega %.2e ir %d tile %s"
-              % (prec, out[prec]["factor_ms"], out[prec]["solve_ms"], out[prec]["omega"], out[prec]["ir_iters"],
-                 out[prec]["tuned"]["tile"]), flush=True)
+        log("[batch %s] factorize %.2f ms solve %.2f ms omega %.2e ir %d tile %s"
+            % (prec, out[prec]["factor_ms"], out[prec]["solve_ms"], out[prec]["omega"], out[prec]["ir_iters"],
+               out[prec]["tuned"]["tile"]))
         del s
     out["fp32_ir"]["speedup_vs_fp64"] = ((out["fp64"]["factor_ms"] + out["fp64"]["solve_ms"])
                                         / (out["fp32_ir"]["factor_ms"] + out["fp32_ir"]["solve_ms"]))
@@ -192,8 +231,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock seconds (from the start of the process) within which optional legs start")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batch leg")
+    ap.add_argument("--headline-only", action="store_true", help="only the FP64 leg (and the CPU baseline)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 512-system batch leg (its JSON object on one line; for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -203,7 +245,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (no multi-GPU path: the factorization and its queue live on one device)", file=sys.stderr)
+        print("bench.py runs on one GPU only (no multi-GPU path: the factorization and its queue live on one device)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -212,16 +255,19 @@ def main():
     from gen import make_config
     from paper_1405_2636_amd import Solver
 
+    log("imports done")
     if args.batch_only:
         print(json.dumps({"batch": run_batch(torch, np, Solver, args.steps)}), flush=True)
         return
     p = make_config(args.config)
+    log("workload %s generated: n %d nnz %d" % (p.name, p.n, p.nnz))
     vals = torch.tensor(p.values, device="cuda")
     b0 = torch.tensor(np.ascontiguousarray(p.b[:, 0]), device="cuda")
-    legs = {prec: run_leg(torch, np, Solver, p, vals, b0, prec, args.steps, args.warmup)
-            for prec in ("fp64", "fp32_ir", "bf16x3_ir")}
-    r64, r32, rbf = legs["fp64"], legs["fp32_ir"], legs["bf16x3_ir"]
-    rld = run_leg(torch, np, Solver, p, vals, b0, "fp64", args.steps, args.warmup, method="ldlt")
+
+    # headline: FP64 L L^T
+    t_leg = time.perf_counter()
+    r64 = run_leg(torch, np, Solver, p, vals, b0, "fp64", args.steps, args.warmup)
+    leg_s = time.perf_counter() - t_leg
     flops = r64["flops"]
     achieved = flops / (r64["kernel_ms"] * 1e-3) / 1e12
     out = {
@@ -243,27 +289,46 @@ def main():
         "solve_ms": r64["solve_ms"],
         "omega": r64["omega"],
         "ir_iters": r64["ir_iters"],
-        "adjoint_ms": r64["adjoint_ms"],
-        "fp32_ir": {"factor_ms": r32["factor_ms"], "solve_ms": r32["solve_ms"],
-                    "factor_gflops": flops / (r32["factor_ms"] * 1e-3) / 1e9, "omega": r32["omega"],
-                    "ir_iters": r32["ir_iters"], "kernel_ms": r32["kernel_ms"],
-                    "speedup_vs_fp64": (r64["factor_ms"] + r64["solve_ms"]) / (r32["factor_ms"] + r32["solve_ms"])},
-        "bf16x3_ir": {"factor_ms": rbf["factor_ms"], "solve_ms": rbf["solve_ms"],
-                      "factor_gflops": flops / (rbf["factor_ms"] * 1e-3) / 1e9, "omega": rbf["omega"],
-                      "ir_iters": rbf["ir_iters"], "kernel_ms": rbf["kernel_ms"],
-                      "speedup_vs_fp64": (r64["factor_ms"] + r64["solve_ms"]) / (rbf["factor_ms"] + rbf["solve_ms"])},
-        "ldlt_fp64": {"factor_ms": rld["factor_ms"], "solve_ms": rld["solve_ms"],
-                      "factor_gflops": flops / (rld["factor_ms"] * 1e-3) / 1e9, "omega": rld["omega"],
-                      "ir_iters": rld["ir_iters"], "kernel_ms": rld["kernel_ms"],
-                      "kernel_frac_of_fp64_peak": flops / (rld["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS},
+        "adjoint_ms": r64.get("adjoint_ms"),
+        "logdet": r64["logdet"],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "sched_kernel<double, false>", "kernel_ms": r64["kernel_ms"]},
+        "skipped": [],
     }
-    if not args.no_batch:
-        out["batch"] = run_batch(torch, np, Solver, args.steps)
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p)
+        log("cpu baseline: %.2f GFLOP/s" % out["cpu_baseline"]["value"])
+
+    def fits(est_s):
+        return time.perf_counter() - T_START + est_s <= args.budget_s
+
+    def speedup(r):
+        return (r64["factor_ms"] + r64["solve_ms"]) / (r["factor_ms"] + r["solve_ms"])
+
+    legs = [] if args.headline_only else ["fp32_ir", "bf16x3_ir", "ldlt_fp64"] + ([] if args.no_batch else ["batch"])
+    for leg in legs:
+        est = 1.3 * leg_s if leg != "batch" else 90.0
+        if not fits(est):
+            out["skipped"].append(leg)
+            log("[%s] skipped: %.0f s estimated, budget %.0f s" % (leg, est, args.budget_s))
+            continue
+        if leg in ("fp32_ir", "bf16x3_ir"):
+            r = run_leg(torch, np, Solver, p, vals, b0, leg, args.steps, args.warmup, adjoint=False)
+            out[leg] = {"factor_ms": r["factor_ms"], "solve_ms": r["solve_ms"],
+                        "factor_gflops": flops / (r["factor_ms"] * 1e-3) / 1e9, "omega": r["omega"],
+                        "ir_iters": r["ir_iters"], "kernel_ms": r["kernel_ms"], "speedup_vs_fp64": speedup(r)}
+        elif leg == "ldlt_fp64":
+            r = run_leg(torch, np, Solver, p, vals, b0, "fp64", args.steps, args.warmup, method="ldlt",
+                        adjoint=False)
+            out[leg] = {"factor_ms": r["factor_ms"], "solve_ms": r["solve_ms"],
+                        "factor_gflops": flops / (r["factor_ms"] * 1e-3) / 1e9, "omega": r["omega"],
+                        "ir_iters": r["ir_iters"], "kernel_ms": r["kernel_ms"],
+                        "kernel_frac_of_fp64_peak": flops / (r["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+        elif leg == "batch":
+            out["batch"] = run_batch(torch, np, Solver, args.steps)
+    log("done")
     print(json.dumps(out), flush=True)
 
 

@@ -69,6 +69,10 @@ def _load():
     L.orc_factor.argtypes = [vp, vp, C.POINTER(i32)]
     L.orc_factor_upto.restype = C.c_int
     L.orc_factor_upto.argtypes = [vp, vp, i32, C.POINTER(i32)]
+    L.orc_factor_range.restype = C.c_int
+    L.orc_factor_range.argtypes = [vp, vp, i32, i32, C.POINTER(i32)]
+    L.orc_assemble_range.restype = C.c_int
+    L.orc_assemble_range.argtypes = [vp, vp, vp, vp, vp, i32, i32]
     L.orc_solve.restype = C.c_int
     L.orc_solve.argtypes = [vp, vp, i32, vp, i64, vp, i64]
     L.orc_residual.restype = None
@@ -260,6 +264,45 @@ def factor_upto(sym: Symbolic, colptr, rowind, values, kend):
     if rc != 0:
         raise RuntimeError("orc_factor_upto failed %d" % rc)
     return P
+
+
+def subtree_first(sym: Symbolic):
+    """First column block of the subtree rooted at every block of the block
+    elimination tree (blocks are numbered in postorder, so the subtree of r is
+    the range first[r] .. r)."""
+    nc = int(sym.stats["ncblk"])
+    first = np.arange(nc, dtype=np.int64)
+    par = sym.cparent
+    for k in range(nc):
+        p = int(par[k])
+        if p >= 0 and first[k] < first[p]:
+            first[p] = first[k]
+    return first
+
+
+def factor_subtree(sym: Symbolic, colptr, rowind, values, root):
+    """Assemble and factor the subtree of block ``root`` only (its updates into
+    the blocks above it included).  Returns (P, assembly seconds,
+    factorization seconds); the subtree's panels hold their final values."""
+    import time
+    L = _load()
+    k0 = int(subtree_first(sym)[root])
+    k1 = int(root) + 1
+    P = np.zeros(max(int(sym.stats["panel_size"]), 1), np.float64)
+    t0 = time.perf_counter()
+    rc = L.orc_assemble_range(C.c_void_p(sym.handle), _p(_c(colptr, np.int64)), _p(_c(rowind, np.int32)),
+                              _p(_c(values, np.float64)), _p(P), k0, k1)
+    t1 = time.perf_counter()
+    if rc != 0:
+        raise ValueError("assemble_range failed")
+    fc = C.c_int32(-1)
+    rc = L.orc_factor_range(C.c_void_p(sym.handle), _p(P), k0, k1, C.byref(fc))
+    t2 = time.perf_counter()
+    if rc == ENOTPD:
+        raise NotPositiveDefinite(fc.value, int(sym.perm[fc.value]))
+    if rc != 0:
+        raise RuntimeError("orc_factor_range failed %d" % rc)
+    return P, t1 - t0, t2 - t1
 
 
 class ZeroPivot(RuntimeError):

@@ -819,6 +819,39 @@ int orc_assemble(const orc_sym* s, const i64* colptr, const i32* rowind, const d
 }
 
 /*
+ * The same assembly for the column blocks k0..k1-1 only: their panels are
+ * zeroed and receive the entries whose (permuted) column they hold; other
+ * panels are left as they are.  Used to time the factorization of one
+ * subtree of the block elimination tree without assembling the whole matrix.
+ */
+int orc_assemble_range(const orc_sym* s, const i64* colptr, const i32* rowind, const double* val, double* P,
+                       i32 k0, i32 k1)
+{
+    if (k0 < 0) k0 = 0;
+    if (k1 > s->ncblk) k1 = s->ncblk;
+    if (k0 >= k1) return ORC_OK;
+    memset(P + s->panel_off[k0], 0, sizeof(double) * (size_t)(s->panel_off[k1] - s->panel_off[k0]));
+    const i32 c0 = s->fcol[k0], c1 = s->lcol[k1 - 1];
+    i32* col2cblk = (i32*)malloc(sizeof(i32) * ((size_t)s->n + 1));
+    if (!col2cblk) return ORC_ENOMEM;
+    for (i32 k = 0; k < s->ncblk; k++) for (i32 j = s->fcol[k]; j <= s->lcol[k]; j++) col2cblk[j] = k;
+    for (i32 j = 0; j < s->n; j++)
+        for (i64 p = colptr[j]; p < colptr[j + 1]; p++) {
+            i32 i = rowind[p];
+            if (i < j) continue;
+            i32 a = s->iperm[i], b = s->iperm[j];
+            i32 r = a > b ? a : b, c = a > b ? b : a;
+            if (c < c0 || c > c1) continue;
+            i32 k = col2cblk[c];
+            i32 pos = row_pos(s, k, r);
+            if (pos < 0) { free(col2cblk); return ORC_EINVAL; }
+            P[s->panel_off[k] + (i64)(c - s->fcol[k]) * s->stride[k] + pos] += val[p];
+        }
+    free(col2cblk);
+    return ORC_OK;
+}
+
+/*
  * Right-looking supernodal LL^T in ascending column-block order
  * (Section III, steps 1-3 of the 1D task; Section V-B CPU update scheme):
  *   1. Cholesky of the diagonal block, column by column; breakdown when a
@@ -831,22 +864,33 @@ int orc_assemble(const orc_sym* s, const i64* colptr, const i32* rowind, const d
  *      triangle of j's diagonal block is touched.
  * Returns ORC_ENOTPD and the failing column (final numbering) on breakdown.
  */
-int orc_factor_upto(const orc_sym* s, double* P, i32 kend, i32* fail_col);
+int orc_factor_range(const orc_sym* s, double* P, i32 kbeg, i32 kend, i32* fail_col);
 
-int orc_factor(const orc_sym* s, double* P, i32* fail_col) { return orc_factor_upto(s, P, s->ncblk, fail_col); }
+int orc_factor(const orc_sym* s, double* P, i32* fail_col) { return orc_factor_range(s, P, 0, s->ncblk, fail_col); }
 
 /* Column blocks 0..kend-1 only: after it they hold their final values (every
  * update into them comes from a smaller block). */
 int orc_factor_upto(const orc_sym* s, double* P, i32 kend, i32* fail_col)
 {
+    return orc_factor_range(s, P, 0, kend, fail_col);
+}
+
+/* Column blocks kbeg..kend-1 only (their updates into later blocks
+ * included).  When kbeg..kend-1 is a whole subtree of the block elimination
+ * tree (the descendants of kend-1 and itself, consecutive in the postorder),
+ * every update into these blocks comes from inside the range, so they hold
+ * their final values afterwards. */
+int orc_factor_range(const orc_sym* s, double* P, i32 kbeg, i32 kend, i32* fail_col)
+{
     *fail_col = -1;
     if (kend > s->ncblk) kend = s->ncblk;
+    if (kbeg < 0) kbeg = 0;
     i32 maxs = 0;
     for (i32 k = 0; k < s->ncblk; k++) if (s->stride[k] > maxs) maxs = s->stride[k];
     double* W = (double*)malloc(sizeof(double) * (size_t)maxs * (size_t)maxs + 8);
     i32* grow = (i32*)malloc(sizeof(i32) * ((size_t)maxs + 1));
     if (!W || !grow) return ORC_ENOMEM;
-    for (i32 k = 0; k < kend; k++) {
+    for (i32 k = kbeg; k < kend; k++) {
         i32 wd = s->lcol[k] - s->fcol[k] + 1, ld = s->stride[k];
         double* L = P + s->panel_off[k];
         /* global row of each panel row */

@@ -26,6 +26,7 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_assemble(void* panels, bool f32, const int64_t* amap, const double* values, int64_t nnz,
                            hipStream_t s);
 hipError_t launch_widen(double* dst, const float* src, int64_t n, hipStream_t s);
+hipError_t launch_gather_diag(double* dst, const void* panels, bool f32, const int64_t* off, int64_t n, hipStream_t s);
 hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, int32_t nready_hp,
                              const int32_t* fact_dep0, int32_t ncblk, hipStream_t s);
 int sched_blocks_per_cu(bool f32, bool ldlt);
@@ -118,6 +119,7 @@ struct spx_handle {
     // device plan
     DevBuf<int32_t> fcol, lcol, stride, bptr, frow, lrow, coefind, perm;
     DevBuf<int64_t> panel_off, dinv_off;
+    DevBuf<int64_t> diag_off;   // panel offset of the diagonal entry of every column
     DevBuf<int64_t> amap, rptr, rval;
     DevBuf<int32_t> rcol;
     DevBuf<int32_t> erow, ecol;   // row and column of every stored entry (-1: above the diagonal)
@@ -528,6 +530,13 @@ void upload_plan(spx_handle* h)
     }
     h->dinv_size = doff[P.ncblk];
     h->dinv_off.upload(doff);
+    {
+        std::vector<int64_t> dg(static_cast<size_t>(P.n));
+        for (int32_t k = 0; k < P.ncblk; ++k)
+            for (int32_t c = P.fcol[k]; c <= P.lcol[k]; ++c)
+                dg[c] = P.panel_off[k] + static_cast<int64_t>(c - P.fcol[k]) * (P.stride[k] + 1);
+        h->diag_off.upload(dg);
+    }
     h->amap.upload(P.amap);
     h->rptr.upload(P.rptr);
     h->rcol.upload(P.rcol);
@@ -999,19 +1008,14 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
         if (h->factorized && !h->logdet_valid) {
             // 2 * sum log l_jj (L D L^T: sum log |d_j| and the count of d_j < 0)
             // with pairwise summation, from the diagonal of each panel
+            // one gather kernel into a contiguous FP64 vector, one copy
             std::vector<double> diag(static_cast<size_t>(P.n));
-            std::vector<float> diag_f(h->f32() ? static_cast<size_t>(P.n) : 0);
-            for (int32_t k = 0; k < P.ncblk; ++k) {
-                const int32_t w = P.lcol[k] - P.fcol[k] + 1;
-                const size_t pitch = static_cast<size_t>(P.stride[k]) + 1;
-                if (h->f32())
-                    HIPCHK(hipMemcpy2D(diag_f.data() + P.fcol[k], sizeof(float), h->panels_f.p + P.panel_off[k],
-                                       pitch * sizeof(float), sizeof(float), w, hipMemcpyDeviceToHost));
-                else
-                    HIPCHK(hipMemcpy2D(diag.data() + P.fcol[k], sizeof(double), h->panels.p + P.panel_off[k],
-                                       pitch * sizeof(double), sizeof(double), w, hipMemcpyDeviceToHost));
+            if (P.n > 0) {
+                DevBuf<double> dd;
+                dd.alloc(static_cast<size_t>(P.n));
+                HIPCHK(launch_gather_diag(dd.p, h->panel_ptr(), h->f32(), h->diag_off.p, P.n, nullptr));
+                HIPCHK(hipMemcpy(diag.data(), dd.p, static_cast<size_t>(P.n) * sizeof(double), hipMemcpyDeviceToHost));
             }
-            if (h->f32()) std::copy(diag_f.begin(), diag_f.end(), diag.begin());
             h->nneg = 0;
             if (h->ldlt()) {
                 for (auto& d : diag) {

@@ -1217,6 +1217,24 @@ __global__ void widen_kernel(double* dst, const float* src, int64_t n)
         dst[i] = (double)src[i];
 }
 
+// dst[j] = panels[off[j]] widened to FP64 (the diagonal of every panel, one
+// entry per column, for the log-determinant)
+template <class T>
+__global__ void gather_diag_kernel(double* dst, const T* panels, const int64_t* off, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (double)panels[off[i]];
+}
+
+hipError_t launch_gather_diag(double* dst, const void* panels, bool f32, const int64_t* off, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    if (f32) gather_diag_kernel<float><<<blocks, 256, 0, s>>>(dst, static_cast<const float*>(panels), off, n);
+    else gather_diag_kernel<double><<<blocks, 256, 0, s>>>(dst, static_cast<const double*>(panels), off, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_widen(double* dst, const float* src, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;

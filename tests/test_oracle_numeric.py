@@ -149,3 +149,26 @@ def test_omega_conventions(orc):
     s = np.array([0.0, 2.0, 1.0])
     assert orc.omega(r, s) == pytest.approx(1e-3)
     assert orc.omega(np.array([1.0]), np.array([0.0])) == np.inf
+
+
+@pytest.mark.parametrize("dims", [(12, 12, 12), (40, 40)])
+def test_subtree_factor_equals_full_factor(orc, dims):
+    # the bounded CPU sample factors one subtree of the block elimination
+    # tree: every update into its blocks comes from inside it (postorder), so
+    # its panels equal those of the full factorization bit for bit, and the
+    # subtrees' ranges nest as in a tree
+    p = grid_laplacian(dims, shift=1e-3)
+    s = orc.analyze(p.n, p.colptr, p.rowind, leaf=16)
+    first = orc.subtree_first(s)
+    nc = int(s.stats["ncblk"])
+    for k in range(nc):
+        c = int(s.cparent[k])
+        assert first[k] <= k
+        if c >= 0:
+            assert first[c] <= first[k] and k < c
+    P = orc.factor(s, p.colptr, p.rowind, p.values)
+    sizes = np.arange(nc) - first
+    for root in (int(np.argmax(np.where(sizes < nc // 3, sizes, -1))), nc - 1, 0):
+        Ps, _, _ = orc.factor_subtree(s, p.colptr, p.rowind, p.values, root)
+        lo, hi = int(s.panel_off[first[root]]), int(s.panel_off[root + 1])
+        assert np.array_equal(Ps[lo:hi], P[lo:hi])
