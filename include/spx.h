@@ -204,6 +204,23 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
 int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_device,
               spx_solve_info* info, void* hip_stream);
 
+/* Allocation-free variant of spx_solve, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same result and refinement as spx_solve; b is a
+ * device pointer (n x nrhs, column-major, leading dimension ldb >= n),
+ * overwritten with x.  The work vectors live in a fixed array of 64 MiB per
+ * device inside the library (set up by spx_analyze on the handle's device and
+ * held until the process ends), not in allocations: 7 * n * nrhs doubles
+ * (each vector rounded up to 256 bytes) plus 1280 bytes must fit, i.e. n *
+ * nrhs up to about 1.19e6; larger calls return SPX_EINVAL before any device
+ * work.  The sweeps are launched one by one (no graph).  Every call on a
+ * device shares that device's array and leaves its contents behind: calls
+ * that overlap on one device (two threads, or two streams not ordered with
+ * each other) race and must be serialized by the caller.  The current
+ * device must be the handle's.  Errors: as spx_solve. */
+int spx_solve_noalloc(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, spx_solve_info* info,
+                      void* hip_stream);
+
 /* Adjoint of the solve (x = A^{-1} b): gradient of a loss with respect to
  * the values passed to spx_factorize, given x and db = A^{-T} xbar (for
  * symmetric A, db is spx_solve applied to xbar with the same factor).  The

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspx.so")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = ["analyze.cpp", "api.cpp", "factor.hip", "solve.hip"]
+SOURCES = ["analyze.cpp", "api.cpp", "factor.hip", "solve.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]

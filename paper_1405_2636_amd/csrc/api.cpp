@@ -49,6 +49,7 @@ hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const doubl
                            const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
                            unsigned long long* stats, hipStream_t s);
 hipError_t launch_gather(double* rv, const double* vals, const int64_t* idx, int64_t m, hipStream_t s);
+hipError_t scratch_region(void** ptr, size_t* bytes);
 
 struct DeviceError : std::runtime_error {
     explicit DeviceError(const std::string& s) : std::runtime_error(s) {}
@@ -168,6 +169,10 @@ struct spx_handle {
     hipGraphExec_t fgraph_exec[2] = {nullptr, nullptr};
     int device = 0;
     int grid = 0;
+    // the fixed work array of the allocation-free solve on this handle's
+    // device (device address, from scratch_region at the plan upload)
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
     int64_t timeout_ticks = 0;
     bool uploaded = false;
 
@@ -576,11 +581,19 @@ void upload_plan(spx_handle* h)
         clk_khz = 100000;
     h->grid = std::max(1, ncu * sched_blocks_per_cu(h->f32(), h->ldlt()));
     h->timeout_ticks = static_cast<int64_t>(clk_khz) * 1000 * 20;   // 20 s per wait
+    HIPCHK(scratch_region(&h->scratch, &h->scratch_bytes));
 }
 
-// One application of (L L^T)^{-1} to the permuted vectors in y (consumed):
-// result in h->xv.
-void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
+// Vectors of one application of the inverse: y (permuted right-hand side,
+// consumed), z (forward result), x (backward result), tacc (backward partial
+// sums); n x nrhs each, leading dimension n.
+struct SweepBufs {
+    double *y, *z, *x, *tacc;
+};
+
+// One application of (L L^T)^{-1} to the permuted vectors in w.y (consumed):
+// result in w.x.
+void sweeps(spx_handle* h, const SweepBufs& w, int32_t nrhs, hipStream_t s)
 {
     SweepArgs a;
     a.pl = h->devplan();
@@ -590,10 +603,10 @@ void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
     a.ldlt = h->ldlt() ? 1 : 0;
     a.rowg = h->rowg.p;
     a.rowg_off = h->rowg_off.p;
-    a.y = y;
-    a.z = h->zv.p;
-    a.x = h->xv.p;
-    a.tacc = h->tacc.p;
+    a.y = w.y;
+    a.z = w.z;
+    a.x = w.x;
+    a.tacc = w.tacc;
     a.n = h->n;
     a.nrhs = nrhs;
     const Level& L = h->lv;
@@ -605,7 +618,7 @@ void sweeps(spx_handle* h, double* y, int32_t nrhs, hipStream_t s)
         HIPCHK(launch_fwd_diag(a, sm + ns, nb, L.maxw[l], s));
         HIPCHK(launch_fwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
     }
-    HIPCHK(launch_fill_f64(h->tacc.p, static_cast<int64_t>(h->n) * nrhs, 0.0, s));
+    HIPCHK(launch_fill_f64(w.tacc, static_cast<int64_t>(h->n) * nrhs, 0.0, s));
     for (int l = nl - 1; l >= 0; --l) {
         const int32_t* sm = h->lv_cblk.p + L.cptr[l];
         const int ns = L.nsmall[l], nb = L.cptr[l + 1] - L.cptr[l] - ns;
@@ -712,6 +725,44 @@ void run_factorization(spx_handle* h, hipStream_t s)
         throw StatusError(SPX_ENOTPD, std::string(h->ldlt() ? "zero or non-finite pivot" : "pivot not positive") +
                                           " at column " + std::to_string(h->fail_col));
     }
+}
+
+// Refinement shared by the solve entry points (FP64 residual, Section III's
+// solve followed by iterative refinement): apply_b() sets xw = A^{-1} b;
+// then, until omega <= ir_tol, ir_max_iter steps or stagnation (omega above
+// half its previous value twice in a row): r = b - A xw with its statistics
+// (stats: 5 lines of kStatStride words), apply_r() sets dw = A^{-1} rw,
+// xw += dw.  b is a device array with leading dimension ldb.
+template <class FB, class FR>
+spx_solve_info refine(spx_handle* h, int32_t nrhs, const double* b, int64_t ldb, double* xw, double* rw,
+                      const double* dw, unsigned long long* stats, FB apply_b, FR apply_r, hipStream_t s)
+{
+    const int32_t n = h->n;
+    const size_t tot = static_cast<size_t>(n) * nrhs;
+    apply_b();
+    int iters = 0, slow = 0;
+    double omega = 0.0, eta = 0.0, prev = INFINITY;
+    const double tol = h->opt.ir_tol;
+    for (;;) {
+        HIPCHK(launch_zero_u64(stats, 5 * kStatStride, s));
+        HIPCHK(launch_residual(h->rptr.p, h->rcol.p, h->rv.p, xw, b, ldb, rw, n, nrhs, stats, s));
+        unsigned long long st[5 * kStatStride];
+        HIPCHK(hipMemcpyAsync(st, stats, sizeof st, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double v[5];
+        for (int q = 0; q < 5; ++q) std::memcpy(&v[q], &st[q * kStatStride], sizeof(double));
+        omega = v[0];
+        const double den = v[4] * v[2] + v[3];
+        eta = v[1] == 0.0 ? 0.0 : (den == 0.0 ? INFINITY : v[1] / den);
+        if (omega <= tol || iters >= h->opt.ir_max_iter) break;
+        slow = omega > 0.5 * prev ? slow + 1 : 0;
+        if (slow >= 2) break;
+        prev = omega;
+        apply_r();
+        HIPCHK(launch_axpy(xw, dw, static_cast<int64_t>(tot), s));
+        ++iters;
+    }
+    return spx_solve_info{iters, omega <= tol ? 1 : 0, omega, eta};
 }
 
 double pairwise_sum(const double* v, int64_t n)
@@ -935,7 +986,7 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
             if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
             HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
             HIPCHK(launch_permute_in(h->y.p, h->rw.p, n, h->perm.p, n, nrhs, h->cap_stream));
-            sweeps(h, h->y.p, nrhs, h->cap_stream);
+            sweeps(h, SweepBufs{h->y.p, h->zv.p, h->xv.p, h->tacc.p}, nrhs, h->cap_stream);
             HIPCHK(launch_permute_out(h->dw.p, n, h->xv.p, h->perm.p, n, nrhs, h->cap_stream));
             HIPCHK(hipStreamEndCapture(h->cap_stream, &h->graph));
             HIPCHK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
@@ -944,41 +995,74 @@ int spx_solve(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, int32_t b_on_
         // the right-hand side, packed (leading dimension n)
         HIPCHK(hipMemcpy2DAsync(h->bw.p, n * sizeof(double), b, ldb * sizeof(double), n * sizeof(double), nrhs,
                                 b_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
-        // x0 = A^{-1} b
-        HIPCHK(hipMemcpyAsync(h->rw.p, h->bw.p, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipGraphLaunch(h->graph_exec, s));
-        HIPCHK(hipMemcpyAsync(h->xw.p, h->dw.p, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
-        int iters = 0, slow = 0;
-        double omega = 0.0, eta = 0.0, prev = INFINITY;
-        const double tol = h->opt.ir_tol;
-        for (;;) {
-            HIPCHK(launch_zero_u64(h->stats.p, 5 * kStatStride, s));
-            HIPCHK(launch_residual(h->rptr.p, h->rcol.p, h->rv.p, h->xw.p, h->bw.p, n, h->rw.p, n, nrhs,
-                                   h->stats.p, s));
-            unsigned long long st[5 * kStatStride];
-            HIPCHK(hipMemcpyAsync(st, h->stats.p, sizeof st, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            double v[5];
-            for (int q = 0; q < 5; ++q) std::memcpy(&v[q], &st[q * kStatStride], sizeof(double));
-            omega = v[0];
-            const double den = v[4] * v[2] + v[3];
-            eta = v[1] == 0.0 ? 0.0 : (den == 0.0 ? INFINITY : v[1] / den);
-            if (omega <= tol || iters >= h->opt.ir_max_iter) break;
-            // stagnation: omega above half its previous value twice in a row
-            slow = omega > 0.5 * prev ? slow + 1 : 0;
-            if (slow >= 2) break;
-            prev = omega;
-            // d = A^{-1} r ; x += d
-            HIPCHK(hipGraphLaunch(h->graph_exec, s));
-            HIPCHK(launch_axpy(h->xw.p, h->dw.p, static_cast<int64_t>(tot), s));
-            ++iters;
-        }
+        const spx_solve_info si = refine(
+            h, nrhs, h->bw.p, n, h->xw.p, h->rw.p, h->dw.p, h->stats.p,
+            [&] {   // x0 = A^{-1} b
+                HIPCHK(hipMemcpyAsync(h->rw.p, h->bw.p, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipGraphLaunch(h->graph_exec, s));
+                HIPCHK(hipMemcpyAsync(h->xw.p, h->dw.p, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+            },
+            [&] { HIPCHK(hipGraphLaunch(h->graph_exec, s)); }, s);
         HIPCHK(hipMemcpy2DAsync(b, ldb * sizeof(double), h->xw.p, n * sizeof(double), n * sizeof(double), nrhs,
                                 b_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        const bool conv = omega <= tol;
-        if (info) *info = spx_solve_info{iters, conv ? 1 : 0, omega, eta};
-        if (!conv) throw StatusError(SPX_ENOCONV, "refinement stopped above the tolerance");
+        if (info) *info = si;
+        if (!si.converged) throw StatusError(SPX_ENOCONV, "refinement stopped above the tolerance");
+        return SPX_OK;
+    });
+}
+
+int spx_solve_noalloc(spx_handle* h, int32_t nrhs, double* b, int64_t ldb, spx_solve_info* info, void* hip_stream)
+{
+    if (!h) return SPX_EINVAL;
+    return guarded(h, [&]() -> int {
+        if (!h->factorized) throw StatusError(SPX_ESTATE, "solve called without a successful factorization");
+        if (nrhs < 0 || ldb < h->n || (nrhs > 0 && h->n > 0 && !b)) throw InvalidArgument("bad right-hand side");
+        if (info) *info = spx_solve_info{0, 1, 0.0, 0.0};
+        if (nrhs == 0 || h->n == 0) return SPX_OK;
+        int dev = -1;
+        HIPCHK(hipGetDevice(&dev));
+        if (dev != h->device || !h->scratch) throw InvalidArgument("the current device is not the handle's device");
+        // work layout in the device's fixed array: the statistics lines, then
+        // y, z, x, tacc, xw, rw, dw (n x nrhs doubles each, 256-byte aligned)
+        const int32_t n = h->n;
+        const size_t tot = static_cast<size_t>(n) * nrhs;
+        const size_t vec = (tot * sizeof(double) + 255) / 256 * 256;
+        const size_t head = 5 * kStatStride * sizeof(unsigned long long);
+        const size_t need = head + 7 * vec;
+        if (need > h->scratch_bytes) {
+            char buf[200];
+            std::snprintf(buf, sizeof buf,
+                          "n * nrhs = %zu needs %zu bytes of work memory; the allocation-free solve has %zu "
+                          "(at most %zu unknowns times right-hand sides)",
+                          tot, need, h->scratch_bytes, (h->scratch_bytes - head) / 7 / sizeof(double));
+            throw InvalidArgument(buf);
+        }
+        char* base = static_cast<char*>(h->scratch);
+        unsigned long long* stats = reinterpret_cast<unsigned long long*>(base);
+        double* v[7];
+        for (int q = 0; q < 7; ++q) v[q] = reinterpret_cast<double*>(base + head + q * vec);
+        const SweepBufs w{v[0], v[1], v[2], v[3]};
+        double *xw = v[4], *rw = v[5], *dw = v[6];
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        const spx_solve_info si = refine(
+            h, nrhs, b, ldb, xw, rw, dw, stats,
+            [&] {   // x0 = A^{-1} b, read in place
+                HIPCHK(launch_permute_in(w.y, b, ldb, h->perm.p, n, nrhs, s));
+                sweeps(h, w, nrhs, s);
+                HIPCHK(launch_permute_out(xw, n, w.x, h->perm.p, n, nrhs, s));
+            },
+            [&] {
+                HIPCHK(launch_permute_in(w.y, rw, n, h->perm.p, n, nrhs, s));
+                sweeps(h, w, nrhs, s);
+                HIPCHK(launch_permute_out(dw, n, w.x, h->perm.p, n, nrhs, s));
+            },
+            s);
+        HIPCHK(hipMemcpy2DAsync(b, ldb * sizeof(double), xw, n * sizeof(double), n * sizeof(double), nrhs,
+                                hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (info) *info = si;
+        if (!si.converged) throw StatusError(SPX_ENOCONV, "refinement stopped above the tolerance");
         return SPX_OK;
     });
 }

@@ -99,6 +99,9 @@ constexpr int kSmallMap = 2048;
 constexpr int kStatStride = 32;   // u64 words between statistics
 constexpr int kResidualBlocks = 1024;
 
+// Fixed work memory of the allocation-free solve, per device (bytes).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+
 constexpr int kThreads = 256;   // 4 waves of 64
 constexpr int kTile = 64;       // rows/cols of update, triangular-solve tiles
 constexpr int kNB = 32;         // diagonal tile (inverted explicitly)

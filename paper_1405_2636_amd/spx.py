@@ -76,7 +76,7 @@ class SymView(C.Structure):
 
 EXPORTED = ["spx_default_options", "spx_analyze", "spx_factorize", "spx_solve", "spx_get_info",
             "spx_export_symbolic", "spx_copy_factor", "spx_get_trace", "spx_destroy", "spx_strerror",
-            "spx_last_error", "spx_values_grad", "spx_analyze_batch"]
+            "spx_last_error", "spx_values_grad", "spx_analyze_batch", "spx_solve_noalloc"]
 
 _lib = None
 
@@ -98,6 +98,8 @@ def load_library():
     L.spx_factorize.argtypes = [vp, vp, C.c_int32, vp]
     L.spx_solve.restype = C.c_int
     L.spx_solve.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_int32, C.POINTER(SolveInfo), vp]
+    L.spx_solve_noalloc.restype = C.c_int
+    L.spx_solve_noalloc.argtypes = [vp, C.c_int32, vp, C.c_int64, C.POINTER(SolveInfo), vp]
     L.spx_get_info.restype = C.c_int
     L.spx_get_info.argtypes = [vp, C.POINTER(Info)]
     L.spx_export_symbolic.restype = C.c_int
@@ -279,6 +281,27 @@ class Solver:
         if rc == SPX_ENOCONV:
             raise NotConverged(rc, self._lib.spx_last_error(self._h).decode(), b, info)
         self._check(rc, "solve")
+        return b, info
+
+    def solve_noalloc(self, b, stream=None, raise_on_noconv=True):
+        """solve() through spx_solve_noalloc: no device allocation (fixed work
+        array of the library, n * nrhs up to about 1.19e6; calls on one device
+        must not overlap).  b: contiguous float64 CUDA tensor (n,) or (nrhs, n)."""
+        import torch
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64 and b.is_contiguous()):
+            raise ValueError("b must be a contiguous float64 CUDA tensor")
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        if b.shape[-1] != self.n:
+            raise ValueError("b has the wrong length")
+        si = SolveInfo()
+        rc = self._lib.spx_solve_noalloc(self._h, nrhs, C.c_void_p(b.data_ptr()), self.n, C.byref(si),
+                                         _stream_ptr(stream))
+        info = {"ir_iters": si.ir_iters, "converged": bool(si.converged), "omega": si.omega, "eta": si.eta}
+        if rc == SPX_ENOCONV and not raise_on_noconv:
+            return b, info
+        if rc == SPX_ENOCONV:
+            raise NotConverged(rc, self._lib.spx_last_error(self._h).decode(), b, info)
+        self._check(rc, "solve_noalloc")
         return b, info
 
     def info(self) -> dict:
