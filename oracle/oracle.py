@@ -71,6 +71,8 @@ def _load():
     L.orc_factor_upto.argtypes = [vp, vp, i32, C.POINTER(i32)]
     L.orc_factor_range.restype = C.c_int
     L.orc_factor_range.argtypes = [vp, vp, i32, i32, C.POINTER(i32)]
+    L.orc_values_grad.restype = None
+    L.orc_values_grad.argtypes = [i32, vp, vp, i32, vp, vp, i64, vp]
     L.orc_assemble_range.restype = C.c_int
     L.orc_assemble_range.argtypes = [vp, vp, vp, vp, vp, i32, i32]
     L.orc_solve.restype = C.c_int
@@ -459,19 +461,15 @@ def values_grad(n, colptr, rowind, x, db):
     lower entry a_ij (i > j) sets both A_ij and A_ji, so its gradient is
     -(db_i x_j + db_j x_i); a diagonal entry gets -db_i x_i; an entry above
     the diagonal is not read by the factorization and gets 0."""
-    colptr = np.asarray(colptr, np.int64)
-    rowind = np.asarray(rowind, np.int64)
+    L = _load()
+    colptr = _c(colptr, np.int64)
+    rowind = _c(rowind, np.int32)
     x = np.asarray(x, np.float64).reshape(n, -1)
     db = np.asarray(db, np.float64).reshape(n, -1)
-    col = np.repeat(np.arange(n), np.diff(colptr))
-    g = np.zeros(len(rowind))
-    for p in range(len(rowind)):
-        i, j = int(rowind[p]), int(col[p])
-        if i > j:
-            g[p] = -float(np.dot(db[i], x[j]) + np.dot(db[j], x[i]))
-        elif i == j:
-            g[p] = -float(np.dot(db[i], x[i]))
-    return g
+    xf, dbf = np.asfortranarray(x), np.asfortranarray(db)
+    g = np.zeros(max(len(rowind), 1))
+    L.orc_values_grad(n, _p(colptr), _p(rowind), x.shape[1], _p(xf), _p(dbf), n, _p(g))
+    return g[:len(rowind)]
 
 
 def adjoint(sym: Symbolic, P, colptr, rowind, values, x, xbar):

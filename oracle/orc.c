@@ -1427,3 +1427,28 @@ i64 orc_unpack(const orc_sym* s, const double* P, i32* ri, i32* ci, double* v)
     }
     return q;
 }
+
+/*
+ * Value gradient of a loss through x = A^{-1} b, A symmetric and given by
+ * its lower triangle, from x and db = A^{-T} xbar (n x nrhs, column-major,
+ * leading dimension ld).  The derivative with respect to the matrix is
+ * dA = -db x^T summed over the right-hand sides; a stored entry (i, j) with
+ * i > j sets both A_ij and A_ji, so it gets -sum_k (db_ik x_jk + db_jk x_ik);
+ * a diagonal entry gets -sum_k db_ik x_ik; an entry above the diagonal is
+ * never read and gets 0.
+ */
+void orc_values_grad(i32 n, const i64* colptr, const i32* rowind, i32 nrhs, const double* x, const double* db,
+                     i64 ld, double* g)
+{
+    for (i32 j = 0; j < n; j++)
+        for (i64 p = colptr[j]; p < colptr[j + 1]; p++) {
+            i32 i = rowind[p];
+            double acc = 0.0;
+            if (i == j)
+                for (i32 k = 0; k < nrhs; k++) acc += db[(i64)k * ld + i] * x[(i64)k * ld + i];
+            else if (i > j)
+                for (i32 k = 0; k < nrhs; k++)
+                    acc += db[(i64)k * ld + i] * x[(i64)k * ld + j] + db[(i64)k * ld + j] * x[(i64)k * ld + i];
+            g[p] = i < j ? 0.0 : -acc;
+        }
+}

@@ -261,6 +261,7 @@ class Solver:
             on_dev, ptr = 0, keep.ctypes.data
         rc = self._lib.spx_factorize(self._h, C.c_void_p(ptr), on_dev, _stream_ptr(stream))
         del keep
+        self._gen = getattr(self, "_gen", 0) + 1   # factorizations started on this handle
         self._check(rc, "factorize")
 
     def solve(self, b, stream=None, raise_on_noconv=True):
@@ -377,20 +378,29 @@ def _solve_function():
     class SolveFunction(torch.autograd.Function):
         """x = A(values)^{-1} b with a hand-written adjoint: the backward pass
         solves with the same factor (db = A^{-1} xbar, A symmetric) and forms the
-        value gradient -db x^T restricted to the pattern (spx_values_grad)."""
+        value gradient -db x^T restricted to the pattern (spx_values_grad).
+        If the solver was factorized again between this forward pass and its
+        backward pass (another solve_autograd call on the same solver), the
+        backward pass first refactorizes the values saved by the forward pass,
+        so that db and the gradient belong to this pass's matrix."""
 
         @staticmethod
         def forward(ctx, values, b, solver):
-            solver.factorize(values.detach().contiguous())
+            v = values.detach().contiguous()
+            solver.factorize(v)
             x, _ = solver.solve(b.detach().clone().contiguous())
             ctx.solver = solver
-            ctx.save_for_backward(x)
+            ctx.gen = solver._gen
+            ctx.save_for_backward(x, v)
             return x
 
         @staticmethod
         def backward(ctx, xbar):
-            (x,) = ctx.saved_tensors
+            x, v = ctx.saved_tensors
             solver = ctx.solver
+            if solver._gen != ctx.gen:
+                solver.factorize(v)
+                ctx.gen = solver._gen
             db, _ = solver.solve(xbar.detach().clone().contiguous())
             gv = solver.values_grad(x, db) if ctx.needs_input_grad[0] else None
             return gv, (db if ctx.needs_input_grad[1] else None), None

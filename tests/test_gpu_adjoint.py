@@ -77,3 +77,27 @@ def test_autograd_finite_differences(torch):
 
     fd = (L(v0 + h * dv) - L(v0 - h * dv)) / (2 * h)
     assert abs(fd - analytic) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_backward_after_refactorization(orc, torch):
+    # two forward passes on one solver with different values before either
+    # backward pass: each backward pass must use its own matrix
+    from paper_1405_2636_amd import Solver, solve_autograd
+    p = grid_laplacian((11, 10, 9), shift=1e-3)
+    q = grid_laplacian((11, 10, 9), shift=0.5)          # same pattern, other values
+    assert np.array_equal(p.rowind, q.rowind)
+    print("adjoint after refactorization n=%d" % p.n, flush=True)
+    B, Xbar = rhs(p.n, 1, 41), rhs(p.n, 1, 42)
+    s = Solver(p.n, p.colptr, p.rowind)
+    vp = torch.tensor(p.values, device="cuda", requires_grad=True)
+    vq = torch.tensor(q.values, device="cuda", requires_grad=True)
+    b = torch.tensor(np.ascontiguousarray(B[:, 0]), device="cuda")
+    xp = solve_autograd(s, vp, b)
+    xq = solve_autograd(s, vq, b)
+    xbar = torch.tensor(np.ascontiguousarray(Xbar[:, 0]), device="cuda")
+    (gq,) = torch.autograd.grad(xq, vq, grad_outputs=xbar)
+    (gp,) = torch.autograd.grad(xp, vp, grad_outputs=xbar)
+    for prob, x, g in ((p, xp, gp), (q, xq, gq)):
+        xo, _, go = _oracle_adjoint(orc, prob, B, Xbar)
+        assert np.max(np.abs(x.detach().cpu().numpy() - xo[:, 0])) <= 1e-10 * np.max(np.abs(xo))
+        assert np.max(np.abs(g.cpu().numpy() - go)) <= 1e-9 * np.max(np.abs(go))

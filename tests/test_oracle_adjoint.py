@@ -62,3 +62,22 @@ def test_adjoint_backward_solve_is_dense_solve(orc):
     db, _ = orc.adjoint(sym, P, p.colptr, p.rowind, p.values, x, xbar)
     ref = np.linalg.solve(A, xbar)
     assert np.max(np.abs(db - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_values_grad_entry_by_entry(orc):
+    # the C routine against the definition written out entry by entry
+    p = random_spd(40, 0.15, 13)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((p.n, 3))
+    db = rng.standard_normal((p.n, 3))
+    g = orc.values_grad(p.n, p.colptr, p.rowind, x, db)
+    col = np.repeat(np.arange(p.n), np.diff(p.colptr))
+    for q in range(p.nnz):
+        i, j = int(p.rowind[q]), int(col[q])
+        if i > j:
+            ref = -(db[i] @ x[j] + db[j] @ x[i])
+        elif i == j:
+            ref = -(db[i] @ x[i])
+        else:
+            ref = 0.0
+        assert abs(g[q] - ref) <= 1e-14 * max(1.0, abs(ref))
