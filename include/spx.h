@@ -55,11 +55,21 @@ enum spx_status {
 
 enum spx_method {
     SPX_LLT = 0,   /* P A P^T = L L^T, A symmetric positive definite */
-    SPX_LDLT = 1   /* P A P^T = L D L^T with unit L and diagonal D, A symmetric with
+    SPX_LDLT = 1,  /* P A P^T = L D L^T with unit L and diagonal D, A symmetric with
                     * non-zero pivots in the computed order (static pivoting,
                     * Section III: the structure is the one of L L^T); e.g.
                     * quasi-definite matrices.  SPX_FP64 only; fuse_small is
                     * ignored (treated as 0) */
+    SPX_LU = 2     /* P A P^T = L U with unit L, A unsymmetric with a symmetric or
+                    * unsymmetric pattern (analysed on the pattern of A + A^T) and
+                    * non-zero pivots in the computed order (static pivoting,
+                    * Section III: steps 2 and 3 duplicated for L and U).  Values
+                    * of both triangles are read.  All precision modes; fuse_small
+                    * is ignored (treated as 0); spx_values_grad is not available.
+                    * The factor is two panel arrays of the same layout: L (the
+                    * square diagonal blocks hold unit L strictly below the
+                    * diagonal and U on and above it), then U^T below the
+                    * diagonal blocks (row r of column c: u_{c, row r}) */
 };
 
 enum spx_precision {
@@ -116,7 +126,7 @@ typedef struct spx_info {
     int64_t ntasks;           /* device scheduler work items per factorization */
     int32_t fail_col;         /* after SPX_ENOTPD: failing column, original numbering */
     int32_t factorized;       /* 1 once a factorization succeeded */
-    double logdet;            /* log det A after a factorization (SPX_LDLT: log |det A|) */
+    double logdet;            /* log det A after a factorization (SPX_LDLT, SPX_LU: log |det A|) */
     double factor_kernel_ms;  /* last factorization: scheduler kernel time (HIP events) */
     double assemble_ms;       /* last factorization: assembly kernel time */
     int32_t tile_rows;        /* update tile in use: 256 x 64 or 128 x 128 */
@@ -126,7 +136,8 @@ typedef struct spx_info {
     int64_t nfused_tiles;     /* update tiles carried out inside fused items (not in ntasks) */
     int32_t nsmall;           /* column blocks handled as one fused item (fuse_small) */
     int32_t nneg;             /* SPX_LDLT: negative pivots (the inertia's negative count;
-                               * sign det A = (-1)^nneg); 0 for SPX_LLT */
+                               * sign det A = (-1)^nneg); SPX_LU: negative u_jj (sign det
+                               * A = (-1)^nneg); 0 for SPX_LLT */
 } spx_info;
 
 typedef struct spx_solve_info {
@@ -244,7 +255,8 @@ int spx_get_info(const spx_handle* h, spx_info* info);
 int spx_export_symbolic(const spx_handle* h, spx_symbolic_view* view);
 
 /* Copy the factor panels (panel_entries doubles, layout of the symbolic
- * view; the strict upper triangle of diagonal blocks is zero) to dst, a host
+ * view; the strict upper triangle of diagonal blocks is zero; SPX_LU:
+ * 2 * panel_entries doubles, the L panels then the U^T panels) to dst, a host
  * or device pointer.  An FP32 factor is widened to FP64.  Errors: SPX_ESTATE
  * before a factorization. */
 int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip_stream);

@@ -543,7 +543,7 @@ void analyze_pattern(int32_t n, const int64_t* colptr, const int32_t* rowind, co
     P.flops_exec = flops_exec;
     P.col_cblk = std::move(col_cblk);
 
-    build_device_maps(colptr, rowind, P);
+    build_device_maps(colptr, rowind, P, opt.lu);
 }
 
 // Position, inside cblk k's panel, of the row r of its structure (binary search over blocks).
@@ -558,12 +558,54 @@ int32_t panel_row(const Plan& P, int32_t k, int32_t r)
     return P.coefind[lo] + (r - P.frow[lo]);
 }
 
-void build_device_maps(const int64_t* colptr, const int32_t* rowind, Plan& P)
+void build_device_maps(const int64_t* colptr, const int32_t* rowind, Plan& P, bool lu)
 {
     const int32_t n = P.n;
     const int64_t nnz = colptr[n];
-    // assembly destinations of the lower-triangle entries
     P.amap.assign(static_cast<size_t>(nnz), -1);
+    if (lu) {
+        // L U: an entry (a, b) of P A P^T with a >= b goes to the L panel of
+        // column b (row a); with a < b to the square diagonal block of the
+        // L panel when b is a column of a's block, else to the U^T panel of
+        // column a (row b)
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
+                const int32_t a = P.iperm[rowind[p]], b = P.iperm[j];
+                if (a >= b) {
+                    const int32_t k = P.col_cblk[b];
+                    const int32_t pos = panel_row(P, k, a);
+                    if (pos < 0) throw std::runtime_error("entry outside the symbolic structure");
+                    P.amap[p] = P.panel_off[k] + static_cast<int64_t>(b - P.fcol[k]) * P.stride[k] + pos;
+                } else {
+                    const int32_t k = P.col_cblk[a];
+                    if (b <= P.lcol[k]) {
+                        P.amap[p] = P.panel_off[k] + static_cast<int64_t>(b - P.fcol[k]) * P.stride[k] + (a - P.fcol[k]);
+                    } else {
+                        const int32_t pos = panel_row(P, k, b);
+                        if (pos < 0) throw std::runtime_error("entry outside the symbolic structure");
+                        P.amap[p] = P.panel_entries + P.panel_off[k] +
+                                    static_cast<int64_t>(a - P.fcol[k]) * P.stride[k] + pos;
+                    }
+                }
+            }
+        // row lists of A itself for the residual: row i lists (column, value
+        // index) of every entry (i, j)
+        std::vector<int64_t> cnt(static_cast<size_t>(n) + 1, 0);
+        for (int64_t p = 0; p < nnz; ++p) ++cnt[rowind[p] + 1];
+        for (int32_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+        P.rptr = cnt;
+        P.rcol.assign(static_cast<size_t>(nnz), 0);
+        P.rval.assign(static_cast<size_t>(nnz), 0);
+        std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+        for (int32_t j = 0; j < n; ++j)
+            for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
+                const int32_t i = rowind[p];
+                P.rcol[pos[i]] = j;
+                P.rval[pos[i]++] = p;
+            }
+        return;
+    }
+    // assembly destinations of the lower-triangle entries
     for (int32_t j = 0; j < n; ++j)
         for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
             const int32_t i = rowind[p];
@@ -575,8 +617,8 @@ void build_device_maps(const int64_t* colptr, const int32_t* rowind, Plan& P)
             if (pos < 0) throw std::runtime_error("entry outside the symbolic structure");
             P.amap[p] = P.panel_off[k] + static_cast<int64_t>(c - P.fcol[k]) * P.stride[k] + pos;
         }
-    // symmetric row pattern for the residual: row i lists (column, value index) of
-    // every lower entry (i, j) and its mirror (j, i)
+    // symmetric row pattern for the residual: row i lists (column, value
+    // index) of every lower entry (i, j) and its mirror (j, i)
     std::vector<int64_t> cnt(static_cast<size_t>(n) + 1, 0);
     for (int32_t j = 0; j < n; ++j)
         for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {

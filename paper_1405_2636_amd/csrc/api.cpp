@@ -29,8 +29,8 @@ hipError_t launch_widen(double* dst, const float* src, int64_t n, hipStream_t s)
 hipError_t launch_gather_diag(double* dst, const void* panels, bool f32, const int64_t* off, int64_t n, hipStream_t s);
 hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, int32_t nready_hp,
                              const int32_t* fact_dep0, int32_t ncblk, hipStream_t s);
-int sched_blocks_per_cu(bool f32, bool ldlt);
-hipError_t launch_sched(const SchedArgs& a, bool f32, int grid, hipStream_t s);
+int sched_blocks_per_cu(bool f32, bool ldlt, bool lu);
+hipError_t launch_sched(const SchedArgs& a, bool f32, bool lu, int grid, hipStream_t s);
 hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s);
 hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
 hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
@@ -206,6 +206,9 @@ struct spx_handle {
 
     bool f32() const { return opt.precision != SPX_FP64; }   // FP32 panel storage
     bool ldlt() const { return opt.method == SPX_LDLT; }     // L D L^T (D on the panel diagonals)
+    bool lu() const { return opt.method == SPX_LU; }         // L U: L panels, then U^T panels (same layout)
+    int64_t panel_count() const { return plan.panel_entries * (lu() ? 2 : 1); }
+    int64_t dinv_count() const { return dinv_size * (lu() ? 2 : 1); }
     void* panel_ptr() { return f32() ? static_cast<void*>(panels_f.p) : static_cast<void*>(panels.p); }
     void* dinv_ptr() { return f32() ? static_cast<void*>(dinv_f.p) : static_cast<void*>(dinv.p); }
 
@@ -292,7 +295,7 @@ void build_tasks(spx_handle* h)
         for (int32_t r0 = rs; r0 < ld; r0 += tr) {
             const int32_t mr = std::min(tr, ld - r0);
             for (int32_t c0 = rs; c0 < re; c0 += tcl) {
-                if (r0 + mr - 1 < c0) continue;   // strictly above the diagonal of j
+                if (r0 + mr - 1 < c0 && !h->lu()) continue;   // strictly above the diagonal of j (L U: whole square)
                 fn(r0, mr, c0, std::min(tcl, re - c0));
             }
         }
@@ -579,7 +582,7 @@ void upload_plan(spx_handle* h)
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
     if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess || clk_khz <= 0)
         clk_khz = 100000;
-    h->grid = std::max(1, ncu * sched_blocks_per_cu(h->f32(), h->ldlt()));
+    h->grid = std::max(1, ncu * sched_blocks_per_cu(h->f32(), h->ldlt(), h->lu()));
     h->timeout_ticks = static_cast<int64_t>(clk_khz) * 1000 * 20;   // 20 s per wait
     HIPCHK(scratch_region(&h->scratch, &h->scratch_bytes));
 }
@@ -599,6 +602,12 @@ void sweeps(spx_handle* h, const SweepBufs& w, int32_t nrhs, hipStream_t s)
     a.pl = h->devplan();
     a.panels = h->panel_ptr();
     a.dinv = h->dinv_ptr();
+    {
+        const size_t esz = h->f32() ? sizeof(float) : sizeof(double);
+        const int64_t pu = h->lu() ? h->plan.panel_entries : 0, du = h->lu() ? h->dinv_size : 0;
+        a.panels_b = static_cast<const char*>(a.panels) + pu * esz;
+        a.dinv_b = static_cast<const char*>(a.dinv) + du * esz;
+    }
     a.f32 = h->f32() ? 1 : 0;
     a.ldlt = h->ldlt() ? 1 : 0;
     a.rowg = h->rowg.p;
@@ -639,12 +648,12 @@ void factor_part(spx_handle* h, int part, hipStream_t s)
     const bool f32 = h->f32();
     const SchedArgs a = sched_args(h);
     if (part == 1) {
-        if (h->total > 0) HIPCHK(launch_sched(a, f32, h->grid, s));
+        if (h->total > 0) HIPCHK(launch_sched(a, f32, h->lu(), h->grid, s));
         return;
     }
     const int64_t nsym = P.rptr.empty() ? 0 : P.rptr.back();
-    if (f32) HIPCHK(launch_fill_f32(h->panels_f.p, P.panel_entries, 0.0f, s));
-    else HIPCHK(launch_fill_f64(h->panels.p, P.panel_entries, 0.0, s));
+    if (f32) HIPCHK(launch_fill_f32(h->panels_f.p, h->panel_count(), 0.0f, s));
+    else HIPCHK(launch_fill_f64(h->panels.p, h->panel_count(), 0.0, s));
     HIPCHK(launch_assemble(h->panel_ptr(), f32, h->amap.p, h->vals.p, h->nnz, s));
     HIPCHK(launch_gather(h->rv.p, h->vals.p, h->rval.p, nsym, s));
     HIPCHK(launch_sched_init(a, h->ready.p, h->nready, h->nready_hp, h->fact_dep0.p, P.ncblk, s));
@@ -658,6 +667,8 @@ SchedArgs sched_args(spx_handle* h)
     a.dinv = h->dinv_ptr();
     a.split = h->opt.precision == SPX_BF16X3_IR ? 1 : 0;
     a.ldlt = h->ldlt() ? 1 : 0;
+    a.upanel = h->lu() ? h->plan.panel_entries : 0;
+    a.uinv = h->lu() ? h->dinv_size : 0;
     a.desc = h->desc.p;
     a.rmap = h->rmap.p;
     a.ftab = h->ftab.p;
@@ -722,7 +733,7 @@ void run_factorization(spx_handle* h, hipStream_t s)
     }
     if (st[0] != INT_MAX) {
         h->fail_col = (st[0] >= 0 && st[0] < h->n) ? P.perm[st[0]] : st[0];
-        throw StatusError(SPX_ENOTPD, std::string(h->ldlt() ? "zero or non-finite pivot" : "pivot not positive") +
+        throw StatusError(SPX_ENOTPD, std::string(h->opt.method != SPX_LLT ? "zero or non-finite pivot" : "pivot not positive") +
                                           " at column " + std::to_string(h->fail_col));
     }
 }
@@ -812,7 +823,9 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
     }
     if (opt) h->opt = *opt; else spx_default_options(&h->opt);
     int rc = guarded(h, [&]() -> int {
-        if (h->opt.method != SPX_LLT && h->opt.method != SPX_LDLT) throw InvalidArgument("unsupported method");
+        if (h->opt.method != SPX_LLT && h->opt.method != SPX_LDLT && h->opt.method != SPX_LU)
+            throw InvalidArgument("unsupported method");
+        if (h->opt.method == SPX_LU) h->opt.fuse_small = 0;   // every column block a FACT / TRSM / UPDATE sequence
         if (h->opt.method == SPX_LDLT) {
             // L D L^T: FP64 factor; every column block is a FACT / TRSM /
             // UPDATE sequence (no fused small items; merged updates apply
@@ -833,6 +846,7 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
         o.amalg_pct = h->opt.amalg_pct;
         o.split_width = h->opt.split_width;
         o.user_perm = h->opt.user_perm;
+        o.lu = h->opt.method == SPX_LU;
         analyze_pattern(n, colptr, rowind, o, h->plan);
         h->n = n;
         h->nnz = n > 0 ? colptr[n] : 0;
@@ -909,16 +923,16 @@ int spx_factorize(spx_handle* h, const double* values, int32_t values_on_device,
             HIPCHK(hipMemcpyAsync(h->vals.p, values, h->nnz * sizeof(double),
                                   values_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         const bool f32 = h->f32();
-        if (f32) h->panels_f.alloc(static_cast<size_t>(P.panel_entries));
-        else h->panels.alloc(static_cast<size_t>(P.panel_entries));
+        if (f32) h->panels_f.alloc(static_cast<size_t>(h->panel_count()));
+        else h->panels.alloc(static_cast<size_t>(h->panel_count()));
         if (!h->dinv_ptr()) {
             // blocks above the diagonal of each inverse are never written: zero them once
             if (f32) {
-                h->dinv_f.alloc(static_cast<size_t>(h->dinv_size));
-                HIPCHK(launch_fill_f32(h->dinv_f.p, h->dinv_size, 0.0f, s));
+                h->dinv_f.alloc(static_cast<size_t>(h->dinv_count()));
+                HIPCHK(launch_fill_f32(h->dinv_f.p, h->dinv_count(), 0.0f, s));
             } else {
-                h->dinv.alloc(static_cast<size_t>(h->dinv_size));
-                HIPCHK(launch_fill_f64(h->dinv.p, h->dinv_size, 0.0, s));
+                h->dinv.alloc(static_cast<size_t>(h->dinv_count()));
+                HIPCHK(launch_fill_f64(h->dinv.p, h->dinv_count(), 0.0, s));
             }
         }
         const int64_t nsym = P.rptr.empty() ? 0 : P.rptr.back();
@@ -1074,6 +1088,7 @@ int spx_values_grad(spx_handle* h, int32_t nrhs, const double* x, const double* 
     return guarded(h, [&]() -> int {
         if (!h->uploaded) throw StatusError(SPX_ESTATE, "no device plan (no factorization yet)");
         if (nrhs < 0 || (nrhs > 0 && ld < h->n)) throw InvalidArgument("bad vector shape");
+        if (h->lu()) throw InvalidArgument("the value gradient needs a symmetric method (SPX_LLT or SPX_LDLT)");
         if (h->nnz > 0 && !grad) throw InvalidArgument("grad is NULL");
         if (nrhs > 0 && h->n > 0 && (!x || !db)) throw InvalidArgument("x or db is NULL");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -1101,7 +1116,7 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
                 HIPCHK(hipMemcpy(diag.data(), dd.p, static_cast<size_t>(P.n) * sizeof(double), hipMemcpyDeviceToHost));
             }
             h->nneg = 0;
-            if (h->ldlt()) {
+            if (h->ldlt() || h->lu()) {
                 for (auto& d : diag) {
                     h->nneg += d < 0.0;
                     d = std::log(std::fabs(d));
@@ -1176,9 +1191,9 @@ int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip
     if (!h) return SPX_EINVAL;
     return guarded(h, [&]() -> int {
         if (!h->factorized) throw StatusError(SPX_ESTATE, "no factorization");
-        if (!dst && h->plan.panel_entries > 0) throw InvalidArgument("dst is NULL");
+        if (!dst && h->panel_count() > 0) throw InvalidArgument("dst is NULL");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        const int64_t ne = h->plan.panel_entries;
+        const int64_t ne = h->panel_count();
         if (ne > 0 && h->f32()) {
             if (dst_on_device) {
                 HIPCHK(launch_widen(dst, h->panels_f.p, ne, s));

@@ -39,6 +39,8 @@ struct SchedArgs {
     void* dinv;              // same element type as the panels
     int32_t split;           // FP32 panels: update and TRSM products as split-BF16 products
     int32_t ldlt;            // L D L^T (FP64): D on the panels' diagonals, inverse D^{-1} L^{-1}
+    int64_t upanel;          // L U: elements from the L panels to the U^T panels (same layout)
+    int64_t uinv;            // L U: elements from the inverses L_kk^{-1} to U_kk^{-T} (same layout)
     const int4* desc;
     const int32_t* rmap;     // panel row of k -> row inside panel j, per update pair
     const int4* ftab;        // update tiles of fused small blocks
@@ -68,6 +70,8 @@ struct SweepArgs {
     DevPlan pl;
     const void* panels;       // double, or float in the FP32 refinement mode
     const void* dinv;
+    const void* panels_b;     // backward sweep: L U's U^T panels and U_kk^{-T} (else the same as forward)
+    const void* dinv_b;
     int32_t f32;              // 1: panels and inverses are float
     int32_t ldlt;             // 1: L D L^T factor (D on the panel diagonals, inverses D^{-1} L^{-1})
     const int32_t* rowg;      // global row of every off-diagonal panel row

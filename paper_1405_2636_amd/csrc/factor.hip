@@ -761,20 +761,283 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
     }
 }
 
+// ---------------------------------------------------------------- FACT(k), L U
+// L U factorization without pivoting (the static pivoting of Section III:
+// the elimination order is the analysis' order) of one 32x32 diagonal tile
+// and the two inverses the panel solves use, in FP64, by one wave.  Lt
+// (column-major, ld 33) holds the whole tile; rows and columns >= jb hold
+// the identity.  Pass 1 keeps the tile twice: lane r < 32 holds row r, lane
+// 32 + q holds column q.  Step c: the pivot u_cc is broadcast by readlane;
+// the entries of column c below it become l_rc = a_rc / u_cc (in the row
+// lanes, and in column lane c); every lane puts one value in LDS (row lane r
+// its l_rc, column lane q its u_cq), so that row lane r > c updates
+// a_rq -= l_rc u_cq (q > c) with u_cq from LDS and column lane q > c updates
+// a_pq -= l_pc u_cq (p > c) with l_pc from LDS: the same operands in both
+// copies.  Pass 2, from L\U in Lt: lane q < 32 forms column q of
+// X = L^{-1} by forward substitution with the unit L (x_i -= l_ic x_c, i > c),
+// lane 32 + q column q of Y = U^{-T} by forward substitution with U^T
+// (y_c /= u_cc, then y_i -= u_ci y_c, i > c).  Out: L\U in Lt (unit L
+// strictly below the diagonal, U on and above), X in Dt (column-major, ld
+// 33), Y (rounded to T) in Yg[i + q*ldy] for q <= i < jb.  A zero or
+// non-finite pivot among the first jb records its column with atomicMin.
+template <class T>
+__device__ __noinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, int ldy, int jb, int col0,
+                                         int32_t* status)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 31;
+    const bool colh = lane >= 32;
+    double v[32], invp[32];   // invp: the inverse pivots (uniform), for pass 2
+#pragma unroll
+    for (int c = 0; c < 32; ++c) v[c] = colh ? Lt[c + r * 33] : Lt[r + c * 33];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+        const double d = readlane_d(v[c], c);   // row lane c: u_cc
+        double y = __builtin_amdgcn_rcp(d);
+        y = y * __builtin_fma(-d, y, 2.0);
+        y = y * __builtin_fma(-d, y, 2.0);
+        invp[c] = y;
+        if (!colh && r > c) v[c] *= y;   // l_rc
+        // row lanes: l_rc (meaningful for r > c); column lanes: u_cq
+        bc[lane] = v[c];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // column lane c takes its scaled entries l_pc (p > c) from the row
+        // lanes' values, the others update
+        const double own = (r > c) ? v[c] : 0.0;
+        const bool take = colh && r == c;
+        const int bo = colh ? 0 : 32;
+#pragma unroll
+        for (int q = c + 1; q < 32; ++q) {
+            const double b = bc[bo + q];
+            v[q] = take ? b : v[q] - own * b;
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // breakdown: a zero or non-finite pivot among the first jb
+    double dd = 0.0;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) dd = (r == c) ? v[c] : dd;
+    const bool bad = !colh && r < jb && !(dd != 0.0 && dd - dd == 0.0);
+    const uint64_t m = __ballot(bad);
+    if (lane == 0 && m) atomicMin(status, col0 + (int)__builtin_ctzll(m));
+    if (!colh) {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) Lt[r + c * 33] = v[c];
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // pass 2: X (lanes < 32) and Y (lanes >= 32), column r of each
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = i == r ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+        if (colh) v[c] *= invp[c];
+        const double xc = v[c];
+        // coefficient i: U(c, i) at c + 33 i for the Y lanes, L(i, c) at i + 33 c for the X lanes
+        const int base = colh ? c : 33 * c, step = colh ? 33 : 1;
+#pragma unroll
+        for (int i = c + 1; i < 32; ++i) v[i] -= Lt[base + i * step] * xc;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (!colh) {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) Dt[c + r * 33] = c >= r ? (T)v[c] : T(0);
+    } else if (r < jb) {
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+            if (c >= r && c < jb) Yg[c + (int64_t)r * ldy] = (T)v[c];
+    }
+}
+
+// L U factorization of the w x w diagonal block (w <= 256) of panel k, in
+// place in the L panel (unit L below the diagonal, U on and above), with the
+// inverses X = L_kk^{-1} (L inverse array) and Y = U_kk^{-T} (U inverse
+// array), both lower triangular, by one workgroup, right-looking over 32
+// columns at a time.  Step J (tile columns J .. J+jb):
+//   1. the tile, fully updated, is factored and inverted by wave 0
+//      (tile_lu_inv): L\U_JJ -> panel, X_JJ -> X, Y_JJ -> Y;
+//   2. rows below: P = A[J+jb:w, J:J+jb] Y_JJ^T (= L rows) -> panel and LDS;
+//      columns to the right, transposed: Q = A[J:J+jb, J+jb:w]^T X_JJ^T
+//      (= U^T rows) -> the panel's upper part (U_J,right); block rows J of
+//      the inverses: X_J[:, 0:J] = X_JJ X_J[:, 0:J], Y_J[:, 0:J] = Y_JJ Y_J[:, 0:J];
+//   3. trailing updates, 64x32 tiles dealt to the four waves:
+//      A[J+jb:, J+jb:] -= P Q^T (the whole square), X[J+jb:, 0:J+jb] -= P X_J
+//      and Y[J+jb:, 0:J+jb] -= Q Y_J (columns J .. J+jb written for the first
+//      time).  The wave taking tile 0 (which holds the next diagonal tile)
+//      writes it to LDS and factors it while the others go on.
+// P is read from LDS, Q and the inverses' block rows from global memory
+// (written by this workgroup earlier in the step).
+template <class T>
+__device__ __noinline__ void task_fact_lu(const SchedArgs& a, int k, double* Lt, T* Dt, T* Pb)
+{
+    typedef typename MM<T>::acc acc_t;
+    const DevPlan& pl = a.pl;
+    const int f = pl.fcol[k];
+    const int w = pl.lcol[k] - f + 1;
+    const int64_t ld = pl.stride[k];
+    T* A = static_cast<T*>(a.panels) + pl.panel_off[k];
+    T* X = static_cast<T*>(a.dinv) + pl.dinv_off[k];
+    T* Y = X + a.uinv;
+    const int64_t nA = ld * w, nD = (int64_t)w * w;
+    const GOp gA = make_gop(A, nA, 0, 1, ld);   // A(i, p) at i + p*ld
+    const GOp gX = make_gop(X, nD, 0, 1, w);
+    const GOp gY = make_gop(Y, nD, 0, 1, w);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    double* bc = Lt + kNB * 33;
+    __shared__ int s_next;
+    bool ready = false;
+    for (int J = 0; J < w; J += kNB) {
+        const int jb = min(kNB, w - J);
+        const int R = w - J - jb;
+        if (!ready) {
+            for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
+                const int r = idx & 31, c = idx >> 5;
+                Lt[r + c * 33] = (r < jb && c < jb) ? (double)A[(J + r) + (int64_t)(J + c) * ld] : (r == c ? 1.0 : 0.0);
+            }
+            __syncthreads();
+            if (wave == 0) tile_lu_inv<T>(Lt, bc, Dt, Y + J + (int64_t)J * w, w, jb, f + J, a.status);
+        }
+        if (tid == 0) s_next = 0;
+        __syncthreads();
+        for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
+            const int r = idx & 31, c = idx >> 5;
+            if (r < jb && c < jb) {
+                A[(J + r) + (int64_t)(J + c) * ld] = (T)Lt[r + c * 33];
+                if (c <= r) X[(J + r) + (int64_t)(J + c) * w] = Dt[r + c * 33];
+            }
+        }
+        __syncthreads();   // Y_JJ (global, from wave 0) and the tile are in place
+        const int r0 = 64 * wave;
+        if (r0 < R) {
+            // 2a. P = A_rows Y_JJ^T (R > 0 implies jb = 32)
+            {
+                acc_t acc[2][4];
+                zero_acc(acc);
+                const int gbase = gA.off + (J + jb + r0) * gA.si + J * gA.sk;
+                wave_mm<2, T>(acc, [&](int i, int p) { return gload<T>(gA, gbase + i * gA.si + p * gA.sk); },
+                              [&](int c, int p) { return gload<T>(gY, gY.off + (J + c) * gY.si + (J + p) * gY.sk); });
+                wave_store<T>(acc, min(64, R - r0), jb, [&](int r, int c, T v) {
+                    Pb[(r0 + r) + c * kPbLd] = v;
+                    A[(J + jb + r0 + r) + (int64_t)(J + c) * ld] = v;
+                });
+            }
+            // 2a'. Q = A[J:J+jb, right]^T X_JJ^T, stored as U_J,right
+            {
+                acc_t acc[2][4];
+                zero_acc(acc);
+                wave_mm<2, T>(acc,
+                              [&](int i, int p) { return gload<T>(gA, gA.off + (J + p) * gA.si + (J + jb + r0 + i) * gA.sk); },
+                              [&](int c, int p) { return Dt[c + p * 33]; });
+                // (the upper rows of the inverse tile are zero: products over
+                // p > c vanish)
+                wave_store<T>(acc, min(64, R - r0), jb,
+                              [&](int r, int c, T v) { A[(J + c) + (int64_t)(J + jb + r0 + r) * ld] = v; });
+            }
+        }
+        // 2b. block rows J of X and Y for columns < J, in place; each wave a
+        // 64-column slice of one of them
+        for (int t = wave; t < 2 * ((J + 63) >> 6); t += kThreads / 64) {
+            const bool isY = (t & 1) != 0;
+            const int c0 = 64 * (t >> 1);
+            const GOp& g = isY ? gY : gX;
+            T* Z = isY ? Y : X;
+            acc_t acc[2][4];
+            zero_acc(acc);
+            if (isY)
+                wave_mm<2, T>(acc, [&](int i, int p) { return gload<T>(g, g.off + (J + p) * g.si + (c0 + i) * g.sk); },
+                              [&](int c, int p) { return gload<T>(gY, gY.off + (J + c) * gY.si + (J + p) * gY.sk); });
+            else
+                wave_mm<2, T>(acc, [&](int i, int p) { return gload<T>(g, g.off + (J + p) * g.si + (c0 + i) * g.sk); },
+                              [&](int c, int p) { return Dt[c + p * 33]; });
+            wave_store<T>(acc, min(64, J - c0), jb, [&](int r, int c, T v) { Z[(J + c) + (int64_t)(c0 + r) * w] = v; });
+        }
+        __syncthreads();
+        if (R == 0) break;
+        // 3. trailing updates: A tiles (rt, ct) over the whole R x R square,
+        // then X tiles and Y tiles (rt, ct), ct*32 < J + jb
+        const int nrt = (R + 63) >> 6, ncs = (R + 31) >> 5, nci = (J + jb + 31) >> 5;
+        const int nsq = nrt * ncs, ninv = nrt * nci;
+        const int ntiles = nsq + 2 * ninv;
+        const int jn = min(kNB, R);
+        for (;;) {
+            int t = 0;
+            if (lane == 0) t = atomicAdd(&s_next, 1);
+            t = __shfl(t, 0);
+            if (t >= ntiles) break;
+            auto sub = [](T o, T v) { return o - v; };
+            if (t < nsq) {
+                const int rt = t / ncs, ct = t - rt * ncs;
+                const int i0 = 64 * rt, c0 = 32 * ct;
+                const int mv = min(64, R - i0), nv = min(32, R - c0);
+                auto ldx = [&](int i, int p) { return Pb[(i0 + i) + p * kPbLd]; };
+                auto ldq = [&](int c, int p) {
+                    return gload<T>(gA, gA.off + (J + p) * gA.si + (J + jb + c0 + c) * gA.sk);
+                };
+                GOp cA = gA;
+                cA.off = uni(gA.off + (J + jb + i0) * gA.si + (J + jb + c0) * gA.sk);
+                if (t == 0) {
+                    for (int idx = lane; idx < kNB * kNB; idx += 64) {
+                        const int r = idx & 31, c = idx >> 5;
+                        Lt[r + c * 33] = r == c && r >= jn ? 1.0 : 0.0;
+                    }
+                    wave_mm_rmw<2, T>(
+                        ldx, ldq, mv, nv, cA, [](int, int) { return true; }, sub, [&](int r, int c, T v) {
+                            if (r < jn && c < jn) Lt[r + c * 33] = (double)v;
+                        });
+                    tile_lu_inv<T>(Lt, bc, Dt, Y + (J + jb) + (int64_t)(J + jb) * w, w, jn, f + J + jb, a.status);
+                } else {
+                    wave_mm_rmw<2, T>(ldx, ldq, mv, nv, cA, [](int, int) { return true; }, sub, [](int, int, T) {});
+                }
+            } else {
+                const bool isY = t >= nsq + ninv;
+                const int u = t - nsq - (isY ? ninv : 0);
+                const int rt = u / nci, ct = u - rt * nci;
+                const int i0 = 64 * rt, c0 = 32 * ct;
+                const int mv = min(64, R - i0), nv = min(32, J + jb - c0);
+                const GOp& g = isY ? gY : gX;
+                T* Z = isY ? Y : X;
+                auto ldy = [&](int c, int p) { return gload<T>(g, g.off + (J + p) * g.si + (c0 + c) * g.sk); };
+                auto ldp = [&](int i, int p) { return Pb[(i0 + i) + p * kPbLd]; };
+                auto ldqr = [&](int i, int p) {
+                    return gload<T>(gA, gA.off + (J + p) * gA.si + (J + jb + i0 + i) * gA.sk);
+                };
+                if (c0 >= J) {   // columns written for the first time
+                    acc_t acc[2][4];
+                    zero_acc(acc);
+                    if (isY) wave_mm<2, T>(acc, ldqr, ldy);
+                    else wave_mm<2, T>(acc, ldp, ldy);
+                    wave_store<T>(acc, mv, nv,
+                                  [&](int r, int c, T v) { Z[(J + jb + i0 + r) + (int64_t)(c0 + c) * w] = -v; });
+                } else {
+                    GOp cZ = g;
+                    cZ.off = uni(g.off + (J + jb + i0) * g.si + c0 * g.sk);
+                    if (isY) wave_mm_rmw<2, T>(ldqr, ldy, mv, nv, cZ, [](int, int) { return true; }, sub, [](int, int, T) {});
+                    else wave_mm_rmw<2, T>(ldp, ldy, mv, nv, cZ, [](int, int) { return true; }, sub, [](int, int, T) {});
+                }
+            }
+        }
+        __syncthreads();
+        ready = true;
+    }
+}
+
 // ---------------------------------------------------------------- TRSM(k, rows)
 // Rows [row0, row0+nrows) (nrows <= 64 * (4 / ceil(w / 64))) of panel k below its diagonal block
 // are replaced by B L_kk^{-T} = B D^T.  Wave v computes the 64 output columns
 // starting at 64v; the inner range stops at the diagonal of the lower
-// triangular D.
+// triangular D.  poff / doff select the panel array and the inverse (L U:
+// the L rows take U_kk^{-T}, giving A_off U_kk^{-1}; the U^T rows take
+// L_kk^{-1}, giving A_up^T L_kk^{-T}).
 template <class T>
-__device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int nrows)
+__device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int nrows, int64_t poff = 0,
+                                       int64_t doff = 0)
 {
     const DevPlan& pl = a.pl;
     const int w = pl.lcol[k] - pl.fcol[k] + 1;
     const int64_t ld = pl.stride[k];
-    T* P = static_cast<T*>(a.panels) + pl.panel_off[k];
+    T* P = static_cast<T*>(a.panels) + poff + pl.panel_off[k];
     auto B = glob(P + row0);
-    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
+    const T* D = static_cast<const T*>(a.dinv) + doff + pl.dinv_off[k];
     const int wave = threadIdx.x >> 6;
     typename MM<T>::acc acc[4][4];
     zero_acc(acc);
@@ -807,7 +1070,11 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // pieces k-np+1 .. k of a split supernode (piece p's rows are k's rows
 // shifted by fcol[k] - fcol[p]) before its one scatter.  LDL (FP64):
 // each piece's product is L_p[rows] D_p L_p[cols]^T, D_p on the diagonal of panel p.
-template <class T, bool LDL = false>
+// LU: the tile covers the whole square of the facing rows (no triangle);
+// W_L = L_k[rows] U^T_k[cols]^T goes to j's L panel (its square diagonal
+// block included), and, for rows below j's diagonal block, W_U =
+// U^T_k[rows] L_k[cols]^T to j's U^T panel.
+template <class T, bool LDL = false, bool LU = false>
 __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos, int* cpos)
 {
     const DevPlan& pl = a.pl;
@@ -824,24 +1091,40 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
     const int c0 = square ? 64 * (wave >> 1) : 0;
     const int mv = min(64, mrows - r0), nv = min(64, ncols - c0);
     if (mv > 0 && nv > 0) {
-        typename MM<T>::acc acc[4][4];
-        zero_acc(acc);
         const int fk = pl.fcol[k];
-        for (int p = k - np + 1; p <= k; ++p) {
-            const int fp = pl.fcol[p], w = pl.lcol[p] - fp + 1, sh = fk - fp;
-            const int64_t ld = pl.stride[p];
-            const T* A = static_cast<const T*>(a.panels) + pl.panel_off[p];
-            if constexpr (LDL)
-                wave_gemm_d<4>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld),
-                               make_gop(A, ld * w, col0 + c0 + sh, 1, ld), make_gop(A, ld * w, 0, 0, ld + 1), w);
-            else
-                tile_gemm<4, T>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld),
-                                make_gop(A, ld * w, col0 + c0 + sh, 1, ld), w, a.split != 0);
+        // half 0: W = X Y^T with X the rows and Y the facing rows of the L
+        // panels (L U: Y from the U^T panels); half 1 (L U, rows below j's
+        // diagonal block only): X from the U^T panels, Y from the L panels
+        const int wj = pl.lcol[j] - pl.fcol[j] + 1;
+        const int nhalf = (LU && rpos[r0 + mv - 1] >= wj) ? 2 : 1;
+        for (int half = 0; half < nhalf; ++half) {
+            typename MM<T>::acc acc[4][4];
+            zero_acc(acc);
+            const int64_t xo = (LU && half == 1) ? a.upanel : 0, yo = (LU && half == 0) ? a.upanel : 0;
+            for (int p = k - np + 1; p <= k; ++p) {
+                const int fp = pl.fcol[p], w = pl.lcol[p] - fp + 1, sh = fk - fp;
+                const int64_t ld = pl.stride[p];
+                const T* A = static_cast<const T*>(a.panels) + pl.panel_off[p];
+                if constexpr (LDL)
+                    wave_gemm_d<4>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld),
+                                   make_gop(A, ld * w, col0 + c0 + sh, 1, ld), make_gop(A, ld * w, 0, 0, ld + 1), w);
+                else
+                    tile_gemm<4, T>(acc, make_gop(A + xo, ld * w, row0 + r0 + sh, 1, ld),
+                                    make_gop(A + yo, ld * w, col0 + c0 + sh, 1, ld), w, a.split != 0);
+            }
+            if constexpr (LU) {
+                auto Cu = Cg + (half == 1 ? a.upanel : 0);
+                wave_store<T>(acc, mv, nv, [&](int r, int c, T v) {
+                    const int tr = rpos[r0 + r], tc = cpos[c0 + c];
+                    if (half == 0 || tr >= wj) __hip_atomic_fetch_add(Cu + (int64_t)tc * ldj + tr, -v, __ATOMIC_RELAXED, AGENT);
+                });
+            } else {
+                wave_store<T>(acc, mv, nv, [&](int r, int c, T v) {
+                    const int tr = rpos[r0 + r], tc = cpos[c0 + c];
+                    if (tr >= tc) __hip_atomic_fetch_add(Cg + (int64_t)tc * ldj + tr, -v, __ATOMIC_RELAXED, AGENT);
+                });
+            }
         }
-        wave_store<T>(acc, mv, nv, [&](int r, int c, T v) {
-            const int tr = rpos[r0 + r], tc = cpos[c0 + c];
-            if (tr >= tc) __hip_atomic_fetch_add(Cg + (int64_t)tc * ldj + tr, -v, __ATOMIC_RELAXED, AGENT);
-        });
     }
 }
 
@@ -993,11 +1276,12 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
 }
 
 // ---------------------------------------------------------------- scheduler
-// LDL: the L D L^T factor (FP64; no fused small items).
-template <class T, bool LDL = false>
+// LDL: the L D L^T factor (FP64; no fused small items).  LU: the L U factor
+// (two panel arrays; no fused small items).
+template <class T, bool LDL = false, bool LU = false>
 __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 {
-    __shared__ double Lt[kNB * 33 + 2 * kNB];
+    __shared__ double Lt[kNB * 33 + 3 * kNB];
     __shared__ T Dt[kNB * 33];
     __shared__ __align__(16) T Pb[kPbLd * kNB + 32];   // + padding: tile row indices up to 255; small-block tables
     __shared__ int rpos[256], cpos[128];
@@ -1064,15 +1348,21 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         const int kind = d0.x & 0xff;   // (bits 8.. of an update: pieces merged - 1)
         if (kind == kFact) {
             __builtin_amdgcn_s_setprio(3);
-            task_fact<T, LDL>(a, d0.y, Lt, Dt, Pb);
+            if constexpr (LU) task_fact_lu<T>(a, d0.y, Lt, Dt, Pb);
+            else task_fact<T, LDL>(a, d0.y, Lt, Dt, Pb);
             __builtin_amdgcn_s_setprio(0);
         } else if (kind == kTrsm) {
             __builtin_amdgcn_s_setprio(2);
-            task_trsm<T>(a, d0.y, d0.z, d0.w);
+            if constexpr (LU) {
+                task_trsm<T>(a, d0.y, d0.z, d0.w, 0, a.uinv);
+                task_trsm<T>(a, d0.y, d0.z, d0.w, a.upanel, 0);
+            } else {
+                task_trsm<T>(a, d0.y, d0.z, d0.w);
+            }
             __builtin_amdgcn_s_setprio(0);
         } else if (kind == kUpdate) {
-            task_update<T, LDL>(a, d0, d1, rpos, cpos);
-        } else if constexpr (!LDL) {
+            task_update<T, LDL, LU>(a, d0, d1, rpos, cpos);
+        } else if constexpr (!LDL && !LU) {
             task_small<T>(a, d0, d1, Lt, Dt, Pb);
         }
         // every wave's stores and atomics have completed before the barrier
@@ -1252,20 +1542,28 @@ hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t n
     return hipGetLastError();
 }
 
-int sched_blocks_per_cu(bool f32, bool ldlt)
+int sched_blocks_per_cu(bool f32, bool ldlt, bool lu)
 {
     int nb = 0;
-    const hipError_t e =
-        f32    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<float>, kThreads, 0)
-        : ldlt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double, true>, kThreads, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double>, kThreads, 0);
+    hipError_t e;
+    if (lu)
+        e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<float, false, true>, kThreads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double, false, true>, kThreads, 0);
+    else if (f32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<float>, kThreads, 0);
+    else if (ldlt)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double, true>, kThreads, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double>, kThreads, 0);
     if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_sched(const SchedArgs& a, bool f32, int grid, hipStream_t s)
+hipError_t launch_sched(const SchedArgs& a, bool f32, bool lu, int grid, hipStream_t s)
 {
-    if (f32) sched_kernel<float><<<grid, kThreads, 0, s>>>(a);
+    if (lu && f32) sched_kernel<float, false, true><<<grid, kThreads, 0, s>>>(a);
+    else if (lu) sched_kernel<double, false, true><<<grid, kThreads, 0, s>>>(a);
+    else if (f32) sched_kernel<float><<<grid, kThreads, 0, s>>>(a);
     else if (a.ldlt) sched_kernel<double, true><<<grid, kThreads, 0, s>>>(a);
     else sched_kernel<double><<<grid, kThreads, 0, s>>>(a);
     return hipGetLastError();

@@ -20,6 +20,7 @@ struct Options {
     int32_t amalg_pct = 12;
     int32_t split_width = 256;
     const int32_t* user_perm = nullptr;
+    bool lu = false;   // L U: device maps for both triangles (assembly into the L and U^T panels)
 };
 
 struct Plan {
@@ -32,13 +33,14 @@ struct Plan {
     std::vector<int32_t> frow, lrow, fcblk, coefind;
     // device maps
     std::vector<int64_t> amap;            // input entry -> panel offset, -1 if not read
+                                          // (L U: offsets >= panel_entries are in the U^T panels)
     std::vector<int64_t> rptr;            // symmetric residual pattern (row pointers)
     std::vector<int32_t> rcol;            //   column of each entry
     std::vector<int64_t> rval;            //   index of its value in the input array
 };
 
 void analyze_pattern(int32_t n, const int64_t* colptr, const int32_t* rowind, const Options& opt, Plan& P);
-void build_device_maps(const int64_t* colptr, const int32_t* rowind, Plan& P);
+void build_device_maps(const int64_t* colptr, const int32_t* rowind, Plan& P, bool lu);
 int32_t panel_row(const Plan& P, int32_t k, int32_t r);
 
 }  // namespace spx

@@ -20,6 +20,11 @@
 // HBM bandwidth and, on the narrow top levels, by load latency.
 // The factor is read in its storage type T (double, or float in the FP32
 // refinement mode); vectors and arithmetic are FP64 in both cases.
+// L U (unit L and U in the square diagonal blocks, L below them, U^T in a
+// second panel array of the same layout, kept inverses L_kk^{-1} and
+// U_kk^{-T}): the forward sweep reads L and L_kk^{-1}, the backward sweep the
+// U^T panels and U_kk^{-T} (x_k = U_kk^{-1} (z_k - t_k), t_k = U_k,off x[rows])
+// in the places of L and L_kk^{-1}.
 // L D L^T (unit L, d_j on the panel diagonal, kept inverse Y = D^{-1} L^{-1}):
 // the same steps give w_k = Y_kk y_k = D_k^{-1} z_k in z, so the forward rows
 // below take D_k w_k, and the backward step x_k = L_kk^{-T} (w_k - t_k) is
@@ -138,7 +143,7 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
     const int nr = min(kChunk, (int)ld - row0);
     const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
     const int tid = threadIdx.x, q = tid & 3;
-    const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0;
+    const T* L = static_cast<const T*>(a.panels_b) + pl.panel_off[k] + row0;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
         const double* x = a.x + (int64_t)rhs * a.n;
         if (tid < nr) xr[tid] = x[g[tid]];
@@ -172,7 +177,7 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblk
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
     const int c0 = ROWS * (blockIdx.x % parts);
     if (c0 >= w) return;
-    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
+    const T* D = static_cast<const T*>(a.dinv_b) + pl.dinv_off[k];
     const int tid = threadIdx.x, q = tid % LANES, col = min(c0 + tid / LANES, w - 1);
     const T* Dc = D + (int64_t)col * w;
     const T* Pd = static_cast<const T*>(a.panels) + pl.panel_off[k];   // d_c at c * (ld + 1) (L D L^T)
@@ -289,8 +294,8 @@ __global__ void __launch_bounds__(256) bwd_small(SweepArgs a, const int32_t* cbl
     const int f = pl.fcol[k];
     const int w = on ? pl.lcol[k] - f + 1 : 0;
     const int ld = on ? pl.stride[k] : 0;
-    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
-    const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k];
+    const T* D = static_cast<const T*>(a.dinv_b) + pl.dinv_off[k];
+    const T* L = static_cast<const T*>(a.panels_b) + pl.panel_off[k];
     const int32_t* rg = a.rowg + a.rowg_off[k] - w;
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
         const int64_t vo = (int64_t)rhs * a.n;

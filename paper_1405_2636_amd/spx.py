@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libspx.so")
 
 SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ESTATE, SPX_ENOTPD, SPX_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 PRECISIONS = {"fp64": 0, "fp32_ir": 1, "bf16x3_ir": 2}   # enum spx_precision
-METHODS = {"llt": 0, "ldlt": 1}                          # enum spx_method
+METHODS = {"llt": 0, "ldlt": 1, "lu": 2}                 # enum spx_method
 
 
 class SpxError(RuntimeError):
@@ -143,7 +143,9 @@ class Solver:
     (P A P^T = L L^T, A positive definite) or "ldlt" (L D L^T with static
     pivoting, A symmetric with non-zero pivots, e.g. quasi-definite; fp64
     only; info()["logdet"] is then log |det A| and info()["nneg"] the number
-    of negative pivots).
+    of negative pivots), or "lu" (P A P^T = L U with static pivoting, A
+    unsymmetric, values of both triangles read; all precisions; the factor
+    is the L panels followed by the U^T panels; no value gradient).
     """
 
     def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,
@@ -346,7 +348,7 @@ class Solver:
     def factor_values(self, out=None, stream=None):
         """The factor panels (panel_entries doubles) as a torch CUDA tensor."""
         import torch
-        cnt = self.info()["panel_entries"]
+        cnt = self.info()["panel_entries"] * (2 if self.method == "lu" else 1)
         if out is None:
             out = torch.empty(max(cnt, 1), dtype=torch.float64, device="cuda")
         rc = self._lib.spx_copy_factor(self._h, C.c_void_p(out.data_ptr()), 1, _stream_ptr(stream))

@@ -70,14 +70,17 @@ def test_bad_options():
     for prec in ["fp32_ir", "bf16x3_ir"]:
         with pytest.raises(SpxError):
             Solver(p.n, p.colptr, p.rowind, method="ldlt", precision=prec)
+    # L U: every precision mode
+    for prec in ["fp64", "fp32_ir", "bf16x3_ir"]:
+        Solver(p.n, p.colptr, p.rowind, method="lu", precision=prec)
     with pytest.raises(ValueError):
-        Solver(p.n, p.colptr, p.rowind, method="lu")
+        Solver(p.n, p.colptr, p.rowind, method="qr")
     from paper_1405_2636_amd import spx
     L = spx.load_library()
     opt = spx.Options()
     L.spx_default_options(C.byref(opt))
     assert opt.method == 0
-    opt.method = 2
+    opt.method = 3
     h = C.c_void_p()
     assert L.spx_analyze(p.n, p.colptr.ctypes.data, p.rowind.ctypes.data, C.byref(opt), C.byref(h)) == -1
 
