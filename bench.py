@@ -14,7 +14,9 @@ value = algorithmic factorization flops (sum of squared exact column counts)
 
 Order of the run: the FP64 headline leg, then the oracle's CPU baseline,
 then the other legs (FP32 + refinement, split-BF16 + refinement, L D L^T,
-the 512-system batch) while the wall-clock budget (--budget-s, counted from
+the 512-system batch, then L U with static pivoting on the 80^3
+convection-diffusion stencil with 4 right-hand sides in the three precision
+modes) while the wall-clock budget (--budget-s, counted from
 the start of the process) leaves room for them; a leg that does not fit is
 listed under "skipped".  Progress lines with the elapsed time go to stderr;
 the one JSON line goes to stdout at the end.
@@ -307,7 +309,9 @@ def main():
     def speedup(r):
         return (r64["factor_ms"] + r64["solve_ms"]) / (r["factor_ms"] + r["solve_ms"])
 
-    legs = [] if args.headline_only else ["fp32_ir", "bf16x3_ir", "ldlt_fp64"] + ([] if args.no_batch else ["batch"])
+    legs = [] if args.headline_only else (["fp32_ir", "bf16x3_ir", "ldlt_fp64"] + ([] if args.no_batch else ["batch"])
+                                          + ["lu_fp64", "lu_fp32_ir", "lu_bf16x3_ir"])
+    c3 = {}
     for leg in legs:
         est = 1.3 * leg_s if leg != "batch" else 90.0
         if not fits(est):
@@ -328,6 +332,26 @@ def main():
                         "kernel_frac_of_fp64_peak": flops / (r["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
         elif leg == "batch":
             out["batch"] = run_batch(torch, np, Solver, args.steps)
+        elif leg.startswith("lu_"):
+            # L U with static pivoting on the 80^3 convection-diffusion stencil, 4 RHS
+            if not c3:
+                q = make_config(3)
+                c3.update(p=q, vals=torch.tensor(q.values, device="cuda"),
+                          b0=torch.tensor(np.ascontiguousarray(q.b.T), device="cuda"))
+                out["convdiff80_lu"] = {"workload": q.name, "n": q.n, "nnz_a": int(q.nnz), "nrhs": 4}
+            prec = leg[3:]
+            r = run_leg(torch, np, Solver, c3["p"], c3["vals"], c3["b0"], prec, args.steps, args.warmup, method="lu",
+                        adjoint=False)
+            d = out["convdiff80_lu"]
+            d["flops_alg"] = r["flops"]
+            d[prec] = {"factor_ms": r["factor_ms"], "solve_ms": r["solve_ms"],
+                       "factor_gflops": r["flops"] / (r["factor_ms"] * 1e-3) / 1e9, "omega": r["omega"],
+                       "ir_iters": r["ir_iters"], "kernel_ms": r["kernel_ms"]}
+            if prec == "fp64":
+                d[prec]["kernel_frac_of_fp64_peak"] = r["flops"] / (r["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS
+            elif "fp64" in d:
+                d[prec]["speedup_vs_fp64"] = ((d["fp64"]["factor_ms"] + d["fp64"]["solve_ms"])
+                                              / (r["factor_ms"] + r["solve_ms"]))
     log("done")
     print(json.dumps(out), flush=True)
 

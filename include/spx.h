@@ -121,7 +121,8 @@ typedef struct spx_info {
     int64_t nnz_l;            /* exact nonzeros of L (column counts summed) */
     int64_t nnz_l_stored;     /* nonzeros of the block structure (after amalgamation) */
     int64_t panel_entries;    /* size of the panel storage (diagonal blocks stored square) */
-    double flops_alg;         /* sum of squared exact column counts */
+    double flops_alg;         /* sum of squared exact column counts eta_j (SPX_LU: sum of
+                               * 2 (eta_j - 1)^2 + (eta_j - 1)) */
     double flops_exec;        /* the same on the amalgamated structure */
     int64_t ntasks;           /* device scheduler work items per factorization */
     int32_t fail_col;         /* after SPX_ENOTPD: failing column, original numbering */

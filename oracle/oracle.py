@@ -219,6 +219,7 @@ def analyze(n, colptr, rowind, leaf=64, amalg_pct=12, split_width=256, user_perm
         "zeros_used": L.orc_sym_i64(h, 2), "budget": L.orc_sym_i64(h, 3),
         "panel_size": L.orc_sym_i64(h, 4),
         "flops_alg": L.orc_sym_dbl(h, 0), "flops_exec": L.orc_sym_dbl(h, 1),
+        "flops_alg_lu": L.orc_sym_dbl(h, 2), "flops_exec_lu": L.orc_sym_dbl(h, 3),
     })
     return Symbolic(h.value, n, arrays, stats)
 

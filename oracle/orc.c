@@ -382,6 +382,7 @@ typedef struct {
     i64 nupd;
     i64 nnz_exact, nnz_amalg, zeros_used, budget, panel_size;
     double flops_alg, flops_exec;
+    double flops_alg_lu, flops_exec_lu;   /* L U count (Section IV's flop totals; our formula) */
     i64* colcount; /* exact column counts (diagonal included), final numbering */
 } orc_sym;
 
@@ -470,7 +471,12 @@ int orc_analyze(i32 n, const i64* colptr, const i32* rowind, i32 leaf, i32 amalg
     s->nsn_fund = nf;
     i64 nnz_exact = 0;
     double flops_alg = 0.0;
-    for (i32 j = 0; j < n; j++) { nnz_exact += eta[j]; flops_alg += (double)eta[j] * (double)eta[j]; }
+    double flops_alg_lu = 0.0;
+    for (i32 j = 0; j < n; j++) {
+        nnz_exact += eta[j];
+        flops_alg += (double)eta[j] * (double)eta[j];
+        flops_alg_lu += 2.0 * (double)(eta[j] - 1) * (double)(eta[j] - 1) + (double)(eta[j] - 1);
+    }
 
     /* R_s for fundamental supernodes: supernodal merge over children (O3 labels). */
     i32* fw = (i32*)malloc(sizeof(i32) * ((size_t)nf + 1));
@@ -574,6 +580,7 @@ int orc_analyze(i32 n, const i64* colptr, const i32* rowind, i32 leaf, i32 amalg
     s->nnz_exact = nnz_exact;
     s->nnz_amalg = nnz_exact + used;
     s->flops_alg = flops_alg;
+    s->flops_alg_lu = flops_alg_lu;
 
     /* O6: postorder of the amalgamated tree (ids = surviving fundamental index). */
     i32* apar = (i32*)malloc(sizeof(i32) * ((size_t)nf + 1));
@@ -625,7 +632,7 @@ int orc_analyze(i32 n, const i64* colptr, const i32* rowind, i32 leaf, i32 amalg
     s->lcol = (i32*)malloc(sizeof(i32) * ((size_t)ncblk + 1));
     i32* csn = (i32*)malloc(sizeof(i32) * ((size_t)ncblk + 1));
     i32 kk = 0;
-    double flops_exec = 0.0;
+    double flops_exec = 0.0, flops_exec_lu = 0.0;
     for (i32 t = 0; t < nsn; t++) {
         i32 f0 = s->snptr[t], wd = s->snptr[t + 1] - f0;
         i32 np = (wd + split_width - 1) / split_width;
@@ -636,9 +643,14 @@ int orc_analyze(i32 n, const i64* colptr, const i32* rowind, i32 leaf, i32 amalg
             c0 += ww;
         }
         i32 rl = rlen[snR[t]];
-        for (i32 i = 0; i < wd; i++) { double e2 = (double)(wd - i + rl); flops_exec += e2 * e2; }
+        for (i32 i = 0; i < wd; i++) {
+            double e2 = (double)(wd - i + rl);
+            flops_exec += e2 * e2;
+            flops_exec_lu += 2.0 * (e2 - 1.0) * (e2 - 1.0) + (e2 - 1.0);
+        }
     }
     s->flops_exec = flops_exec;
+    s->flops_exec_lu = flops_exec_lu;
     i32* col2cblk = (i32*)malloc(sizeof(i32) * ((size_t)n + 1));
     for (i32 k = 0; k < ncblk; k++) for (i32 j = s->fcol[k]; j <= s->lcol[k]; j++) col2cblk[j] = k;
 
@@ -750,7 +762,10 @@ i64 orc_sym_i64(const orc_sym* s, int what)
     }
 }
 
-double orc_sym_dbl(const orc_sym* s, int what) { return what == 0 ? s->flops_alg : s->flops_exec; }
+double orc_sym_dbl(const orc_sym* s, int what)
+{
+    return what == 0 ? s->flops_alg : what == 1 ? s->flops_exec : what == 2 ? s->flops_alg_lu : s->flops_exec_lu;
+}
 
 /* Copy one exported array out; names are numbered (see the Python driver). */
 int orc_sym_copy(const orc_sym* s, int what, void* dst)

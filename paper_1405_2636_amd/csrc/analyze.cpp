@@ -344,10 +344,12 @@ void analyze_pattern(int32_t n, const int64_t* colptr, const int32_t* rowind, co
         }
     }
     int64_t nnz_exact = 0;
-    double flops_alg = 0.0;
+    double flops_alg = 0.0, flops_alg_lu = 0.0;
     for (int32_t j = 0; j < n; ++j) {
         nnz_exact += colcount[j];
-        flops_alg += static_cast<double>(colcount[j]) * static_cast<double>(colcount[j]);
+        const double e = static_cast<double>(colcount[j]);
+        flops_alg += e * e;
+        flops_alg_lu += 2.0 * (e - 1.0) * (e - 1.0) + (e - 1.0);
     }
 
     // ---- fundamental supernodes
@@ -443,7 +445,7 @@ void analyze_pattern(int32_t n, const int64_t* colptr, const int32_t* rowind, co
     std::vector<int32_t> top_of(static_cast<size_t>(nsn));  // fundamental supernode owning R
     std::vector<int32_t> cols;
     int32_t next = 0;
-    double flops_exec = 0.0;
+    double flops_exec = 0.0, flops_exec_lu = 0.0;
     for (int32_t t = 0; t < nsn; ++t) {
         const int32_t s = alive[apost[t]];
         top_of[t] = s;
@@ -454,7 +456,11 @@ void analyze_pattern(int32_t n, const int64_t* colptr, const int32_t* rowind, co
         std::sort(cols.begin(), cols.end());
         for (int32_t j : cols) { relabel[j] = next; P.perm[next] = q[j]; ++next; }
         const int64_t w = static_cast<int64_t>(cols.size()), r = rcnt[s];
-        for (int64_t i = 0; i < w; ++i) flops_exec += static_cast<double>((w - i + r) * (w - i + r));
+        for (int64_t i = 0; i < w; ++i) {
+            const double e = static_cast<double>(w - i + r);
+            flops_exec += e * e;
+            flops_exec_lu += 2.0 * (e - 1.0) * (e - 1.0) + (e - 1.0);
+        }
     }
     P.snptr[nsn] = next;
     for (int32_t k = 0; k < n; ++k) P.iperm[P.perm[k]] = k;
@@ -541,6 +547,8 @@ void analyze_pattern(int32_t n, const int64_t* colptr, const int32_t* rowind, co
     P.panel_entries = off;
     P.flops_alg = flops_alg;
     P.flops_exec = flops_exec;
+    P.flops_alg_lu = flops_alg_lu;
+    P.flops_exec_lu = flops_exec_lu;
     P.col_cblk = std::move(col_cblk);
 
     build_device_maps(colptr, rowind, P, opt.lu);

@@ -1137,8 +1137,8 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
         o.nnz_l = P.nnz_exact;
         o.nnz_l_stored = P.nnz_stored;
         o.panel_entries = P.panel_entries;
-        o.flops_alg = P.flops_alg;
-        o.flops_exec = P.flops_exec;
+        o.flops_alg = h->lu() ? P.flops_alg_lu : P.flops_alg;
+        o.flops_exec = h->lu() ? P.flops_exec_lu : P.flops_exec;
         o.ntasks = h->total;
         o.nfused_tiles = h->nfused_tiles;
         o.nsmall = h->nsmall;

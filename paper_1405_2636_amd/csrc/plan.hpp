@@ -26,7 +26,8 @@ struct Options {
 struct Plan {
     int32_t n = 0, ncblk = 0, nblok = 0, nsnode = 0, nsn_fund = 0;
     int64_t nnz_a = 0, nnz_exact = 0, nnz_stored = 0, zeros_used = 0, panel_entries = 0;
-    double flops_alg = 0.0, flops_exec = 0.0;
+    double flops_alg = 0.0, flops_exec = 0.0;         // L L^T and L D L^T: sum of squared column counts
+    double flops_alg_lu = 0.0, flops_exec_lu = 0.0;   // L U: sum of 2 (eta - 1)^2 + (eta - 1)
     std::vector<int32_t> perm, iperm, etree, snptr;
     std::vector<int32_t> fcol, lcol, stride, bptr, cparent, uptr, utgt, dep, col_cblk;
     std::vector<int64_t> panel_off;

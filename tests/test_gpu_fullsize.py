@@ -16,6 +16,10 @@ factorization would take many minutes: properties that hold at any size.
 * the 512-system batch (2-D weighted grids, sides 16..96), FP64 and
   FP32 + refinement, graph-replayed and tuned: every system's x against the
   oracle's refined solution.
+* 80^3 convection-diffusion (N = 512,000), L U with static pivoting and 4
+  right-hand sides, the three precision modes: omega <= 1e-14, the probe
+  residual of L U (1e-12 in FP64; FP32 gates as above), no negative pivot
+  (an M-matrix), solutions agreeing across modes.
 * 40^3 clamped elasticity (N = 192,000, 27-point 3-dof), L D L^T with 8
   right-hand sides: omega <= 1e-14, probe residual of L D L^T <= 1e-12,
   log |det| and inertia equal to those of the L L^T factorization of the same
@@ -49,11 +53,14 @@ def _panel_rows(sv):
     return rows, off
 
 
-def _probe_residual(torch, s, p, ldlt=False, nprobe=8, seed=5):
+def _probe_residual(torch, s, p, ldlt=False, nprobe=8, seed=5, lu=False):
     """Rademacher estimate of ||P A P^T - L L^T||_F / ||A||_F (L D L^T with
-    ldlt); the factor products on the GPU (torch), A v on the host."""
+    ldlt, L U with lu); the factor products on the GPU (torch), A v on the
+    host."""
     sv = s.symbolic()
     F = s.factor_values()
+    if lu:
+        return _probe_residual_lu(torch, sv, F, p, nprobe, seed)
     rows, roff = _panel_rows(sv)
     rows_d = torch.tensor(rows, device="cuda")
     n = p.n
@@ -80,6 +87,39 @@ def _probe_residual(torch, s, p, ldlt=False, nprobe=8, seed=5):
     for f, w, Pk, d, r in blocks:                      # Y = L T
         Y.index_add_(0, r, Pk @ T[f:f + w])
     A = sp.csr_matrix((p.values, p.rowind, p.colptr), shape=(n, n)).T.tocsr()   # CSC arrays -> A
+    perm = sv["perm"]
+    U = np.empty_like(V)
+    U[perm] = V
+    R = (A @ U)[perm]
+    num = float(((torch.tensor(R, device="cuda") - Y) ** 2).sum())
+    return np.sqrt(num / float((R ** 2).sum()))
+
+
+def _probe_residual_lu(torch, sv, F, p, nprobe, seed):
+    rows, roff = _panel_rows(sv)
+    rows_d = torch.tensor(rows, device="cuda")
+    n = p.n
+    pe = int(sv["panel_off"][-1])
+    rng = np.random.default_rng(seed)
+    V = rng.integers(0, 2, (n, nprobe)).astype(np.float64) * 2.0 - 1.0
+    Vd = torch.tensor(V, device="cuda")
+    T = torch.zeros_like(Vd)
+    Y = torch.zeros_like(Vd)
+    blocks = []
+    for k in range(sv["ncblk"]):
+        f, w, ld, off = int(sv["fcol"][k]), int(sv["lcol"][k] - sv["fcol"][k] + 1), int(sv["stride"][k]), \
+            int(sv["panel_off"][k])
+        Pk = F[off:off + ld * w].view(w, ld).t()              # L panel (ld, w)
+        Uk = F[pe + off:pe + off + ld * w].view(w, ld).t()    # U^T panel (ld, w)
+        sq = Pk[:w, :w]
+        blocks.append((f, w, torch.tril(sq, -1) + torch.eye(w, dtype=sq.dtype, device="cuda"), torch.triu(sq),
+                       Pk[w:], Uk[w:], rows_d[roff[k] + w:roff[k + 1]]))
+    for f, w, Lsq, Usq, Lo, Uo, r in blocks:             # T = U V
+        T[f:f + w] = Usq @ Vd[f:f + w] + Uo.t() @ Vd[r]
+    for f, w, Lsq, Usq, Lo, Uo, r in blocks:             # Y = L T
+        Y[f:f + w] += Lsq @ T[f:f + w]
+        Y.index_add_(0, r, Lo @ T[f:f + w])
+    A = sp.csr_matrix((p.values, p.rowind, p.colptr), shape=(n, n)).T.tocsr()
     perm = sv["perm"]
     U = np.empty_like(V)
     U[perm] = V
@@ -220,3 +260,47 @@ def test_elasticity40_ldlt_adjoint_finite_differences(torch, c5):
     fd = (L(v0 + h * dv) - L(v0 - h * dv)) / (2 * h)
     print("elasticity adjoint: analytic %.10e fd %.10e" % (analytic, fd), flush=True)
     assert abs(fd - analytic) <= 1e-5 * max(1.0, abs(fd))
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return make_config(3)
+
+
+@pytest.fixture(scope="module")
+def c3_x64(torch, c3):
+    from paper_1405_2636_amd import Solver
+    s = Solver(c3.n, c3.colptr, c3.rowind, method="lu")
+    s.factorize(torch.tensor(c3.values, device="cuda"))
+    x, info = s.solve(torch.tensor(np.ascontiguousarray(c3.b.T), device="cuda"))
+    return s, x.cpu().numpy(), info
+
+
+def test_convdiff80_lu_fp64(torch, c3, c3_x64):
+    s, x, info = c3_x64
+    assert c3.n == 512000 and c3.nnz == 3545600 and c3.b.shape == (c3.n, 4)
+    print("80^3 lu fp64: omega %.2e ir %d" % (info["omega"], info["ir_iters"]), flush=True)
+    assert info["omega"] <= 1e-14 and info["converged"]
+    res = _probe_residual(torch, s, c3, lu=True)
+    print("80^3 lu fp64 probe residual %.3e" % res, flush=True)
+    assert res <= 1e-12
+    # the matrix is an irreducibly diagonally dominant M-matrix: every pivot
+    # of L U without pivoting is positive
+    assert s.info()["nneg"] == 0
+
+
+@pytest.mark.parametrize("prec,gate", [("fp32_ir", 1e-6), ("bf16x3_ir", 1e-5)])
+def test_convdiff80_lu_refinement_modes(torch, c3, c3_x64, prec, gate):
+    from paper_1405_2636_amd import Solver
+    s64, x64, _ = c3_x64
+    s = Solver(c3.n, c3.colptr, c3.rowind, method="lu", precision=prec)
+    s.factorize(torch.tensor(c3.values, device="cuda"))
+    x, info = s.solve(torch.tensor(np.ascontiguousarray(c3.b.T), device="cuda"))
+    res = _probe_residual(torch, s, c3, lu=True)
+    ld, ld64 = s.info()["logdet"], s64.info()["logdet"]
+    print("80^3 lu %s: omega %.2e ir %d probe residual %.3e logdet rel diff to fp64 %.2e"
+          % (prec, info["omega"], info["ir_iters"], res, abs(ld - ld64) / abs(ld64)), flush=True)
+    assert info["omega"] <= 1e-14 and info["converged"]
+    assert res <= gate
+    # both refined to omega <= 1e-14; kappa of the stencil ~ 3e3
+    assert np.max(np.abs(x.cpu().numpy() - x64)) <= 3e3 * 1e-14 * 10 * np.max(np.abs(x64))

@@ -185,6 +185,10 @@ def test_flop_convention_dense(orc):
         s = orc.analyze(n, cp, ri)
         assert s.stats["flops_alg"] == n * (n + 1) * (2 * n + 1) // 6
         assert s.stats["flops_exec"] == s.stats["flops_alg"]
+        # L U: sum over e = 1..n of 2 (e - 1)^2 + (e - 1) = (n - 1) n (2n - 1) / 3 + n (n - 1) / 2,
+        # about 2 n^3 / 3
+        assert s.stats["flops_alg_lu"] == (n - 1) * n * (2 * n - 1) // 3 + n * (n - 1) // 2
+        assert s.stats["flops_exec_lu"] == s.stats["flops_alg_lu"]
 
 
 def test_nd_reduces_fill_on_grid(orc):

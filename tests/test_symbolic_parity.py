@@ -28,6 +28,8 @@ def _compare(orc, n, cp, ri, **kw):
     assert info["flops_alg"] == o.stats["flops_alg"]
     assert info["flops_exec"] == o.stats["flops_exec"]
     assert info["panel_entries"] == o.stats["panel_size"]
+    lu = Solver(n, cp, ri, method="lu", **kw).info()
+    assert lu["flops_alg"] == o.stats["flops_alg_lu"] and lu["flops_exec"] == o.stats["flops_exec_lu"]
     return sy
 
 
