@@ -9,6 +9,8 @@
 //   t_k  = L_k,off^T x[rows of k]         (64-row chunks)
 //   x_k  = L_kk^{-T} (z_k - t_k)
 // Both use the inverse of each diagonal block kept by the factorization.
+// Several right-hand sides are handled in blocks of up to 8 per pass over
+// the panels (each loaded entry serves the whole block).
 // Column blocks of width <= 32 with at most 128 panel rows take both halves
 // of a step in one kernel per level, a group of 16 lanes per block
 // (fwd_small, bwd_small).
@@ -45,17 +47,25 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+// Every sweep kernel handles the right-hand sides in blocks of NR (1, 4 or
+// 8, the small-block kernels 1 or 2; chosen from nrhs at launch): the panel and inverse entries a thread
+// loads serve all NR columns of the block, so a panel is read once per
+// block of right-hand sides instead of once per right-hand side.
+// (staged vectors: element c of right-hand side j at [c * NR + j]; a masked
+// term is formed as 0 * value, so clamped indices stay inside the staged
+// entries: a value read from unwritten LDS may be NaN)
+
 // ---- forward, diagonal block: z_k = D y_k, D = L_kk^{-1} (lower, w x w,
 // column-major).  LANES lanes per row, 256/LANES rows per workgroup
 // (workgroup g of a block: rows g*256/LANES ..); lane q of a row takes the
 // columns p = q, q+LANES, ..., sixteen loads at a time (p > row clamped and
 // multiplied by zero).  Narrow levels (few blocks) use 16 lanes: fewer
 // dependent load rounds; wide levels 4.  grid = blocks * parts.
-template <class T, int LANES>
+template <class T, int LANES, int NR>
 __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblks, int parts)
 {
     constexpr int ROWS = 256 / LANES;
-    __shared__ double ys[256];
+    __shared__ double ys[256 * NR];
     const int k = cblks[blockIdx.x / parts];
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
@@ -64,11 +74,16 @@ __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblk
     const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
     const int tid = threadIdx.x, q = tid % LANES, row = min(r0 + tid / LANES, w - 1);
     const T* Dr = D + row;
-    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        const double* y = a.y + (int64_t)rhs * a.n + f;
-        if (tid < w) ys[tid] = y[tid];
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        const int nv = min(NR, a.nrhs - rb);
+        for (int idx = tid; idx < w * NR; idx += 256) {
+            const int c = idx / NR, j = idx - c * NR;
+            ys[idx] = j < nv ? a.y[(int64_t)(rb + j) * a.n + f + c] : 0.0;
+        }
         __syncthreads();
-        double v = 0.0;
+        double v[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) v[j] = 0.0;
         for (int pb = 0; pb <= row; pb += 16 * LANES) {
             T d[16];
 #pragma unroll
@@ -76,11 +91,16 @@ __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblk
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int p = pb + q + LANES * u;
-                v += (double)d[u] * (p <= row ? ys[min(p, 255)] : 0.0);
+                const double dv = p <= row ? (double)d[u] : 0.0;
+                const double* yp = ys + min(p, w - 1) * NR;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) v[j] += dv * yp[j];
             }
         }
-        const double sum = group_sum<LANES>(v);
-        if (r0 + tid / LANES < w && q == 0) a.z[(int64_t)rhs * a.n + f + row] = sum;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) v[j] = group_sum<LANES>(v[j]);
+        if (r0 + tid / LANES < w && q == 0)
+            for (int j = 0; j < nv; ++j) a.z[(int64_t)(rb + j) * a.n + f + row] = v[j];
         __syncthreads();
     }
 }
@@ -89,11 +109,11 @@ __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblk
 // workgroup per chunk of 64 rows: lane = row (each load covers 64
 // consecutive rows of one column), wave v = quarter v of the columns (at
 // most 64, issued 16 at a time); the four partial sums meet in LDS.
-template <class T>
+template <class T, int NR>
 __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
 {
-    __shared__ double zk[256];
-    __shared__ double part[4][64];
+    __shared__ double zk[256 * NR];
+    __shared__ double part[4 * 64 * NR];
     const int2 it = chunks[blockIdx.x];
     const int k = it.x, row0 = it.y;
     const DevPlan& pl = a.pl;
@@ -105,22 +125,38 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
     const int qw = (w + 3) >> 2, cb = wave * qw, ce = min(w, cb + qw);
     const T* Lr = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0 + r;
     const T* Pd = static_cast<const T*>(a.panels) + pl.panel_off[k];   // d_c at c * (ld + 1) (L D L^T)
-    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        if (tid < w) zk[tid] = a.z[(int64_t)rhs * a.n + f + tid] * (a.ldlt ? (double)Pd[tid * (ld + 1)] : 1.0);
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        const int nv = min(NR, a.nrhs - rb);
+        for (int idx = tid; idx < w * NR; idx += 256) {
+            const int c = idx / NR, j = idx - c * NR;
+            zk[idx] = j < nv ? a.z[(int64_t)(rb + j) * a.n + f + c] * (a.ldlt ? (double)Pd[c * (ld + 1)] : 1.0) : 0.0;
+        }
         __syncthreads();
-        double v = 0.0;
+        double v[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) v[j] = 0.0;
         for (int c = cb; c < ce; c += 16) {
             T l[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) l[u] = Lr[(int64_t)min(c + u, ce - 1) * ld];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v += (double)l[u] * (c + u < ce ? zk[min(c + u, w - 1)] : 0.0);
+            for (int u = 0; u < 16; ++u) {
+                const double lv = c + u < ce ? (double)l[u] : 0.0;
+                const double* zc = zk + min(c + u, w - 1) * NR;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) v[j] += lv * zc[j];
+            }
         }
-        part[wave][lane] = v;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) part[(wave * 64 + lane) * NR + j] = v[j];
         __syncthreads();
         if (wave == 0 && lane < nr) {
-            const double sum = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-            unsafeAtomicAdd(a.y + (int64_t)rhs * a.n + a.rowg[a.rowg_off[k] + (row0 - w) + lane], -sum);
+            const int gi = a.rowg[a.rowg_off[k] + (row0 - w) + lane];
+            for (int j = 0; j < nv; ++j) {
+                const double sum = (part[lane * NR + j] + part[(64 + lane) * NR + j]) +
+                                   (part[(128 + lane) * NR + j] + part[(192 + lane) * NR + j]);
+                unsafeAtomicAdd(a.y + (int64_t)(rb + j) * a.n + gi, -sum);
+            }
         }
         __syncthreads();
     }
@@ -131,10 +167,10 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
 // tid/4, tid/4 + 64, ...), lane q takes the rows q, q+4, ..., q+60 with all
 // sixteen loads in flight; each load instruction covers four consecutive
 // rows of sixteen columns.
-template <class T>
+template <class T, int NR>
 __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
 {
-    __shared__ double xr[kChunk];
+    __shared__ double xr[kChunk * NR];
     const int2 it = chunks[blockIdx.x];
     const int k = it.x, row0 = it.y;
     const DevPlan& pl = a.pl;
@@ -144,9 +180,12 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
     const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
     const int tid = threadIdx.x, q = tid & 3;
     const T* L = static_cast<const T*>(a.panels_b) + pl.panel_off[k] + row0;
-    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        const double* x = a.x + (int64_t)rhs * a.n;
-        if (tid < nr) xr[tid] = x[g[tid]];
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        const int nv = min(NR, a.nrhs - rb);
+        for (int idx = tid; idx < nr * NR; idx += 256) {
+            const int r = idx / NR, j = idx - r * NR;
+            xr[idx] = j < nv ? a.x[(int64_t)(rb + j) * a.n + g[r]] : 0.0;
+        }
         __syncthreads();
         for (int cb = 0; cb < w; cb += 64) {
             const int c = min(cb + (tid >> 2), w - 1);
@@ -154,11 +193,20 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
             T l[16];
 #pragma unroll
             for (int u = 0; u < 16; ++u) l[u] = Lc[min(q + 4 * u, nr - 1)];
-            double v = 0.0;
+            double v[NR];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v += (double)l[u] * (q + 4 * u < nr ? xr[q + 4 * u] : 0.0);
-            const double sum = group_sum<4>(v);
-            if (cb + (tid >> 2) < w && q == 0) unsafeAtomicAdd(a.tacc + (int64_t)rhs * a.n + f + c, sum);
+            for (int j = 0; j < NR; ++j) v[j] = 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const double lv = q + 4 * u < nr ? (double)l[u] : 0.0;
+                const double* xp = xr + min(q + 4 * u, nr - 1) * NR;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) v[j] += lv * xp[j];
+            }
+#pragma unroll
+            for (int j = 0; j < NR; ++j) v[j] = group_sum<4>(v[j]);
+            if (cb + (tid >> 2) < w && q == 0)
+                for (int j = 0; j < nv; ++j) unsafeAtomicAdd(a.tacc + (int64_t)(rb + j) * a.n + f + c, v[j]);
         }
         __syncthreads();
     }
@@ -167,11 +215,11 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
 // ---- backward, diagonal block: x_k = D^T (z_k - t_k); LANES lanes per
 // column c of D, lane q takes the rows p = c+q, c+q+LANES, ... (p >= w
 // clamped and multiplied by zero); same grid as the forward kernel
-template <class T, int LANES>
+template <class T, int LANES, int NR>
 __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblks, int parts)
 {
     constexpr int ROWS = 256 / LANES;
-    __shared__ double zs[256];
+    __shared__ double zs[256 * NR];
     const int k = cblks[blockIdx.x / parts];
     const DevPlan& pl = a.pl;
     const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
@@ -182,12 +230,17 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblk
     const T* Dc = D + (int64_t)col * w;
     const T* Pd = static_cast<const T*>(a.panels) + pl.panel_off[k];   // d_c at c * (ld + 1) (L D L^T)
     const int64_t ld = pl.stride[k];
-    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        const double* z = a.z + (int64_t)rhs * a.n + f;
-        const double* t = a.tacc + (int64_t)rhs * a.n + f;
-        if (tid < w) zs[tid] = (z[tid] - t[tid]) * (a.ldlt ? (double)Pd[tid * (ld + 1)] : 1.0);
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        const int nv = min(NR, a.nrhs - rb);
+        for (int idx = tid; idx < w * NR; idx += 256) {
+            const int c = idx / NR, j = idx - c * NR;
+            const int64_t o = (int64_t)(rb + j) * a.n + f + c;
+            zs[idx] = j < nv ? (a.z[o] - a.tacc[o]) * (a.ldlt ? (double)Pd[c * (ld + 1)] : 1.0) : 0.0;
+        }
         __syncthreads();
-        double v = 0.0;
+        double v[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) v[j] = 0.0;
         for (int pb = col; pb < w; pb += 16 * LANES) {
             T d[16];
 #pragma unroll
@@ -195,17 +248,22 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblk
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int p = pb + q + LANES * u;
-                v += (double)d[u] * (p < w ? zs[min(p, w - 1)] : 0.0);
+                const double dv = p < w ? (double)d[u] : 0.0;
+                const double* zp = zs + min(p, w - 1) * NR;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) v[j] += dv * zp[j];
             }
         }
-        const double sum = group_sum<LANES>(v);
-        if (c0 + tid / LANES < w && q == 0) a.x[(int64_t)rhs * a.n + f + col] = sum;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) v[j] = group_sum<LANES>(v[j]);
+        if (c0 + tid / LANES < w && q == 0)
+            for (int j = 0; j < nv; ++j) a.x[(int64_t)(rb + j) * a.n + f + col] = v[j];
         __syncthreads();
     }
 }
 
 // ---- small blocks (width <= 32, at most 128 panel rows), both halves of a
-// sweep step in one kernel: a group of 16 lanes per block, 16 blocks per
+// sweep step in one kernel per level: a group of 16 lanes per block, 16 blocks per
 // workgroup (the bottom levels of small systems hold tens of thousands of
 // blocks a few columns wide; one workgroup per block would leave most of
 // each workgroup idle and the launch bound by workgroup dispatch).
@@ -215,11 +273,11 @@ constexpr int kSGroups = 256 / kSG;        // small blocks per workgroup
 // forward: z_k = D y_k, then y[g(r)] -= L[r, :] z_k for the rows below
 constexpr int kMaxPass = (128 + kSG - 1) / kSG;   // rows below per lane, at most
 
-template <class T>
+template <class T, int NR>
 __global__ void __launch_bounds__(256) fwd_small(SweepArgs a, const int32_t* cblks, int count)
 {
-    __shared__ double ys[kSGroups][32];
-    __shared__ double zs[kSGroups][32];
+    __shared__ double ys[kSGroups][32 * NR];
+    __shared__ double zs[kSGroups][32 * NR];
     const int tid = threadIdx.x, g = tid / kSG, l = tid % kSG;
     const int idx = blockIdx.x * kSGroups + g;
     const bool on = idx < count;
@@ -231,30 +289,43 @@ __global__ void __launch_bounds__(256) fwd_small(SweepArgs a, const int32_t* cbl
     const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
     const T* L = static_cast<const T*>(a.panels) + pl.panel_off[k];
     const int32_t* rg = a.rowg + a.rowg_off[k] - w;   // rg[r]: global row of panel row r >= w
-    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        const int64_t vo = (int64_t)rhs * a.n;
-        for (int r = l; r < w; r += kSG) ys[g][r] = a.y[vo + f + r];
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        const int nv = min(NR, a.nrhs - rb);
+        for (int r = l; r < w; r += kSG)
+#pragma unroll
+            for (int j = 0; j < NR; ++j) ys[g][r * NR + j] = j < nv ? a.y[(int64_t)(rb + j) * a.n + f + r] : 0.0;
         __syncthreads();
         // (indices past the triangle or the panel are clamped; their terms
         // are multiplied by zero, so the loads of a round are unconditional)
         for (int r = l; r < w; r += kSG) {
-            double v = 0.0;
+            double v[NR];
+#pragma unroll
+            for (int j = 0; j < NR; ++j) v[j] = 0.0;
 #pragma unroll 1
             for (int p0 = 0; p0 <= r; p0 += 8) {
                 T d[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) d[u] = D[r + min(p0 + u, r) * w];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v += (double)d[u] * (p0 + u <= r ? ys[g][min(p0 + u, 31)] : 0.0);
+                for (int u = 0; u < 8; ++u) {
+                    const double dv = p0 + u <= r ? (double)d[u] : 0.0;
+                    const double* yp = &ys[g][min(p0 + u, r) * NR];
+#pragma unroll
+                    for (int j = 0; j < NR; ++j) v[j] += dv * yp[j];
+                }
             }
-            zs[g][r] = a.ldlt ? v * (double)L[r * (ld + 1)] : v;
-            a.z[vo + f + r] = v;
+            const double s = a.ldlt ? (double)L[r * (ld + 1)] : 1.0;
+#pragma unroll
+            for (int j = 0; j < NR; ++j) zs[g][r * NR + j] = v[j] * s;
+            for (int j = 0; j < nv; ++j) a.z[(int64_t)(rb + j) * a.n + f + r] = v[j];
         }
         __syncthreads();
         if (ld > w) {
-            double v[kMaxPass];
+            double v[kMaxPass][NR];
 #pragma unroll
-            for (int i = 0; i < kMaxPass; ++i) v[i] = 0.0;
+            for (int i = 0; i < kMaxPass; ++i)
+#pragma unroll
+                for (int j = 0; j < NR; ++j) v[i][j] = 0.0;
 #pragma unroll 1
             for (int c0 = 0; c0 < w; c0 += 4) {
                 T lv[4][kMaxPass];
@@ -265,15 +336,21 @@ __global__ void __launch_bounds__(256) fwd_small(SweepArgs a, const int32_t* cbl
                         lv[u][i] = L[min(w + l + kSG * i, ld - 1) + (int64_t)min(c0 + u, w - 1) * ld];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const double z = c0 + u < w ? zs[g][min(c0 + u, 31)] : 0.0;
+                    const bool cu = c0 + u < w;
+                    const double* zp = &zs[g][min(c0 + u, 31) * NR];
 #pragma unroll
-                    for (int i = 0; i < kMaxPass; ++i) v[i] += (double)lv[u][i] * z;
+                    for (int j = 0; j < NR; ++j) {
+                        const double z = cu ? zp[j] : 0.0;
+#pragma unroll
+                        for (int i = 0; i < kMaxPass; ++i) v[i][j] += (double)lv[u][i] * z;
+                    }
                 }
             }
 #pragma unroll
             for (int i = 0; i < kMaxPass; ++i) {
                 const int r = w + l + kSG * i;
-                if (r < ld) unsafeAtomicAdd(a.y + vo + rg[r], -v[i]);
+                if (r < ld)
+                    for (int j = 0; j < nv; ++j) unsafeAtomicAdd(a.y + (int64_t)(rb + j) * a.n + rg[r], -v[i][j]);
             }
         }
         __syncthreads();
@@ -282,10 +359,10 @@ __global__ void __launch_bounds__(256) fwd_small(SweepArgs a, const int32_t* cbl
 
 // backward: t = L_off^T x[g(rows below)] (sums over the group's lanes),
 // then x_k = D^T (z_k - t)
-template <class T>
+template <class T, int NR>
 __global__ void __launch_bounds__(256) bwd_small(SweepArgs a, const int32_t* cblks, int count)
 {
-    __shared__ double us[kSGroups][32];
+    __shared__ double us[kSGroups][32 * NR];
     const int tid = threadIdx.x, g = tid / kSG, l = tid % kSG;
     const int idx = blockIdx.x * kSGroups + g;
     const bool on = idx < count;
@@ -297,49 +374,62 @@ __global__ void __launch_bounds__(256) bwd_small(SweepArgs a, const int32_t* cbl
     const T* D = static_cast<const T*>(a.dinv_b) + pl.dinv_off[k];
     const T* L = static_cast<const T*>(a.panels_b) + pl.panel_off[k];
     const int32_t* rg = a.rowg + a.rowg_off[k] - w;
-    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
-        const int64_t vo = (int64_t)rhs * a.n;
-        double xr[kMaxPass];
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        const int nv = min(NR, a.nrhs - rb);
+        double xr[kMaxPass][NR];
 #pragma unroll
         for (int i = 0; i < kMaxPass; ++i) {
             const int r = w + l + kSG * i;
-            xr[i] = r < ld ? a.x[vo + rg[r]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NR; ++j) xr[i][j] = (r < ld && j < nv) ? a.x[(int64_t)(rb + j) * a.n + rg[r]] : 0.0;
         }
         // (xr is zero for rows past the panel: their clamped loads count zero)
 #pragma unroll 1
         for (int c0 = 0; c0 < w; c0 += 4) {
-            double v[4];
+            double v[4][NR];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 T lv[kMaxPass];
 #pragma unroll
                 for (int i = 0; i < kMaxPass; ++i)
                     lv[i] = L[min(w + l + kSG * i, ld - 1) + (int64_t)min(c0 + u, w - 1) * ld];
-                double t = 0.0;
 #pragma unroll
-                for (int i = 0; i < kMaxPass; ++i) t += (double)lv[i] * xr[i];
-                v[u] = t;
+                for (int j = 0; j < NR; ++j) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int i = 0; i < kMaxPass; ++i) t += (double)lv[i] * xr[i][j];
+                    v[u][j] = group_sum<kSG>(t);
+                }
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = group_sum<kSG>(v[u]);
             if (l < 4 && c0 + l < w) {
-                const double t = l == 0 ? v[0] : l == 1 ? v[1] : l == 2 ? v[2] : v[3];
-                const double u = a.z[vo + f + c0 + l] - t;
-                us[g][c0 + l] = a.ldlt ? u * (double)L[(c0 + l) * (ld + 1)] : u;
+                const double s = a.ldlt ? (double)L[(c0 + l) * (ld + 1)] : 1.0;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    const double t = l == 0 ? v[0][j] : l == 1 ? v[1][j] : l == 2 ? v[2][j] : v[3][j];
+                    const double u = j < nv ? a.z[(int64_t)(rb + j) * a.n + f + c0 + l] - t : 0.0;
+                    us[g][(c0 + l) * NR + j] = u * s;
+                }
             }
         }
         __syncthreads();
         for (int c = l; c < w; c += kSG) {
-            double v = 0.0;
+            double v[NR];
+#pragma unroll
+            for (int j = 0; j < NR; ++j) v[j] = 0.0;
 #pragma unroll 1
             for (int p0 = c; p0 < w; p0 += 8) {
                 T d[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) d[u] = D[min(p0 + u, w - 1) + c * w];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v += (double)d[u] * (p0 + u < w ? us[g][min(p0 + u, 31)] : 0.0);
+                for (int u = 0; u < 8; ++u) {
+                    const double dv = p0 + u < w ? (double)d[u] : 0.0;
+                    const double* up = &us[g][min(p0 + u, w - 1) * NR];
+#pragma unroll
+                    for (int j = 0; j < NR; ++j) v[j] += dv * up[j];
+                }
             }
-            a.x[vo + f + c] = v;
+            for (int j = 0; j < nv; ++j) a.x[(int64_t)(rb + j) * a.n + f + c] = v[j];
         }
         __syncthreads();
     }
@@ -484,45 +574,58 @@ static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64
 // levels with fewer blocks than this use 16 lanes per row in the diagonal kernels
 constexpr int kNarrowLevel = 64;
 
+// right-hand sides per pass over a panel: 1, 4 or 8 (16-lane small-block
+// kernels, whose lanes each keep up to 8 rows: 1 or 2)
+static int nr_block(int nrhs) { return nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 8); }
+
+#define SPX_NR_DISPATCH(NRV, CALL) \
+    do {                           \
+        if ((NRV) == 1) { constexpr int NR = 1; CALL; } \
+        else if ((NRV) == 4) { constexpr int NR = 4; CALL; } \
+        else { constexpr int NR = 8; CALL; } \
+    } while (0)
+
 hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
+    const int nrv = nr_block(a.nrhs);
     if (count < kNarrowLevel) {
         const int parts = (maxw + 15) / 16;
-        if (a.f32) fwd_diag<float, 16><<<parts * count, 256, 0, s>>>(a, cblks, parts);
-        else fwd_diag<double, 16><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 16, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)
+                                    : fwd_diag<double, 16, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)));
     } else {
         const int parts = (maxw + 63) / 64;
-        if (a.f32) fwd_diag<float, 4><<<parts * count, 256, 0, s>>>(a, cblks, parts);
-        else fwd_diag<double, 4><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 4, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)
+                                    : fwd_diag<double, 4, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)));
     }
     return hipGetLastError();
 }
 hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    if (a.f32) fwd_off<float><<<count, 256, 0, s>>>(a, chunks);
-    else fwd_off<double><<<count, 256, 0, s>>>(a, chunks);
+    SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? fwd_off<float, NR><<<count, 256, 0, s>>>(a, chunks)
+                                             : fwd_off<double, NR><<<count, 256, 0, s>>>(a, chunks)));
     return hipGetLastError();
 }
 hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    if (a.f32) bwd_off<float><<<count, 256, 0, s>>>(a, chunks);
-    else bwd_off<double><<<count, 256, 0, s>>>(a, chunks);
+    SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, NR><<<count, 256, 0, s>>>(a, chunks)
+                                             : bwd_off<double, NR><<<count, 256, 0, s>>>(a, chunks)));
     return hipGetLastError();
 }
 hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
+    const int nrv = nr_block(a.nrhs);
     if (count < kNarrowLevel) {
         const int parts = (maxw + 15) / 16;
-        if (a.f32) bwd_diag<float, 16><<<parts * count, 256, 0, s>>>(a, cblks, parts);
-        else bwd_diag<double, 16><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 16, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)
+                                    : bwd_diag<double, 16, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)));
     } else {
         const int parts = (maxw + 63) / 64;
-        if (a.f32) bwd_diag<float, 4><<<parts * count, 256, 0, s>>>(a, cblks, parts);
-        else bwd_diag<double, 4><<<parts * count, 256, 0, s>>>(a, cblks, parts);
+        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 4, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)
+                                    : bwd_diag<double, 4, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)));
     }
     return hipGetLastError();
 }
@@ -548,8 +651,13 @@ hipError_t launch_fwd_small(const SweepArgs& a, const int32_t* cblks, int count,
 {
     if (count <= 0) return hipSuccess;
     const int blocks = (count + kSGroups - 1) / kSGroups;
-    if (a.f32) fwd_small<float><<<blocks, 256, 0, s>>>(a, cblks, count);
-    else fwd_small<double><<<blocks, 256, 0, s>>>(a, cblks, count);
+    if (a.nrhs <= 1) {
+        if (a.f32) fwd_small<float, 1><<<blocks, 256, 0, s>>>(a, cblks, count);
+        else fwd_small<double, 1><<<blocks, 256, 0, s>>>(a, cblks, count);
+    } else {
+        if (a.f32) fwd_small<float, 2><<<blocks, 256, 0, s>>>(a, cblks, count);
+        else fwd_small<double, 2><<<blocks, 256, 0, s>>>(a, cblks, count);
+    }
     return hipGetLastError();
 }
 
@@ -557,8 +665,13 @@ hipError_t launch_bwd_small(const SweepArgs& a, const int32_t* cblks, int count,
 {
     if (count <= 0) return hipSuccess;
     const int blocks = (count + kSGroups - 1) / kSGroups;
-    if (a.f32) bwd_small<float><<<blocks, 256, 0, s>>>(a, cblks, count);
-    else bwd_small<double><<<blocks, 256, 0, s>>>(a, cblks, count);
+    if (a.nrhs <= 1) {
+        if (a.f32) bwd_small<float, 1><<<blocks, 256, 0, s>>>(a, cblks, count);
+        else bwd_small<double, 1><<<blocks, 256, 0, s>>>(a, cblks, count);
+    } else {
+        if (a.f32) bwd_small<float, 2><<<blocks, 256, 0, s>>>(a, cblks, count);
+        else bwd_small<double, 2><<<blocks, 256, 0, s>>>(a, cblks, count);
+    }
     return hipGetLastError();
 }
 
