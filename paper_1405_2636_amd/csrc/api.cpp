@@ -273,22 +273,31 @@ void build_tasks(spx_handle* h)
     const Plan& P = h->plan;
     const int32_t nc = P.ncblk;
     constexpr int kTrsmRows = 64;
+    constexpr int kChainLevel = 1;
     // high priority: FACT, the TRSM tiles and the update tiles into the first
     // facing block (the elimination chain) of every block, or (policy 1) of
     // the blocks in dependency levels of at most 32 blocks only; the other
     // update tiles form the bulk in the normal queue
     std::vector<int32_t> hp(nc, 1);
-    if (h->hp_policy == 1) {
-        std::vector<int32_t> lvl(nc, 0), per_level(static_cast<size_t>(nc) + 1, 0);
-        for (int32_t k = 0; k < nc; ++k)
-            for (int32_t q = P.uptr[k]; q < P.uptr[k + 1]; ++q)
-                lvl[P.utgt[q]] = std::max(lvl[P.utgt[q]], lvl[k] + 1);
-        for (int32_t k = 0; k < nc; ++k) ++per_level[lvl[k]];
+    // dependency levels (level(j) = 1 + max level of the blocks updating j)
+    std::vector<int32_t> lvl(nc, 0), per_level(static_cast<size_t>(nc) + 1, 0);
+    for (int32_t k = 0; k < nc; ++k)
+        for (int32_t q = P.uptr[k]; q < P.uptr[k + 1]; ++q)
+            lvl[P.utgt[q]] = std::max(lvl[P.utgt[q]], lvl[k] + 1);
+    for (int32_t k = 0; k < nc; ++k) ++per_level[lvl[k]];
+    if (h->hp_policy == 1)
         for (int32_t k = 0; k < nc; ++k) hp[k] = per_level[lvl[k]] <= 32 ? 1 : 0;
-    }
-    const int32_t tr = h->tile_rows, tcl = h->tile_cols;
-    // update tiles of source k into target group [b, b2) (blocks facing one cblk)
-    auto for_tiles = [&](int32_t k, int32_t b, int32_t b2, auto&& fn) {
+    // elimination chains: a block of width >= 128 in a level of at most
+    // kChainLevel blocks (the top separators' pieces, factored one after the
+    // other while most of the GPU waits) takes thin TRSM items and thin
+    // update tiles into its first facing block: a quarter of the work per
+    // wave, four times as many items side by side, a shorter chain link
+    std::vector<char> chain(nc, 0);
+    for (int32_t k = 0; k < nc; ++k)
+        chain[k] = per_level[lvl[k]] <= kChainLevel && P.lcol[k] - P.fcol[k] + 1 >= 128;
+    // update tiles of source k into target group [b, b2) (blocks facing one
+    // cblk), tr x tcl each
+    auto for_tiles = [&](int32_t k, int32_t b, int32_t b2, int32_t tr, int32_t tcl, auto&& fn) {
         const int32_t ld = P.stride[k];
         const int32_t rs = P.coefind[b];
         const int32_t re = P.coefind[b2 - 1] + (P.lrow[b2 - 1] - P.frow[b2 - 1] + 1);
@@ -313,7 +322,7 @@ void build_tasks(spx_handle* h)
                 int32_t b2 = b;
                 while (b2 < P.bptr[k + 1] && P.fcblk[b2] == P.fcblk[b]) ++b2;
                 nmap += ld - P.coefind[b];
-                for_tiles(k, b, b2, [&](int32_t, int32_t, int32_t, int32_t) { ++ntiles; });
+                for_tiles(k, b, b2, h->tile_rows, h->tile_cols, [&](int32_t, int32_t, int32_t, int32_t) { ++ntiles; });
                 b = b2;
             }
             if (ntiles <= kSmallMaxUpd && nmap <= kSmallMap) {
@@ -365,10 +374,11 @@ void build_tasks(spx_handle* h)
     for (int32_t k = 0; k < nc; ++k) {
         const int32_t w = P.lcol[k] - P.fcol[k] + 1, ld = P.stride[k];
         tf[k] = id;
-        // 64 rows per wave tile; panels narrower than 256 columns stack 4/ceil(w/64) of them
-        const int32_t trows = kTrsmRows * (4 / ((w + 63) / 64));
+        // 64 rows per wave tile (chains: 16); panels narrower than 256
+        // columns stack 4/ceil(w/64) of them
+        const int32_t trows = (chain[k] ? 16 : kTrsmRows) * (4 / ((w + 63) / 64));
         for (int32_t r = w; r < ld && !small[k]; r += trows) {
-            desc.push_back(int4{kTrsm, k, r, std::min(trows, ld - r)});
+            desc.push_back(int4{kTrsm | (chain[k] ? kThinItem : 0), k, r, std::min(trows, ld - r)});
             desc.push_back(int4{0, 0, 0, 0});
             ++id;
         }
@@ -410,7 +420,9 @@ void build_tasks(spx_handle* h)
                 rmap.push_back(pos);
             }
             const int32_t mbase = static_cast<int32_t>(moff - rs);
-            for_tiles(k, b, b2, [&](int32_t r0, int32_t mr, int32_t c0, int32_t ncl) {
+            const bool thin = chain[k] && first_pair && !small[k];
+            const int32_t ttr = thin ? 64 : h->tile_rows, ttc = thin ? 64 : h->tile_cols;
+            for_tiles(k, b, b2, ttr, ttc, [&](int32_t r0, int32_t mr, int32_t c0, int32_t ncl) {
                 ++dep[j];
                 if (small[k]) {
                     const int64_t po = P.panel_off[j];
@@ -419,7 +431,7 @@ void build_tasks(spx_handle* h)
                     ftab.push_back(int4{static_cast<int32_t>(po & 0xffffffff), static_cast<int32_t>(po >> 32), 0, 0});
                     return;
                 }
-                desc.push_back(int4{kUpdate | ((npieces - 1) << 8), k, j, r0});
+                desc.push_back(int4{kUpdate | ((npieces - 1) << 8) | (thin ? kThinItem : 0), k, j, r0});
                 desc.push_back(int4{mr, c0, ncl, mbase});
                 ++id;
                 if (first_pair && hp[k]) ++uh[k];

@@ -20,12 +20,15 @@ struct DevPlan {
     const int64_t* dinv_off;   // offset of the inverted diagonal tiles of each cblk
 };
 
-// Work-item kinds of the device scheduler.
+// Work-item kinds of the device scheduler (low byte of the first word; an
+// update keeps its merged piece count - 1 in bits 8..11; bit 12 marks a thin
+// TRSM or update item of an elimination chain: 16-row wave tiles).
 enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2, kSmall = 3 };
+constexpr int32_t kThinItem = 1 << 12;
 
 // Two int4 per item: {kind, k, a, b}, {c, d, e, f}
 //   kFact:   k
-//   kTrsm:   k, row0 = first panel row, nrows (<= 64 * (4 / ceil(w / 64)))
+//   kTrsm:   k, row0 = first panel row, nrows (<= 64 * (4 / ceil(w / 64)); thin: 16 * ...)
 //   kUpdate: k (source), j (target), row0 (first source panel row);
 //            mrows, col0 (first facing panel row), ncols, mbase (row-map base)
 //   kSmall:  k; first tile of k in the fused-tile table, tile count, first

@@ -165,43 +165,43 @@ __device__ __forceinline__ void gstore_s(const GOp& g, int voff, int soff, float
 // 128 accumulator registers and the operands exceed the 256 registers of a
 // wave at two workgroups per CU, and the spilled operands each cost a wait
 // for every outstanding load.
-template <int NB, class T>
-__device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][4], const GOp& X, const GOp& Y, int K)
+template <int NB, class T, int RB = 4>
+__device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nchunks = (K + 7) >> 3;
     if (nchunks <= 0) return;
-    int xo[2][4], yo[2][NB];
+    int xo[2][RB], yo[2][NB];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) xo[u][b] = X.off + (16 * b + li) * X.si + (4 * u + lk) * X.sk;
+        for (int b = 0; b < RB; ++b) xo[u][b] = X.off + (16 * b + li) * X.si + (4 * u + lk) * X.sk;
 #pragma unroll
         for (int b = 0; b < NB; ++b) yo[u][b] = Y.off + (16 * b + li) * Y.si + (4 * u + lk) * Y.sk;
     }
     const int dx = 8 * X.sk, dy = 8 * Y.sk;
-    T xa[2][4], ya[2][NB], xb[2][4], yb[2][NB], xc[2][4], yc[2][NB];
+    T xa[2][RB], ya[2][NB], xb[2][RB], yb[2][NB], xc[2][RB], yc[2][NB];
     // (scheduling barriers keep every group of loads ahead of the products
     // it is meant to overlap; left alone, the compiler sinks the FP32 loads
     // next to their uses and waits for them)
-    auto load = [&](T (&xs)[2][4], T (&ys)[2][NB], int ch) {
+    auto load = [&](T (&xs)[2][RB], T (&ys)[2][NB], int ch) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) xs[u][b] = gload<T>(X, xo[u][b] + ch * dx);
+            for (int b = 0; b < RB; ++b) xs[u][b] = gload<T>(X, xo[u][b] + ch * dx);
 #pragma unroll
             for (int b = 0; b < NB; ++b) ys[u][b] = gload<T>(Y, yo[u][b] + ch * dy);
         }
         __builtin_amdgcn_sched_barrier(0);
     };
-    auto mma = [&](const T (&xs)[2][4], const T (&ys)[2][NB]) {
+    auto mma = [&](const T (&xs)[2][RB], const T (&ys)[2][NB]) {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = MM<T>::mfma(ys[u][bi], xs[u][bj], acc[bi][bj]);
+                for (int bj = 0; bj < RB; ++bj) acc[bi][bj] = MM<T>::mfma(ys[u][bi], xs[u][bj], acc[bi][bj]);
         __builtin_amdgcn_sched_barrier(0);
     };
     // (reads past the last chunk repeat it and are not used)
@@ -262,40 +262,40 @@ __device__ __forceinline__ void split_bf16(const float (&v)[4], s16x4& hi, s16x4
     lo = __builtin_bit_cast(s16x4, l);
 }
 
-template <int NB>
-__device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][4], const GOp& X, const GOp& Y, int K)
+template <int NB, int RB = 4>
+__device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][RB], const GOp& X, const GOp& Y, int K)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nchunks = (K + 15) >> 4;
     if (nchunks <= 0) return;
-    int xo[4], yo[NB];
+    int xo[RB], yo[NB];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) xo[b] = X.off + (16 * b + li) * X.si + lk * X.sk;
+    for (int b = 0; b < RB; ++b) xo[b] = X.off + (16 * b + li) * X.si + lk * X.sk;
 #pragma unroll
     for (int b = 0; b < NB; ++b) yo[b] = Y.off + (16 * b + li) * Y.si + lk * Y.sk;
     const int dx = 4 * X.sk, dy = 4 * Y.sk;
-    float xa[4][4], ya[NB][4], xb[4][4], yb[NB][4];
-    auto load = [&](float (&xs)[4][4], float (&ys)[NB][4], int ch) {
+    float xa[RB][4], ya[NB][4], xb[RB][4], yb[NB][4];
+    auto load = [&](float (&xs)[RB][4], float (&ys)[NB][4], int ch) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) xs[b][s] = gload<float>(X, xo[b] + (4 * ch + s) * dx);
+            for (int b = 0; b < RB; ++b) xs[b][s] = gload<float>(X, xo[b] + (4 * ch + s) * dx);
 #pragma unroll
             for (int b = 0; b < NB; ++b) ys[b][s] = gload<float>(Y, yo[b] + (4 * ch + s) * dy);
         }
         __builtin_amdgcn_sched_barrier(0);
     };
-    auto mma = [&](const float (&xs)[4][4], const float (&ys)[NB][4]) {
-        s16x4 xh[4], xl[4];
+    auto mma = [&](const float (&xs)[RB][4], const float (&ys)[NB][4]) {
+        s16x4 xh[RB], xl[RB];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) split_bf16(xs[b], xh[b], xl[b]);
+        for (int b = 0; b < RB; ++b) split_bf16(xs[b], xh[b], xl[b]);
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
             s16x4 yh, yl;
             split_bf16(ys[bi], yh, yl);
 #pragma unroll
-            for (int bj = 0; bj < 4; ++bj) {
+            for (int bj = 0; bj < RB; ++bj) {
                 acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yh, xh[bj], acc[bi][bj], 0, 0, 0);
                 acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yh, xl[bj], acc[bi][bj], 0, 0, 0);
                 acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yl, xh[bj], acc[bi][bj], 0, 0, 0);
@@ -320,41 +320,41 @@ __device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][4], const GOp& X, 
 // scaled by d_p (read through Dg: element p at p * Dg.sk, the diagonal of the
 // source panel) just before the products, so its loads stay in flight; two
 // register buffers of 8 inner indices as in wave_gemm.
-template <int NB>
-__device__ __forceinline__ void wave_gemm_d(d4 (&acc)[NB][4], const GOp& X, const GOp& Y, const GOp& Dg, int K)
+template <int NB, int RB = 4>
+__device__ __forceinline__ void wave_gemm_d(d4 (&acc)[NB][RB], const GOp& X, const GOp& Y, const GOp& Dg, int K)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nchunks = (K + 7) >> 3;
     if (nchunks <= 0) return;
-    int xo[2][4], yo[2][NB];
+    int xo[2][RB], yo[2][NB];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) xo[u][b] = X.off + (16 * b + li) * X.si + (4 * u + lk) * X.sk;
+        for (int b = 0; b < RB; ++b) xo[u][b] = X.off + (16 * b + li) * X.si + (4 * u + lk) * X.sk;
 #pragma unroll
         for (int b = 0; b < NB; ++b) yo[u][b] = Y.off + (16 * b + li) * Y.si + (4 * u + lk) * Y.sk;
     }
     const int dx = 8 * X.sk, dy = 8 * Y.sk;
-    double xa[2][4], ya[2][NB], da[2], xb[2][4], yb[2][NB], db[2];
-    auto load = [&](double (&xs)[2][4], double (&ys)[2][NB], double (&ds)[2], int ch) {
+    double xa[2][RB], ya[2][NB], da[2], xb[2][RB], yb[2][NB], db[2];
+    auto load = [&](double (&xs)[2][RB], double (&ys)[2][NB], double (&ds)[2], int ch) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) xs[u][b] = gload<double>(X, xo[u][b] + ch * dx);
+            for (int b = 0; b < RB; ++b) xs[u][b] = gload<double>(X, xo[u][b] + ch * dx);
 #pragma unroll
             for (int b = 0; b < NB; ++b) ys[u][b] = gload<double>(Y, yo[u][b] + ch * dy);
             ds[u] = gload<double>(Dg, Dg.off + (8 * ch + 4 * u + lk) * Dg.sk);
         }
         __builtin_amdgcn_sched_barrier(0);
     };
-    auto mma = [&](const double (&xs)[2][4], const double (&ys)[2][NB], const double (&ds)[2]) {
+    auto mma = [&](const double (&xs)[2][RB], const double (&ys)[2][NB], const double (&ds)[2]) {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
+                for (int bj = 0; bj < RB; ++bj)
                     acc[bi][bj] = MM<double>::mfma(ys[u][bi] * ds[u], xs[u][bj], acc[bi][bj]);
         __builtin_amdgcn_sched_barrier(0);
     };
@@ -372,37 +372,37 @@ __device__ __forceinline__ void wave_gemm_d(d4 (&acc)[NB][4], const GOp& X, cons
 
 // acc += X Y^T over K inner indices: FP64 or FP32 products, or (FP32 panels
 // with the split option) split-BF16 products
-template <int NB, class T>
-__device__ __forceinline__ void tile_gemm(typename MM<T>::acc (&acc)[NB][4], const GOp& X, const GOp& Y, int K, bool split)
+template <int NB, class T, int RB = 4>
+__device__ __forceinline__ void tile_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K, bool split)
 {
     if constexpr (sizeof(T) == 4) {
         if (split) {
-            wave_gemm_split<NB>(acc, X, Y, K);
+            wave_gemm_split<NB, RB>(acc, X, Y, K);
             return;
         }
     }
-    wave_gemm<NB, T>(acc, X, Y, K);
+    wave_gemm<NB, T, RB>(acc, X, Y, K);
 }
 
-template <int NB, class A>
-__device__ __forceinline__ void zero_acc(A (&acc)[NB][4])
+template <int NB, class A, int RB>
+__device__ __forceinline__ void zero_acc(A (&acc)[NB][RB])
 {
 #pragma unroll
     for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = A{0, 0, 0, 0};
+        for (int j = 0; j < RB; ++j) acc[i][j] = A{0, 0, 0, 0};
 }
 
 // epi(r, c, value) over a wave's accumulator, r < mv, c < nv
-template <class T, int NB, class Epi>
-__device__ __forceinline__ void wave_store(const typename MM<T>::acc (&acc)[NB][4], int mv, int nv, Epi epi)
+template <class T, int NB, int RB, class Epi>
+__device__ __forceinline__ void wave_store(const typename MM<T>::acc (&acc)[NB][RB], int mv, int nv, Epi epi)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
+        for (int bj = 0; bj < RB; ++bj)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = 16 * bj + li, c = 16 * bi + MM<T>::drow(v, lk);
@@ -1028,7 +1028,9 @@ __device__ __noinline__ void task_fact_lu(const SchedArgs& a, int k, double* Lt,
 // triangular D.  poff / doff select the panel array and the inverse (L U:
 // the L rows take U_kk^{-T}, giving A_off U_kk^{-1}; the U^T rows take
 // L_kk^{-1}, giving A_up^T L_kk^{-T}).
-template <class T>
+// RB: 16-row blocks per wave tile (4: 64-row wave tiles; 1: the thin items
+// of elimination chains, a quarter of the work per wave).
+template <class T, int RB = 4>
 __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int nrows, int64_t poff = 0,
                                        int64_t doff = 0)
 {
@@ -1039,22 +1041,23 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
     auto B = glob(P + row0);
     const T* D = static_cast<const T*>(a.dinv) + doff + pl.dinv_off[k];
     const int wave = threadIdx.x >> 6;
-    typename MM<T>::acc acc[4][4];
+    typename MM<T>::acc acc[4][RB];
     zero_acc(acc);
-    // 64x64 wave tiles: ncb column blocks of the output, and 4/ncb blocks of
-    // 64 rows (a chunk has 64 * (4/ncb) rows), so narrow panels keep all four
-    // waves busy
+    // (16 RB) x 64 wave tiles: ncb column blocks of the output, and 4/ncb
+    // blocks of 16 RB rows (a chunk has 16 RB * (4/ncb) rows), so narrow
+    // panels keep all four waves busy
+    constexpr int TR = 16 * RB;
     const int ncb = (w + 63) >> 6, nrb = 4 / ncb;
     const int cb = wave % ncb, rb = wave / ncb;
-    const int c0 = 64 * cb, r0 = 64 * rb;
+    const int c0 = 64 * cb, r0 = TR * rb;
     const int nv = min(64, w - c0);
     const bool on = rb < nrb && nv > 0 && r0 < nrows;
     if (on)
-        tile_gemm<4, T>(acc, make_gop(P, ld * w, row0 + r0, 1, ld), make_gop(D, (int64_t)w * w, c0, 1, w),
-                        min(w, c0 + 64), a.split != 0);
+        tile_gemm<4, T, RB>(acc, make_gop(P, ld * w, row0 + r0, 1, ld), make_gop(D, (int64_t)w * w, c0, 1, w),
+                            min(w, c0 + 64), a.split != 0);
     __syncthreads();   // every wave has read all of B before any result is written
     if (on)
-        wave_store<T>(acc, min(64, nrows - r0), nv,
+        wave_store<T>(acc, min(TR, nrows - r0), nv,
                       [&](int r, int c, T v) { B[(r0 + r) + (int64_t)(c0 + c) * ld] = v; });
 }
 
@@ -1074,11 +1077,13 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // W_L = L_k[rows] U^T_k[cols]^T goes to j's L panel (its square diagonal
 // block included), and, for rows below j's diagonal block, W_U =
 // U^T_k[rows] L_k[cols]^T to j's U^T panel.
-template <class T, bool LDL = false, bool LU = false>
+// RB = 1: a thin tile of an elimination chain, at most 64 x 64, each wave
+// 16 rows of it (a quarter of the work of a 64-row wave tile).
+template <class T, bool LDL = false, bool LU = false, int RB = 4>
 __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos, int* cpos)
 {
     const DevPlan& pl = a.pl;
-    const int k = d0.y, j = d0.z, row0 = d0.w, np = (d0.x >> 8) + 1;
+    const int k = d0.y, j = d0.z, row0 = d0.w, np = ((d0.x >> 8) & 15) + 1;
     const int mrows = d1.x, col0 = d1.y, ncols = d1.z, mbase = d1.w;
     const int64_t ldj = pl.stride[j];
     auto Cg = glob(static_cast<T*>(a.panels) + pl.panel_off[j]);
@@ -1086,10 +1091,10 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
     if (tid < mrows) rpos[tid] = a.rmap[mbase + row0 + tid];
     if (tid < ncols) cpos[tid] = a.rmap[mbase + col0 + tid];
     __syncthreads();
-    const bool square = ncols > 64;
-    const int r0 = square ? 64 * (wave & 1) : 64 * wave;
+    const bool square = RB == 4 && ncols > 64;
+    const int r0 = square ? 64 * (wave & 1) : 16 * RB * wave;
     const int c0 = square ? 64 * (wave >> 1) : 0;
-    const int mv = min(64, mrows - r0), nv = min(64, ncols - c0);
+    const int mv = min(16 * RB, mrows - r0), nv = min(64, ncols - c0);
     if (mv > 0 && nv > 0) {
         const int fk = pl.fcol[k];
         // half 0: W = X Y^T with X the rows and Y the facing rows of the L
@@ -1098,7 +1103,7 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
         const int wj = pl.lcol[j] - pl.fcol[j] + 1;
         const int nhalf = (LU && rpos[r0 + mv - 1] >= wj) ? 2 : 1;
         for (int half = 0; half < nhalf; ++half) {
-            typename MM<T>::acc acc[4][4];
+            typename MM<T>::acc acc[4][RB];
             zero_acc(acc);
             const int64_t xo = (LU && half == 1) ? a.upanel : 0, yo = (LU && half == 0) ? a.upanel : 0;
             for (int p = k - np + 1; p <= k; ++p) {
@@ -1106,11 +1111,11 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
                 const int64_t ld = pl.stride[p];
                 const T* A = static_cast<const T*>(a.panels) + pl.panel_off[p];
                 if constexpr (LDL)
-                    wave_gemm_d<4>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld),
-                                   make_gop(A, ld * w, col0 + c0 + sh, 1, ld), make_gop(A, ld * w, 0, 0, ld + 1), w);
+                    wave_gemm_d<4, RB>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld),
+                                       make_gop(A, ld * w, col0 + c0 + sh, 1, ld), make_gop(A, ld * w, 0, 0, ld + 1), w);
                 else
-                    tile_gemm<4, T>(acc, make_gop(A + xo, ld * w, row0 + r0 + sh, 1, ld),
-                                    make_gop(A + yo, ld * w, col0 + c0 + sh, 1, ld), w, a.split != 0);
+                    tile_gemm<4, T, RB>(acc, make_gop(A + xo, ld * w, row0 + r0 + sh, 1, ld),
+                                        make_gop(A + yo, ld * w, col0 + c0 + sh, 1, ld), w, a.split != 0);
             }
             if constexpr (LU) {
                 auto Cu = Cg + (half == 1 ? a.upanel : 0);
@@ -1345,7 +1350,8 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         __syncthreads();
         const int4 d0 = a.desc[2 * item];
         const int4 d1 = a.desc[2 * item + 1];
-        const int kind = d0.x & 0xff;   // (bits 8.. of an update: pieces merged - 1)
+        const int kind = d0.x & 0xff;   // (bits 8..11 of an update: pieces merged - 1; bit 12: thin item)
+        const bool thin = (d0.x & kThinItem) != 0;
         if (kind == kFact) {
             __builtin_amdgcn_s_setprio(3);
             if constexpr (LU) task_fact_lu<T>(a, d0.y, Lt, Dt, Pb);
@@ -1354,14 +1360,21 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         } else if (kind == kTrsm) {
             __builtin_amdgcn_s_setprio(2);
             if constexpr (LU) {
-                task_trsm<T>(a, d0.y, d0.z, d0.w, 0, a.uinv);
-                task_trsm<T>(a, d0.y, d0.z, d0.w, a.upanel, 0);
+                if (thin) {
+                    task_trsm<T, 1>(a, d0.y, d0.z, d0.w, 0, a.uinv);
+                    task_trsm<T, 1>(a, d0.y, d0.z, d0.w, a.upanel, 0);
+                } else {
+                    task_trsm<T>(a, d0.y, d0.z, d0.w, 0, a.uinv);
+                    task_trsm<T>(a, d0.y, d0.z, d0.w, a.upanel, 0);
+                }
             } else {
-                task_trsm<T>(a, d0.y, d0.z, d0.w);
+                if (thin) task_trsm<T, 1>(a, d0.y, d0.z, d0.w);
+                else task_trsm<T>(a, d0.y, d0.z, d0.w);
             }
             __builtin_amdgcn_s_setprio(0);
         } else if (kind == kUpdate) {
-            task_update<T, LDL, LU>(a, d0, d1, rpos, cpos);
+            if (thin) task_update<T, LDL, LU, 1>(a, d0, d1, rpos, cpos);
+            else task_update<T, LDL, LU>(a, d0, d1, rpos, cpos);
         } else if constexpr (!LDL && !LU) {
             task_small<T>(a, d0, d1, Lt, Dt, Pb);
         }
