@@ -87,6 +87,10 @@ def _load():
     L.orc_unpack.argtypes = [vp, vp, vp, vp, vp]
     L.orc_factor_ldlt.restype = C.c_int
     L.orc_factor_ldlt.argtypes = [vp, vp, C.POINTER(i32)]
+    L.orc_factor_ldlt_sp.restype = C.c_int
+    L.orc_factor_ldlt_sp.argtypes = [vp, vp, dbl, C.POINTER(i32), C.POINTER(i32)]
+    L.orc_factor_lu_sp.restype = C.c_int
+    L.orc_factor_lu_sp.argtypes = [vp, vp, vp, dbl, C.POINTER(i32), C.POINTER(i32)]
     L.orc_solve_ldlt.restype = C.c_int
     L.orc_solve_ldlt.argtypes = [vp, vp, i32, vp, i64, vp, i64]
     L.orc_logabsdet_ldlt.restype = dbl
@@ -315,19 +319,35 @@ class ZeroPivot(RuntimeError):
         self.col_orig = col_orig
 
 
-def factor_ldlt(sym: Symbolic, colptr, rowind, values):
+def static_pivot_tau(colptr, rowind, values, eps, lower_only):
+    """tau = eps * max |a_ij| over the entries the factorization reads (the
+    lower triangle for L D L^T, all entries for L U)."""
+    colptr = np.asarray(colptr, np.int64)
+    rowind = np.asarray(rowind, np.int64)
+    v = np.abs(np.asarray(values, np.float64))
+    if lower_only:
+        col = np.repeat(np.arange(len(colptr) - 1), np.diff(colptr))
+        v = v[rowind >= col]
+    return float(eps) * (float(v.max()) if v.size else 0.0)
+
+
+def factor_ldlt(sym: Symbolic, colptr, rowind, values, pivot_eps=0.0, return_nrep=False):
     """Assemble and factor as L D L^T (static pivoting: the analysis' order);
     returns the panel array: D on the diagonal of each diagonal block, the
-    strictly lower entries of the unit lower L elsewhere."""
+    strictly lower entries of the unit lower L elsewhere.  pivot_eps > 0:
+    pivots below pivot_eps * max |a_ij| in magnitude are replaced (with
+    return_nrep, (P, number replaced) is returned)."""
     L = _load()
     P = assemble(sym, colptr, rowind, values)
     fc = C.c_int32(-1)
-    rc = L.orc_factor_ldlt(C.c_void_p(sym.handle), _p(P), C.byref(fc))
+    nrep = C.c_int32(0)
+    tau = static_pivot_tau(colptr, rowind, values, pivot_eps, True) if pivot_eps > 0 else 0.0
+    rc = L.orc_factor_ldlt_sp(C.c_void_p(sym.handle), _p(P), tau, C.byref(nrep), C.byref(fc))
     if rc == ENOTPD:
         raise ZeroPivot(fc.value, int(sym.perm[fc.value]))
     if rc != 0:
         raise RuntimeError("orc_factor_ldlt failed %d" % rc)
-    return P
+    return (P, nrep.value) if return_nrep else P
 
 
 def solve_ldlt(sym: Symbolic, P, b):
@@ -346,11 +366,13 @@ def logabsdet_ldlt(sym: Symbolic, P):
     return v, nneg.value
 
 
-def factor_lu(sym: Symbolic, colptr, rowind, values):
+def factor_lu(sym: Symbolic, colptr, rowind, values, pivot_eps=0.0, return_nrep=False):
     """Assemble both triangles and factor as L U (static pivoting: the
     analysis' order on the pattern of A + A^T); returns (PL, PU): PL holds
     the diagonal blocks' L (strictly lower) and U (upper) and L below them,
-    PU holds U^T below the diagonal blocks."""
+    PU holds U^T below the diagonal blocks.  pivot_eps > 0: pivots below
+    pivot_eps * max |a_ij| in magnitude are replaced (with return_nrep,
+    (PL, PU, number replaced) is returned)."""
     L = _load()
     PL = np.zeros(max(int(sym.stats["panel_size"]), 1), np.float64)
     PU = np.zeros_like(PL)
@@ -359,12 +381,14 @@ def factor_lu(sym: Symbolic, colptr, rowind, values):
     if rc != 0:
         raise ValueError("assemble_lu failed")
     fc = C.c_int32(-1)
-    rc = L.orc_factor_lu(C.c_void_p(sym.handle), _p(PL), _p(PU), C.byref(fc))
+    nrep = C.c_int32(0)
+    tau = static_pivot_tau(colptr, rowind, values, pivot_eps, False) if pivot_eps > 0 else 0.0
+    rc = L.orc_factor_lu_sp(C.c_void_p(sym.handle), _p(PL), _p(PU), tau, C.byref(nrep), C.byref(fc))
     if rc == ENOTPD:
         raise ZeroPivot(fc.value, int(sym.perm[fc.value]))
     if rc != 0:
         raise RuntimeError("orc_factor_lu failed %d" % rc)
-    return PL, PU
+    return (PL, PU, nrep.value) if return_nrep else (PL, PU)
 
 
 def solve_lu(sym: Symbolic, PL, PU, b):

@@ -982,9 +982,35 @@ int orc_factor_range(const orc_sym* s, double* P, i32 kbeg, i32 kend, i32* fail_
  * entries of L (unit diagonal implied) below it and in the off-diagonal
  * rows.  Returns ORC_ENOTPD and the failing column on breakdown.
  */
+int orc_factor_ldlt_sp(const orc_sym* s, double* P, double tau, i32* nrep, i32* fail_col);
+
 int orc_factor_ldlt(const orc_sym* s, double* P, i32* fail_col)
 {
+    i32 nrep = 0;
+    return orc_factor_ldlt_sp(s, P, 0.0, &nrep, fail_col);
+}
+
+/*
+ * Static pivot replacement (Section III's static pivoting: no row or column
+ * exchange, so a pivot that is too small is replaced instead): with
+ * tau > 0, a pivot of magnitude below tau becomes +tau or -tau with the
+ * pivot's sign (+tau for a zero pivot), and *nrep counts the replacements;
+ * tau = 0 leaves every pivot as it is (a zero or non-finite one is then a
+ * breakdown).  A non-finite pivot is never replaced.
+ */
+static double static_pivot(double d, double tau, i32* nrep)
+{
+    if (tau > 0.0 && fabs(d) < tau) {
+        (*nrep)++;
+        return d < 0.0 ? -tau : tau;
+    }
+    return d;
+}
+
+int orc_factor_ldlt_sp(const orc_sym* s, double* P, double tau, i32* nrep, i32* fail_col)
+{
     *fail_col = -1;
+    *nrep = 0;
     i32 maxs = 0;
     for (i32 k = 0; k < s->ncblk; k++) if (s->stride[k] > maxs) maxs = s->stride[k];
     double* W = (double*)malloc(sizeof(double) * (size_t)maxs * (size_t)maxs + 8);
@@ -999,6 +1025,7 @@ int orc_factor_ldlt(const orc_sym* s, double* P, i32* fail_col)
         for (i32 c = 0; c < wd; c++) {
             double d = L[c + (i64)c * ld];
             for (i32 p = 0; p < c; p++) d -= L[c + (i64)p * ld] * L[p + (i64)p * ld] * L[c + (i64)p * ld];
+            d = static_pivot(d, tau, nrep);
             if (!(d != 0.0) || !isfinite(d)) { *fail_col = s->fcol[k] + c; free(W); free(grow); return ORC_ENOTPD; }
             L[c + (i64)c * ld] = d;
             for (i32 r = c + 1; r < ld; r++) {
@@ -1173,9 +1200,20 @@ int orc_assemble_lu(const orc_sym* s, const i64* colptr, const i32* rowind, cons
  *      block) is subtracted from PL's diagonal block of j in full, the rows
  *      beyond it from PL (W_L) and PU (W_U) of j.
  */
+int orc_factor_lu_sp(const orc_sym* s, double* PL, double* PU, double tau, i32* nrep, i32* fail_col);
+
 int orc_factor_lu(const orc_sym* s, double* PL, double* PU, i32* fail_col)
 {
+    i32 nrep = 0;
+    return orc_factor_lu_sp(s, PL, PU, 0.0, &nrep, fail_col);
+}
+
+/* L U with the static pivot replacement of orc_factor_ldlt_sp (the pivot
+ * u_cc replaced in place before it is used). */
+int orc_factor_lu_sp(const orc_sym* s, double* PL, double* PU, double tau, i32* nrep, i32* fail_col)
+{
     *fail_col = -1;
+    *nrep = 0;
     i32 maxs = 0;
     for (i32 k = 0; k < s->ncblk; k++) if (s->stride[k] > maxs) maxs = s->stride[k];
     double* WL = (double*)malloc(sizeof(double) * (size_t)maxs * (size_t)maxs + 8);
@@ -1190,7 +1228,8 @@ int orc_factor_lu(const orc_sym* s, double* PL, double* PU, i32* fail_col)
             for (i32 r = s->frow[b]; r <= s->lrow[b]; r++) grow[s->coefind[b] + r - s->frow[b]] = r;
         /* 1. diagonal block, in place (B(r, c) at L[r + c*ld]) */
         for (i32 c = 0; c < wd; c++) {
-            double d = L[c + (i64)c * ld];
+            double d = static_pivot(L[c + (i64)c * ld], tau, nrep);
+            L[c + (i64)c * ld] = d;
             if (!(d != 0.0) || !isfinite(d)) {
                 *fail_col = s->fcol[k] + c;
                 free(WL); free(WU); free(grow);
