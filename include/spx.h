@@ -110,6 +110,15 @@ typedef struct spx_options {
                                * split supernode into a block outside it, or into a piece of it
                                * at least two past the group, are one work item (inner
                                * dimension summed over the pieces, one scatter); 1 = off (4) */
+    double static_pivot_eps;  /* SPX_LDLT and SPX_LU (Section III's static pivoting: no row or
+                               * column exchange): a pivot p with |p| < eps * max|a_ij| (over
+                               * the entries read) is replaced by +eps * max|a_ij| with the sign
+                               * of p (+ for p = 0) and counted in spx_info.pivots_replaced;
+                               * 0: no replacement (a zero or non-finite pivot is SPX_ENOTPD);
+                               * -1 (default): sqrt of the unit roundoff of the factor's
+                               * precision (2^-26.5 for SPX_FP64, 2^-12 for the FP32-storage
+                               * modes).  A non-finite pivot is never replaced.  Ignored by
+                               * SPX_LLT. */
 } spx_options;
 
 typedef struct spx_info {
@@ -139,6 +148,8 @@ typedef struct spx_info {
     int32_t nneg;             /* SPX_LDLT: negative pivots (the inertia's negative count;
                                * sign det A = (-1)^nneg); SPX_LU: negative u_jj (sign det
                                * A = (-1)^nneg); 0 for SPX_LLT */
+    int32_t pivots_replaced;  /* SPX_LDLT, SPX_LU: pivots replaced by static pivoting in the
+                               * last factorization (see static_pivot_eps) */
 } spx_info;
 
 typedef struct spx_solve_info {

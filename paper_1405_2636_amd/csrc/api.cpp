@@ -49,6 +49,7 @@ hipError_t launch_residual(const int64_t* rptr, const int32_t* rcol, const doubl
                            const double* b, int64_t ldb, double* r, int32_t n, int32_t nrhs,
                            unsigned long long* stats, hipStream_t s);
 hipError_t launch_gather(double* rv, const double* vals, const int64_t* idx, int64_t m, hipStream_t s);
+hipError_t launch_absmax(const int64_t* amap, const double* values, int64_t nnz, int32_t* status, hipStream_t s);
 hipError_t scratch_region(void** ptr, size_t* bytes);
 
 struct DeviceError : std::runtime_error {
@@ -148,6 +149,7 @@ struct spx_handle {
     bool logdet_valid = false;
     double logdet = 0.0;
     int32_t nneg = 0;   // L D L^T: negative pivots
+    int32_t nrep = 0;   // L D L^T, L U: pivots replaced by static pivoting (last factorization)
     double factor_ms = 0.0, assemble_ms = 0.0;
     // solve work (internal buffers, n x nrhs_cap) and the captured sweep graph
     DevBuf<double> y, zv, xv, tacc, xw, rw, dw, bw;
@@ -668,6 +670,7 @@ void factor_part(spx_handle* h, int part, hipStream_t s)
     else HIPCHK(launch_fill_f64(h->panels.p, h->panel_count(), 0.0, s));
     HIPCHK(launch_assemble(h->panel_ptr(), f32, h->amap.p, h->vals.p, h->nnz, s));
     HIPCHK(launch_gather(h->rv.p, h->vals.p, h->rval.p, nsym, s));
+    if (h->opt.method != SPX_LLT) HIPCHK(launch_absmax(h->amap.p, h->vals.p, h->nnz, h->status.p, s));
     HIPCHK(launch_sched_init(a, h->ready.p, h->nready, h->nready_hp, h->fact_dep0.p, P.ncblk, s));
 }
 
@@ -679,6 +682,7 @@ SchedArgs sched_args(spx_handle* h)
     a.dinv = h->dinv_ptr();
     a.split = h->opt.precision == SPX_BF16X3_IR ? 1 : 0;
     a.ldlt = h->ldlt() ? 1 : 0;
+    a.pivot_eps = h->opt.method != SPX_LLT ? h->opt.static_pivot_eps : 0.0;
     a.upanel = h->lu() ? h->plan.panel_entries : 0;
     a.uinv = h->lu() ? h->dinv_size : 0;
     a.desc = h->desc.p;
@@ -732,6 +736,7 @@ void run_factorization(spx_handle* h, hipStream_t s)
     HIPCHK(hipMemcpyAsync(sw, h->status.p, sizeof sw, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const int32_t st[3] = {sw[kStFail], sw[kStAbort], sw[kStDone]};
+    h->nrep = sw[kStReplaced];
     float ms0 = 0.f, ms1 = 0.f;
     HIPCHK(hipEventElapsedTime(&ms0, h->ev[0], h->ev[1]));
     HIPCHK(hipEventElapsedTime(&ms1, h->ev[1], h->ev[2]));
@@ -820,6 +825,7 @@ void spx_default_options(spx_options* o)
     o->tile = 0;
     o->fuse_small = 1;
     o->merge_split = 4;
+    o->static_pivot_eps = -1.0;
 }
 
 int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const spx_options* opt, spx_handle** out)
@@ -851,6 +857,10 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
         if (h->opt.ir_max_iter == -1) h->opt.ir_max_iter = h->opt.precision == SPX_FP64 ? 2 : 10;
         if (h->opt.tile != 0 && h->opt.tile != 1) throw InvalidArgument("tile must be 0 or 1");
         if (h->opt.merge_split < 1 || h->opt.merge_split > 16) throw InvalidArgument("merge_split must be in 1..16");
+        if (!(h->opt.static_pivot_eps >= 0.0 || h->opt.static_pivot_eps == -1.0) || h->opt.static_pivot_eps >= 1.0)
+            throw InvalidArgument("static_pivot_eps must be -1 (the default) or in [0, 1)");
+        if (h->opt.static_pivot_eps == -1.0)   // sqrt of the unit roundoff of the factor's precision
+            h->opt.static_pivot_eps = h->opt.precision == SPX_FP64 ? std::sqrt(std::ldexp(1.0, -53)) : std::ldexp(1.0, -12);
         h->tile_rows = h->opt.tile == 1 ? 128 : 256;
         h->tile_cols = h->opt.tile == 1 ? 128 : 64;
         Options o;
@@ -1158,6 +1168,7 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
         o.factorized = h->factorized ? 1 : 0;
         o.logdet = h->logdet_valid ? h->logdet : 0.0;
         o.nneg = h->logdet_valid ? h->nneg : 0;
+        o.pivots_replaced = h->factorized ? h->nrep : 0;
         o.factor_kernel_ms = h->factor_ms;
         o.assemble_ms = h->assemble_ms;
         o.tile_rows = h->tile_rows;

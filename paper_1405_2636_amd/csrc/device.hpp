@@ -63,7 +63,9 @@ struct SchedArgs {
     int32_t* hp_queue;
     int32_t* hp_head;
     int32_t* hp_tail;
-    int32_t* status;        // [kStFail] smallest failing column, [kStAbort] abort flag, [kStDone] items done
+    int32_t* status;        // [kStFail] smallest failing column, [kStAbort] abort flag, [kStDone] items done,
+                            // [kStReplaced] pivots replaced (static pivoting), [kStAmax] max |a_ij| (2 words)
+    double pivot_eps;       // L D L^T, L U: replace pivots below pivot_eps * max |a_ij| (0: off)
     int64_t timeout_ticks;  // wall-clock ticks a worker may wait for work
     int64_t* trace;         // optional: 4 words per item {claimed, started, finished, hw id}
 };
@@ -91,8 +93,9 @@ struct SweepArgs {
 // polls the queue heads and the abort flag, and a shared line would put the
 // polls in the way of the claims.
 constexpr int kCtrStride = 64;                 // int32 words between counters
-constexpr int kStFail = 0, kStAbort = kCtrStride, kStDone = 2 * kCtrStride;
-constexpr int kStatusWords = 3 * kCtrStride;
+constexpr int kStFail = 0, kStAbort = kCtrStride, kStDone = 2 * kCtrStride, kStReplaced = 3 * kCtrStride,
+              kStAmax = 4 * kCtrStride;
+constexpr int kStatusWords = 5 * kCtrStride;
 
 // Column blocks factored as one fused item: width <= kNB, at most
 // kSmallRows panel rows, at most kSmallMaxUpd update tiles and kSmallMap

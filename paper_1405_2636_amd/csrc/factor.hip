@@ -435,7 +435,8 @@ __device__ __forceinline__ void wave_store(const typename MM<T>::acc (&acc)[NB][
 // t / d (d itself on the diagonal); on the identity rows the same steps give
 // Y = D^{-1} L^{-1}.  Out: L (unit, d on the diagonal) in Lt, Y in Dt.
 template <class T, int NC = 32, bool LDL = false>
-__device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb, int col0, int32_t* status)
+__device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb, int col0, int32_t* status,
+                                           double thr = 0.0)
 {
     static_assert(NC == 8 || NC == 16 || NC == 32, "tile width");
     const int lane = threadIdx.x & 63;
@@ -451,9 +452,14 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
     // two Newton-Raphson steps y <- y (3 - d y^2) / 2, s = d inv (a short
     // dependency chain; within a few ulps of the rounded values)
     int fail = 32;
+    int nrep = 0;   // (L D L^T) pivots replaced by the static pivoting threshold thr
     auto pivot = [&](int c, double& s, double& inv) {
-        const double d = readlane_d(v[c], c);
+        double d = readlane_d(v[c], c);
         if constexpr (LDL) {
+            if (c < jb && fabs(d) < thr) {
+                d = d < 0.0 ? -thr : thr;
+                ++nrep;
+            }
             // 1/d from the hardware estimate and two Newton-Raphson steps
             double y = __builtin_amdgcn_rcp(d);
             y = y * __builtin_fma(-d, y, 2.0);
@@ -507,6 +513,7 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
         fail = m ? __builtin_ctzll(m) : 32;
     }
     if (lane == 0 && fail < jb) atomicMin(status, col0 + fail);
+    if (LDL && lane == 0 && nrep > 0) atomicAdd(status + kStReplaced, nrep);
     if (r < NC && !upper) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) Lt[r + c * 33] = c <= r ? v[c] : 0.0;
@@ -634,6 +641,10 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
     __shared__ int s_next;   // next trailing tile to deal
     __shared__ double dcur[kNB];   // (L D L^T) this step's pivots
     bool ready = false;      // Lt/Dt already hold this step's factored tile
+    // (L D L^T) static pivoting threshold
+    const double thr = LDL && a.pivot_eps > 0.0
+                           ? a.pivot_eps * __longlong_as_double(*reinterpret_cast<const long long*>(a.status + kStAmax))
+                           : 0.0;
     for (int J = 0; J < w; J += kNB) {
         const int jb = min(kNB, w - J);
         const int R = w - J - jb;   // rows below the tile inside the block
@@ -646,7 +657,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                                                     : (r == c ? 1.0 : 0.0);
             }
             __syncthreads();
-            if (wave == 0) tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jb, f + J, a.status);
+            if (wave == 0) tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jb, f + J, a.status, thr);
         }
         if (tid == 0) s_next = 0;
         __syncthreads();
@@ -734,7 +745,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                         ldx, ldyd, mv, nv, cA, [&](int r, int c) { return r >= c; }, sub, [&](int r, int c, T v) {
                             if (r < jn && c < jn && c <= r) Lt[r + c * 33] = (double)v;
                         });
-                    tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jn, f + J + jb, a.status);
+                    tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jn, f + J + jb, a.status, thr);
                 } else {
                     wave_mm_rmw<2, T>(
                         ldx, ldyd, mv, nv, cA, [&](int r, int c) { return i0 + r >= c0 + c; }, sub,
@@ -782,7 +793,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
 // non-finite pivot among the first jb records its column with atomicMin.
 template <class T>
 __device__ __noinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, int ldy, int jb, int col0,
-                                         int32_t* status)
+                                         int32_t* status, double thr)
 {
     const int lane = threadIdx.x & 63;
     const int r = lane & 31;
@@ -790,9 +801,15 @@ __device__ __noinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, i
     double v[32], invp[32];   // invp: the inverse pivots (uniform), for pass 2
 #pragma unroll
     for (int c = 0; c < 32; ++c) v[c] = colh ? Lt[c + r * 33] : Lt[r + c * 33];
+    int nrep = 0;
 #pragma unroll
     for (int c = 0; c < 32; ++c) {
-        const double d = readlane_d(v[c], c);   // row lane c: u_cc
+        double d = readlane_d(v[c], c);   // row lane c: u_cc
+        if (c < jb && fabs(d) < thr) {     // static pivoting: the pivot replaced in both copies
+            d = d < 0.0 ? -thr : thr;
+            if (r == c) v[c] = d;
+            ++nrep;
+        }
         double y = __builtin_amdgcn_rcp(d);
         y = y * __builtin_fma(-d, y, 2.0);
         y = y * __builtin_fma(-d, y, 2.0);
@@ -821,6 +838,7 @@ __device__ __noinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, i
     const bool bad = !colh && r < jb && !(dd != 0.0 && dd - dd == 0.0);
     const uint64_t m = __ballot(bad);
     if (lane == 0 && m) atomicMin(status, col0 + (int)__builtin_ctzll(m));
+    if (lane == 0 && nrep > 0) atomicAdd(status + kStReplaced, nrep);
     if (!colh) {
 #pragma unroll
         for (int c = 0; c < 32; ++c) Lt[r + c * 33] = v[c];
@@ -886,6 +904,9 @@ __device__ __noinline__ void task_fact_lu(const SchedArgs& a, int k, double* Lt,
     double* bc = Lt + kNB * 33;
     __shared__ int s_next;
     bool ready = false;
+    const double thr = a.pivot_eps > 0.0
+                           ? a.pivot_eps * __longlong_as_double(*reinterpret_cast<const long long*>(a.status + kStAmax))
+                           : 0.0;
     for (int J = 0; J < w; J += kNB) {
         const int jb = min(kNB, w - J);
         const int R = w - J - jb;
@@ -895,7 +916,7 @@ __device__ __noinline__ void task_fact_lu(const SchedArgs& a, int k, double* Lt,
                 Lt[r + c * 33] = (r < jb && c < jb) ? (double)A[(J + r) + (int64_t)(J + c) * ld] : (r == c ? 1.0 : 0.0);
             }
             __syncthreads();
-            if (wave == 0) tile_lu_inv<T>(Lt, bc, Dt, Y + J + (int64_t)J * w, w, jb, f + J, a.status);
+            if (wave == 0) tile_lu_inv<T>(Lt, bc, Dt, Y + J + (int64_t)J * w, w, jb, f + J, a.status, thr);
         }
         if (tid == 0) s_next = 0;
         __syncthreads();
@@ -984,7 +1005,7 @@ __device__ __noinline__ void task_fact_lu(const SchedArgs& a, int k, double* Lt,
                         ldx, ldq, mv, nv, cA, [](int, int) { return true; }, sub, [&](int r, int c, T v) {
                             if (r < jn && c < jn) Lt[r + c * 33] = (double)v;
                         });
-                    tile_lu_inv<T>(Lt, bc, Dt, Y + (J + jb) + (int64_t)(J + jb) * w, w, jn, f + J + jb, a.status);
+                    tile_lu_inv<T>(Lt, bc, Dt, Y + (J + jb) + (int64_t)(J + jb) * w, w, jn, f + J + jb, a.status, thr);
                 } else {
                     wave_mm_rmw<2, T>(ldx, ldq, mv, nv, cA, [](int, int) { return true; }, sub, [](int, int, T) {});
                 }
@@ -1452,6 +1473,39 @@ __global__ void assemble_kernel(T* panels, const int64_t* amap, const double* va
     }
 }
 
+// max |values[p]| over the entries the factorization reads (amap[p] >= 0),
+// into two status words as the bits of a non-negative double (ordered like
+// the doubles; a NaN value counts as larger than every number)
+__global__ void absmax_kernel(const int64_t* amap, const double* values, int64_t nnz, int32_t* status)
+{
+    unsigned long long m = 0;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+        if (amap[p] >= 0) {
+            const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(values[p]));
+            m = b > m ? b : m;
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(reinterpret_cast<unsigned long long*>(status + kStAmax), m);
+}
+
+__global__ void zero_amax_kernel(int32_t* status)
+{
+    if (threadIdx.x < 2) status[kStAmax + threadIdx.x] = 0;
+}
+
+hipError_t launch_absmax(const int64_t* amap, const double* values, int64_t nnz, int32_t* status, hipStream_t s)
+{
+    zero_amax_kernel<<<1, 64, 0, s>>>(status);
+    if (nnz > 0) {
+        const int blocks = (int)std::min<int64_t>((nnz + 255) / 256, 2048);
+        absmax_kernel<<<blocks, 256, 0, s>>>(amap, values, nnz, status);
+    }
+    return hipGetLastError();
+}
+
 // queues and counters of one factorization: the ready FACT items are the
 // first entries of their queues (ready[0..nready_hp) high priority, the rest
 // normal)
@@ -1475,6 +1529,7 @@ __global__ void sched_init(SchedArgs a, const int32_t* ready, int32_t nready, in
         a.status[kStFail] = 0x7fffffff;
         a.status[kStAbort] = 0;
         a.status[kStDone] = 0;
+        a.status[kStReplaced] = 0;
     }
 }
 

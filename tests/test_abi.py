@@ -57,7 +57,8 @@ def test_bad_options():
         Solver(p.n, p.colptr, p.rowind, split_width=300)
     with pytest.raises(SpxError):
         Solver(p.n, p.colptr, p.rowind, user_perm=np.zeros(p.n, np.int32))
-    for kw in [dict(merge_split=0), dict(merge_split=17), dict(tile=2)]:
+    for kw in [dict(merge_split=0), dict(merge_split=17), dict(tile=2), dict(static_pivot_eps=1.0),
+               dict(static_pivot_eps=-0.5), dict(static_pivot_eps=float("nan"))]:
         with pytest.raises(SpxError):
             Solver(p.n, p.colptr, p.rowind, **kw)
     with pytest.raises(ValueError):
@@ -79,7 +80,9 @@ def test_bad_options():
     L = spx.load_library()
     opt = spx.Options()
     L.spx_default_options(C.byref(opt))
-    assert opt.method == 0
+    assert opt.method == 0 and opt.static_pivot_eps == -1.0
+    Solver(p.n, p.colptr, p.rowind, method="lu", static_pivot_eps=0.0)
+    Solver(p.n, p.colptr, p.rowind, method="ldlt", static_pivot_eps=1e-3)
     opt.method = 3
     h = C.c_void_p()
     assert L.spx_analyze(p.n, p.colptr.ctypes.data, p.rowind.ctypes.data, C.byref(opt), C.byref(h)) == -1

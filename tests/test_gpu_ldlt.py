@@ -126,7 +126,7 @@ def test_ldlt_zero_pivot(orc, torch):
         sym = orc.analyze(2, colptr, rowind)
         with pytest.raises(orc.ZeroPivot) as eo:
             orc.factor_ldlt(sym, colptr, rowind, vals)
-        s = Solver(2, colptr, rowind, method="ldlt")
+        s = Solver(2, colptr, rowind, method="ldlt", static_pivot_eps=0)
         with pytest.raises(NotPositiveDefinite) as eg:
             s.factorize(torch.tensor(vals, device="cuda"))
         assert eg.value.col == eo.value.col_orig

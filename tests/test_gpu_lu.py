@@ -151,7 +151,7 @@ def test_lu_zero_pivot(orc, torch):
     rowind = np.array([0, 1, 0, 1], np.int32)
     # [[1, 2], [3, 6]]: the second pivot is 6 - 3 * 2 = 0
     vals = np.array([1.0, 3.0, 2.0, 6.0])
-    s = Solver(2, colptr, rowind, method="lu")
+    s = Solver(2, colptr, rowind, method="lu", static_pivot_eps=0)
     with pytest.raises(NotPositiveDefinite) as e:
         s.factorize(torch.tensor(vals, device="cuda"))
     sym = orc.analyze(2, colptr, rowind)

@@ -11,70 +11,27 @@ zero pivots.  A pivot of exactly 2 tau is kept.  eps is a power of two and
 max |a_ij| an integer, so tau is exact."""
 import numpy as np
 import pytest
-import scipy.sparse as sp
 
-from gen.stencils import Problem
+from planted import dense_problem, planted_ldlt, planted_lu, unpack
 
 EPS = 2.0 ** -26
 ZEROS = (10, 35)
 N = 60
 
 
-def _problem(A):
-    """A dense pattern (zeros kept as entries): the elimination tree is a
-    path, so with the identity ordering the final order is the identity."""
-    n = A.shape[0]
-    colptr = np.arange(0, n * n + 1, n, dtype=np.int64)
-    rowind = np.tile(np.arange(n, dtype=np.int32), n)
-    return Problem(n, colptr, rowind, np.asfortranarray(A).ravel(order="F").copy())
-
-
-def _unit_lower(rng, n, zero_cols):
-    L0 = np.eye(n)
-    for c in range(n):
-        if c in zero_cols:
-            continue
-        rows = rng.choice(np.arange(c + 1, n), size=min(3, n - c - 1), replace=False) if c < n - 1 else []
-        for r in rows:
-            L0[r, c] = float(rng.integers(-2, 3))
-    return L0
-
-
-def _unpack(sym, P, n):
-    """Dense lower panel contents (diagonal blocks square) in the final order."""
-    a = sym.arrays
-    F = np.zeros((n, n))
-    for k in range(len(a["fcol"])):
-        f, l, ld, off = int(a["fcol"][k]), int(a["lcol"][k]), int(a["stride"][k]), int(a["panel_off"][k])
-        wd = l - f + 1
-        blk = P[off:off + ld * wd].reshape(wd, ld).T
-        F[f:f + wd, f:f + wd] = blk[:wd]
-        rows = []
-        for b in range(int(a["bptr"][k]) + 1, int(a["bptr"][k + 1])):
-            rows.extend(range(int(a["frow"][b]), int(a["lrow"][b]) + 1))
-        if rows:
-            F[np.array(rows), f:f + wd] = blk[wd:]
-    return F
-
-
 def test_ldlt_replaces_planted_zero_pivots(orc):
-    rng = np.random.default_rng(3)
-    L0 = _unit_lower(rng, N, ZEROS)
-    d0 = rng.choice([-1.0, 1.0, 2.0], size=N)
-    for z in ZEROS:
-        d0[z] = 0.0
-    A = L0 @ np.diag(d0) @ L0.T
+    A, L0, d0 = planted_ldlt(N, ZEROS, 3)
     amax = np.max(np.abs(np.tril(A)))
     tau = EPS * amax
     d0[5] = 2 * tau                 # exactly twice the threshold: kept
     A = L0 @ np.diag(d0) @ L0.T     # (changes only a_55; still integers elsewhere, amax unchanged)
     assert np.max(np.abs(np.tril(A))) == amax
-    p = _problem(A)
+    p = dense_problem(A)
     sym = orc.analyze(p.n, p.colptr, p.rowind, user_perm=np.arange(N))
     assert np.array_equal(sym.perm, np.arange(N))
     P, nrep = orc.factor_ldlt(sym, p.colptr, p.rowind, p.values, pivot_eps=EPS, return_nrep=True)
     assert nrep == len(ZEROS)
-    F = _unpack(sym, P, N)
+    F = unpack(sym, P, N)
     d = np.diag(F).copy()
     dref = d0.copy()
     for z in ZEROS:
@@ -91,22 +48,16 @@ def test_ldlt_replaces_planted_zero_pivots(orc):
 
 
 def test_lu_replaces_planted_zero_pivots(orc):
-    rng = np.random.default_rng(4)
-    L0 = _unit_lower(rng, N, ZEROS)
-    U0t = _unit_lower(rng, N, ZEROS)            # strict part of U0^T: rows of U0 zero beyond planted pivots
-    u = rng.choice([-3.0, 1.0, 2.0], size=N)
-    for z in ZEROS:
-        u[z] = 0.0
-    U0 = np.diag(u) @ U0t.T
-    A = L0 @ U0
+    A, L0, U0 = planted_lu(N, ZEROS, 4)
+    u = np.diag(U0).copy()
     amax = np.max(np.abs(A))
     tau = EPS * amax
-    p = _problem(A)
+    p = dense_problem(A)
     sym = orc.analyze(p.n, p.colptr, p.rowind, user_perm=np.arange(N))
     assert np.array_equal(sym.perm, np.arange(N))
     PL, PU, nrep = orc.factor_lu(sym, p.colptr, p.rowind, p.values, pivot_eps=EPS, return_nrep=True)
     assert nrep == len(ZEROS)
-    FL, FU = _unpack(sym, PL, N), _unpack(sym, PU, N)
+    FL, FU = unpack(sym, PL, N), unpack(sym, PU, N)
     Lc = np.tril(FL, -1) + np.eye(N)
     Uc = np.triu(FL) + np.tril(FU, -1).T
     uref = u.copy()
