@@ -119,6 +119,14 @@ typedef struct spx_options {
                                * precision (2^-26.5 for SPX_FP64, 2^-12 for the FP32-storage
                                * modes).  A non-finite pivot is never replaced.  Ignored by
                                * SPX_LLT. */
+    int32_t deterministic;    /* 1: the updates into one column block are applied in ascending
+                               * order of their source block (Section III: the runtimes
+                               * serialize the tasks writing one panel; here the order is
+                               * fixed), so the factor is the same bit for bit on every run
+                               * of one analysis; fused small items are off in this mode.
+                               * 0 (default): concurrent updates into one block in any order
+                               * (FP64 atomics; factors agree to rounding).  The solve's
+                               * scatter is in any order in both modes. */
 } spx_options;
 
 typedef struct spx_info {

@@ -135,6 +135,10 @@ struct spx_handle {
     DevBuf<int32_t> trsm_first, trsm_count, upd_first, upd_hp, upd_count, hp_cblk, fact_dep0, fact_dep, trsm_left,
         queue, hp_queue, ready, qctr, status;
     DevBuf<int4> ftab;
+    // deterministic mode: update pairs (see SchedArgs)
+    int32_t npair = 0, ubase = 0;
+    DevBuf<int32_t> upair, kpair, pdep0, pdep, pleft;
+    DevBuf<int4> pairs;
     DevBuf<int64_t> trace;   // per-item task trace, allocated when the trace option is on
     // levels for the sweeps
     Level lv;
@@ -389,7 +393,14 @@ void build_tasks(spx_handle* h)
     int64_t nhp_upd = 0;
     std::vector<int4> ftab;   // update tiles of the fused blocks
     std::vector<int32_t> grow;
+    // deterministic mode: the update items of one (source, target) pair are
+    // consecutive; pairs into one target are chained in ascending source order
+    const bool det = h->opt.deterministic != 0;
+    const int32_t ubase = id;
+    std::vector<int4> pairs;
+    std::vector<int32_t> kpair(static_cast<size_t>(nc) + 1, 0), pdep0, upair, plast(nc, -1);
     for (int32_t k = 0; k < nc; ++k) {
+        kpair[k] = static_cast<int32_t>(pairs.size());
         const int32_t ld = P.stride[k];
         // global row of every panel row of k
         grow.assign(static_cast<size_t>(ld), 0);
@@ -424,6 +435,7 @@ void build_tasks(spx_handle* h)
             const int32_t mbase = static_cast<int32_t>(moff - rs);
             const bool thin = chain[k] && first_pair && !small[k];
             const int32_t ttr = thin ? 64 : h->tile_rows, ttc = thin ? 64 : h->tile_cols;
+            const int32_t pfirst = id;
             for_tiles(k, b, b2, ttr, ttc, [&](int32_t r0, int32_t mr, int32_t c0, int32_t ncl) {
                 ++dep[j];
                 if (small[k]) {
@@ -438,6 +450,14 @@ void build_tasks(spx_handle* h)
                 ++id;
                 if (first_pair && hp[k]) ++uh[k];
             });
+            if (det && id > pfirst) {
+                const int32_t pi = static_cast<int32_t>(pairs.size());
+                pairs.push_back(int4{pfirst, id - pfirst, -1, first_pair && hp[k] ? 1 : 0});
+                pdep0.push_back(plast[j] >= 0 ? 2 : 1);
+                if (plast[j] >= 0) pairs[static_cast<size_t>(plast[j])].z = pi;
+                plast[j] = pi;
+                upair.resize(static_cast<size_t>(id - ubase), pi);
+            }
             first_pair = false;
             b = b2;
         }
@@ -449,7 +469,20 @@ void build_tasks(spx_handle* h)
                 int4{ftile0, nt, static_cast<int32_t>(mstart), static_cast<int32_t>(rmap.size() - mstart)};
         }
     }
+    kpair[nc] = static_cast<int32_t>(pairs.size());
     h->total = id;
+    h->npair = static_cast<int32_t>(pairs.size());
+    h->ubase = ubase;
+    if (det) {
+        if (nsmall > 0) throw std::runtime_error("fused small items in the deterministic mode");
+        if (static_cast<int64_t>(upair.size()) != id - ubase) throw std::runtime_error("update items outside pairs");
+        h->pairs.upload(pairs);
+        h->kpair.upload(kpair);
+        h->pdep0.upload(pdep0);
+        h->upair.upload(upair);
+        h->pdep.alloc(pairs.size());
+        h->pleft.alloc(pairs.size());
+    }
     h->nsmall = nsmall;
     h->nfused_tiles = static_cast<int32_t>(ftab.size() / 3);
     int64_t hp_items = nhp_upd;
@@ -707,6 +740,14 @@ SchedArgs sched_args(spx_handle* h)
     a.status = h->status.p;
     a.timeout_ticks = h->timeout_ticks;
     a.trace = h->opt.trace ? h->trace.p : nullptr;
+    a.npair = h->npair;
+    a.ubase = h->ubase;
+    a.upair = h->upair.p;
+    a.kpair = h->kpair.p;
+    a.pairs = h->pairs.p;
+    a.pdep0 = h->pdep0.p;
+    a.pdep = h->pdep.p;
+    a.pleft = h->pleft.p;
     return a;
 }
 
@@ -826,6 +867,7 @@ void spx_default_options(spx_options* o)
     o->fuse_small = 1;
     o->merge_split = 4;
     o->static_pivot_eps = -1.0;
+    o->deterministic = 0;
 }
 
 int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const spx_options* opt, spx_handle** out)
@@ -844,6 +886,8 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
         if (h->opt.method != SPX_LLT && h->opt.method != SPX_LDLT && h->opt.method != SPX_LU)
             throw InvalidArgument("unsupported method");
         if (h->opt.method == SPX_LU) h->opt.fuse_small = 0;   // every column block a FACT / TRSM / UPDATE sequence
+        if (h->opt.deterministic != 0 && h->opt.deterministic != 1) throw InvalidArgument("deterministic must be 0 or 1");
+        if (h->opt.deterministic) h->opt.fuse_small = 0;   // fused items scatter into several targets at once
         if (h->opt.method == SPX_LDLT) {
             // L D L^T: FP64 factor; every column block is a FACT / TRSM /
             // UPDATE sequence (no fused small items; merged updates apply

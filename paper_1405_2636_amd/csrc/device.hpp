@@ -66,6 +66,17 @@ struct SchedArgs {
     int32_t* status;        // [kStFail] smallest failing column, [kStAbort] abort flag, [kStDone] items done,
                             // [kStReplaced] pivots replaced (static pivoting), [kStAmax] max |a_ij| (2 words)
     double pivot_eps;       // L D L^T, L U: replace pivots below pivot_eps * max |a_ij| (0: off)
+    // Deterministic mode (npair > 0): the update items of one (source,
+    // target) pair are released when the source's panel solves are done and
+    // the previous pair into the same target (ascending source) has finished.
+    int32_t npair;          // update pairs (0: any-order mode)
+    int32_t ubase;          // id of the first update item
+    const int32_t* upair;   // pair of update item ubase + i
+    const int32_t* kpair;   // pairs of source k: kpair[k] .. kpair[k + 1] - 1
+    const int4* pairs;      // {first item, item count, next pair into the same target (-1: none), high priority}
+    const int32_t* pdep0;   // initial pair dependency counts (1, or 2 with a previous pair)
+    int32_t* pdep;          // pair dependency counters
+    int32_t* pleft;         // unfinished items per pair
     int64_t timeout_ticks;  // wall-clock ticks a worker may wait for work
     int64_t* trace;         // optional: 4 words per item {claimed, started, finished, hw id}
 };

@@ -1167,6 +1167,22 @@ __device__ __forceinline__ void push_items(const SchedArgs& a, bool hp, int base
     }
 }
 
+// Deterministic mode: queue the items of pair p (one thread).
+__device__ __forceinline__ void push_pair(const SchedArgs& a, int p)
+{
+    const int4 q = a.pairs[p];
+    const bool hp = q.w != 0;
+    int32_t* qu = hp ? a.hp_queue : a.queue;
+    const int cap = hp ? a.hp_total : a.total_normal;
+    const int base = __hip_atomic_fetch_add(hp ? a.hp_tail : a.qtail, q.y, __ATOMIC_RELAXED, AGENT);
+    for (int i = 0; i < q.y; ++i) {
+        if (base + i < cap)
+            __hip_atomic_store(&qu[base + i], q.x + i, __ATOMIC_RELAXED, AGENT);
+        else
+            __hip_atomic_store(&a.status[kStAbort], 2, __ATOMIC_RELAXED, AGENT);
+    }
+}
+
 // Count down one update tile of target j (any lane); queue j when it was the
 // last one.
 __device__ __forceinline__ void finish_update(const SchedArgs& a, int j)
@@ -1313,6 +1329,7 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
     __shared__ int rpos[256], cpos[128];
     __shared__ int s_item;
     __shared__ int s_push[6];   // {hp first, hp count, hp base, normal first, normal count, normal base}
+    __shared__ int s_rel;       // deterministic mode: source whose update pairs lose one dependency
     __shared__ int64_t s_t0, s_t1;
     const int tid = threadIdx.x;
     // Tickets of the two FIFO queues held by this worker and not yet served
@@ -1324,6 +1341,7 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
     // Items served by this worker are counted in a register and added to the
     // done count once, at exit.
     int my_slot = -1, hp_slot = -1, ndone = 0;
+    if (tid == 0) s_rel = -1;
     for (;;) {
         if (tid == 0) {
             int item = -1;
@@ -1417,15 +1435,32 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
                 }
             } else if (kind == kTrsm) {
                 if (__hip_atomic_fetch_add(&a.trsm_left[d0.y], -1, __ATOMIC_RELAXED, AGENT) == 1) {
-                    hf = a.upd_first[d0.y];
-                    hc = a.upd_hp[d0.y];
-                    nf = hf + hc;
-                    nc = a.upd_count[d0.y] - hc;
+                    if (a.npair > 0) {
+                        s_rel = d0.y;   // its pairs, below
+                    } else {
+                        hf = a.upd_first[d0.y];
+                        hc = a.upd_hp[d0.y];
+                        nf = hf + hc;
+                        nc = a.upd_count[d0.y] - hc;
+                    }
                 }
             } else if (kind == kUpdate) {
                 if (__hip_atomic_fetch_add(&a.fact_dep[d0.z], -1, __ATOMIC_RELAXED, AGENT) == 1) {
                     if (a.hp_cblk[d0.z]) { hf = d0.z; hc = 1; }
                     else { nf = d0.z; nc = 1; }
+                }
+                if (a.npair > 0) {
+                    // the pair's last item releases the next pair into the
+                    // same target (which then cannot have released the target)
+                    const int p = a.upair[item - a.ubase];
+                    if (__hip_atomic_fetch_add(&a.pleft[p], -1, __ATOMIC_RELAXED, AGENT) == 1) {
+                        const int4 q = a.pairs[p];
+                        if (q.z >= 0 && __hip_atomic_fetch_add(&a.pdep[q.z], -1, __ATOMIC_RELAXED, AGENT) == 1) {
+                            const int4 r = a.pairs[q.z];
+                            if (r.w) { hf = r.x; hc = r.y; }
+                            else { nf = r.x; nc = r.y; }
+                        }
+                    }
                 }
             }
             s_push[0] = hf;
@@ -1446,7 +1481,12 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         __syncthreads();
         if (s_push[1] > 0) push_items(a, true, s_push[2], s_push[0], s_push[1]);
         if (s_push[4] > 0) push_items(a, false, s_push[5], s_push[3], s_push[4]);
+        if (s_rel >= 0) {   // deterministic mode: the source's pairs lose their panel dependency
+            for (int p = a.kpair[s_rel] + tid; p < a.kpair[s_rel + 1]; p += kThreads)
+                if (__hip_atomic_fetch_add(&a.pdep[p], -1, __ATOMIC_RELAXED, AGENT) == 1) push_pair(a, p);
+        }
         __syncthreads();
+        if (tid == 0) s_rel = -1;
     }
 }
 
@@ -1520,6 +1560,10 @@ __global__ void sched_init(SchedArgs a, const int32_t* ready, int32_t nready, in
     for (int64_t i = t; i < ncblk; i += stride) {
         a.fact_dep[i] = fact_dep0[i];
         a.trsm_left[i] = a.trsm_count[i];
+    }
+    for (int64_t i = t; i < a.npair; i += stride) {
+        a.pdep[i] = a.pdep0[i];
+        a.pleft[i] = a.pairs[i].y;
     }
     if (t == 0) {
         *a.qhead = 0;
@@ -1604,7 +1648,7 @@ hipError_t launch_widen(double* dst, const float* src, int64_t n, hipStream_t s)
 hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t nready, int32_t nready_hp,
                              const int32_t* fact_dep0, int32_t ncblk, hipStream_t s)
 {
-    const int64_t n = std::max<int64_t>(std::max<int64_t>(a.total_normal, a.hp_total), ncblk);
+    const int64_t n = std::max<int64_t>(std::max<int64_t>(a.total_normal, a.hp_total), std::max(ncblk, a.npair));
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
     sched_init<<<blocks, 256, 0, s>>>(a, ready, nready, nready_hp, fact_dep0, ncblk);
     return hipGetLastError();

@@ -44,7 +44,8 @@ class Options(C.Structure):
                 ("split_width", C.c_int32), ("user_perm", C.c_void_p), ("precision", C.c_int32),
                 ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double), ("trace", C.c_int32),
                 ("graph", C.c_int32), ("tune", C.c_int32), ("tile", C.c_int32), ("fuse_small", C.c_int32),
-                ("merge_split", C.c_int32), ("static_pivot_eps", C.c_double)]
+                ("merge_split", C.c_int32), ("static_pivot_eps", C.c_double),
+                ("deterministic", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -151,11 +152,13 @@ class Solver:
     the factor precision's unit roundoff), 0 = no replacement (a zero pivot
     is an error), else pivots below eps * max|a_ij| in magnitude are replaced
     (count in info()["pivots_replaced"]).
+    deterministic: updates into each column block in ascending source order
+    (the factor is reproducible bit for bit; fused small items off).
     """
 
     def __init__(self, n, colptr, rowind, leaf_size=64, amalg_pct=12, split_width=256, user_perm=None,
                  precision="fp64", ir_max_iter=None, ir_tol=1e-14, trace=False, graph=False, tune=False, tile=0,
-                 fuse_small=True, merge_split=4, method="llt", static_pivot_eps=None):
+                 fuse_small=True, merge_split=4, method="llt", static_pivot_eps=None, deterministic=False):
         L = load_library()
         self._lib = L
         self.n = int(n)
@@ -164,7 +167,8 @@ class Solver:
         self.nnz = int(self._colptr[-1]) if len(self._colptr) else 0
         self.sizes = [self.n]
         opt, up = self._options(L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol,
-                                trace, graph, tune, tile, fuse_small, merge_split, method, static_pivot_eps)
+                                trace, graph, tune, tile, fuse_small, merge_split, method, static_pivot_eps,
+                                deterministic)
         h = C.c_void_p()
         rc = L.spx_analyze(self.n, self._colptr.ctypes.data, self._rowind.ctypes.data, C.byref(opt), C.byref(h))
         if rc != SPX_OK:
@@ -172,9 +176,11 @@ class Solver:
         self._h = h
 
     def _options(self, L, leaf_size, amalg_pct, split_width, user_perm, precision, ir_max_iter, ir_tol, trace,
-                 graph, tune, tile=0, fuse_small=True, merge_split=4, method="llt", static_pivot_eps=None):
+                 graph, tune, tile=0, fuse_small=True, merge_split=4, method="llt", static_pivot_eps=None,
+                 deterministic=False):
         opt = Options()
         L.spx_default_options(C.byref(opt))
+        opt.deterministic = 1 if deterministic else 0
         if static_pivot_eps is not None:
             opt.static_pivot_eps = float(static_pivot_eps)
         if method not in METHODS:
@@ -219,7 +225,8 @@ class Solver:
         opt, _ = self._options(L, kw.get("leaf_size", 64), kw.get("amalg_pct", 12), kw.get("split_width", 256),
                                None, precision, ir_max_iter, ir_tol, kw.get("trace", False), graph, tune,
                                kw.get("tile", 0), kw.get("fuse_small", True), kw.get("merge_split", 4),
-                               kw.get("method", "llt"), kw.get("static_pivot_eps"))
+                               kw.get("method", "llt"), kw.get("static_pivot_eps"),
+                               kw.get("deterministic", False))
         cpp = (C.c_void_p * len(cps))(*[c.ctypes.data for c in cps])
         rip = (C.c_void_p * len(ris))(*[r.ctypes.data for r in ris])
         h = C.c_void_p()
