@@ -58,8 +58,8 @@ enum spx_method {
     SPX_LDLT = 1,  /* P A P^T = L D L^T with unit L and diagonal D, A symmetric with
                     * non-zero pivots in the computed order (static pivoting,
                     * Section III: the structure is the one of L L^T); e.g.
-                    * quasi-definite matrices.  SPX_FP64 only; fuse_small is
-                    * ignored (treated as 0) */
+                    * quasi-definite matrices.  All precision modes (the FP32
+                    * modes refine in FP64 as for SPX_LLT) */
     SPX_LU = 2     /* P A P^T = L U with unit L, A unsymmetric with a symmetric or
                     * unsymmetric pattern (analysed on the pattern of A + A^T) and
                     * non-zero pivots in the computed order (static pivoting,

@@ -888,13 +888,6 @@ int spx_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, const s
         if (h->opt.method == SPX_LU) h->opt.fuse_small = 0;   // every column block a FACT / TRSM / UPDATE sequence
         if (h->opt.deterministic != 0 && h->opt.deterministic != 1) throw InvalidArgument("deterministic must be 0 or 1");
         if (h->opt.deterministic) h->opt.fuse_small = 0;   // fused items scatter into several targets at once
-        if (h->opt.method == SPX_LDLT) {
-            // L D L^T: FP64 factor; every column block is a FACT / TRSM /
-            // UPDATE sequence (no fused small items; merged updates apply
-            // each piece's own D)
-            if (h->opt.precision != SPX_FP64) throw InvalidArgument("SPX_LDLT requires SPX_FP64");
-            h->opt.fuse_small = 0;
-        }
         if (h->opt.precision != SPX_FP64 && h->opt.precision != SPX_FP32_IR && h->opt.precision != SPX_BF16X3_IR)
             throw InvalidArgument("unsupported precision");
         if (h->opt.ir_max_iter < -1) throw InvalidArgument("ir_max_iter must be >= 0, or -1 for the default");

@@ -165,8 +165,12 @@ __device__ __forceinline__ void gstore_s(const GOp& g, int voff, int soff, float
 // 128 accumulator registers and the operands exceed the 256 registers of a
 // wave at two workgroups per CU, and the spilled operands each cost a wait
 // for every outstanding load.
-template <int NB, class T, int RB = 4>
-__device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K)
+// DS (L D L^T updates): acc += X (Y D)^T, the facing operand Y scaled by d_p
+// (element p of Dg at p * Dg.sk: the diagonal of the source panel) just
+// before the products, so its loads stay in flight with the others.
+template <int NB, class T, int RB = 4, bool DS = false>
+__device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K,
+                                          const GOp& Dg)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -181,27 +185,30 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], co
         for (int b = 0; b < NB; ++b) yo[u][b] = Y.off + (16 * b + li) * Y.si + (4 * u + lk) * Y.sk;
     }
     const int dx = 8 * X.sk, dy = 8 * Y.sk;
-    T xa[2][RB], ya[2][NB], xb[2][RB], yb[2][NB], xc[2][RB], yc[2][NB];
+    T xa[2][RB], ya[2][NB], da[2], xb[2][RB], yb[2][NB], db[2], xc[2][RB], yc[2][NB], dc[2];
     // (scheduling barriers keep every group of loads ahead of the products
     // it is meant to overlap; left alone, the compiler sinks the FP32 loads
     // next to their uses and waits for them)
-    auto load = [&](T (&xs)[2][RB], T (&ys)[2][NB], int ch) {
+    auto load = [&](T (&xs)[2][RB], T (&ys)[2][NB], T (&ds)[2], int ch) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
 #pragma unroll
             for (int b = 0; b < RB; ++b) xs[u][b] = gload<T>(X, xo[u][b] + ch * dx);
 #pragma unroll
             for (int b = 0; b < NB; ++b) ys[u][b] = gload<T>(Y, yo[u][b] + ch * dy);
+            if constexpr (DS) ds[u] = gload<T>(Dg, Dg.off + (8 * ch + 4 * u + lk) * Dg.sk);
         }
         __builtin_amdgcn_sched_barrier(0);
     };
-    auto mma = [&](const T (&xs)[2][RB], const T (&ys)[2][NB]) {
+    auto mma = [&](const T (&xs)[2][RB], const T (&ys)[2][NB], const T (&ds)[2]) {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
-            for (int bi = 0; bi < NB; ++bi)
+            for (int bi = 0; bi < NB; ++bi) {
+                const T yv = DS ? ys[u][bi] * ds[u] : ys[u][bi];
 #pragma unroll
-                for (int bj = 0; bj < RB; ++bj) acc[bi][bj] = MM<T>::mfma(ys[u][bi], xs[u][bj], acc[bi][bj]);
+                for (int bj = 0; bj < RB; ++bj) acc[bi][bj] = MM<T>::mfma(yv, xs[u][bj], acc[bi][bj]);
+            }
         __builtin_amdgcn_sched_barrier(0);
     };
     // (reads past the last chunk repeat it and are not used)
@@ -209,29 +216,30 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], co
     if constexpr (sizeof(T) == 8) {
         (void)xc;
         (void)yc;
-        load(xa, ya, 0);
+        (void)dc;
+        load(xa, ya, da, 0);
         int ch = 0;
         for (; ch + 2 <= nchunks; ch += 2) {
-            load(xb, yb, ch + 1);
-            mma(xa, ya);
-            load(xa, ya, min(ch + 2, last));
-            mma(xb, yb);
+            load(xb, yb, db, ch + 1);
+            mma(xa, ya, da);
+            load(xa, ya, da, min(ch + 2, last));
+            mma(xb, yb, db);
         }
-        if (ch < nchunks) mma(xa, ya);
+        if (ch < nchunks) mma(xa, ya, da);
     } else {
-        load(xa, ya, 0);
-        load(xb, yb, min(1, last));
+        load(xa, ya, da, 0);
+        load(xb, yb, db, min(1, last));
         int ch = 0;
         for (; ch + 3 <= nchunks; ch += 3) {
-            load(xc, yc, min(ch + 2, last));
-            mma(xa, ya);
-            load(xa, ya, min(ch + 3, last));
-            mma(xb, yb);
-            load(xb, yb, min(ch + 4, last));
-            mma(xc, yc);
+            load(xc, yc, dc, min(ch + 2, last));
+            mma(xa, ya, da);
+            load(xa, ya, da, min(ch + 3, last));
+            mma(xb, yb, db);
+            load(xb, yb, db, min(ch + 4, last));
+            mma(xc, yc, dc);
         }
-        if (ch < nchunks) mma(xa, ya);
-        if (ch + 1 < nchunks) mma(xb, yb);
+        if (ch < nchunks) mma(xa, ya, da);
+        if (ch + 1 < nchunks) mma(xb, yb, db);
     }
 }
 
@@ -262,8 +270,10 @@ __device__ __forceinline__ void split_bf16(const float (&v)[4], s16x4& hi, s16x4
     lo = __builtin_bit_cast(s16x4, l);
 }
 
-template <int NB, int RB = 4>
-__device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][RB], const GOp& X, const GOp& Y, int K)
+// DS: the facing operand scaled by d_p in FP32 before it is split (as in
+// wave_gemm).
+template <int NB, int RB = 4, bool DS = false>
+__device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][RB], const GOp& X, const GOp& Y, int K, const GOp& Dg)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -275,25 +285,30 @@ __device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][RB], const GOp& X,
 #pragma unroll
     for (int b = 0; b < NB; ++b) yo[b] = Y.off + (16 * b + li) * Y.si + lk * Y.sk;
     const int dx = 4 * X.sk, dy = 4 * Y.sk;
-    float xa[RB][4], ya[NB][4], xb[RB][4], yb[NB][4];
-    auto load = [&](float (&xs)[RB][4], float (&ys)[NB][4], int ch) {
+    float xa[RB][4], ya[NB][4], da[4], xb[RB][4], yb[NB][4], db[4];
+    auto load = [&](float (&xs)[RB][4], float (&ys)[NB][4], float (&ds)[4], int ch) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
 #pragma unroll
             for (int b = 0; b < RB; ++b) xs[b][s] = gload<float>(X, xo[b] + (4 * ch + s) * dx);
 #pragma unroll
             for (int b = 0; b < NB; ++b) ys[b][s] = gload<float>(Y, yo[b] + (4 * ch + s) * dy);
+            // inner index 16 ch + 4 s + l/16
+            if constexpr (DS) ds[s] = gload<float>(Dg, Dg.off + (16 * ch + 4 * s + lk) * Dg.sk);
         }
         __builtin_amdgcn_sched_barrier(0);
     };
-    auto mma = [&](const float (&xs)[RB][4], const float (&ys)[NB][4]) {
+    auto mma = [&](const float (&xs)[RB][4], const float (&ys)[NB][4], const float (&ds)[4]) {
         s16x4 xh[RB], xl[RB];
 #pragma unroll
         for (int b = 0; b < RB; ++b) split_bf16(xs[b], xh[b], xl[b]);
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
             s16x4 yh, yl;
-            split_bf16(ys[bi], yh, yl);
+            float yv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) yv[q] = DS ? ys[bi][q] * ds[q] : ys[bi][q];
+            split_bf16(yv, yh, yl);
 #pragma unroll
             for (int bj = 0; bj < RB; ++bj) {
                 acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yh, xh[bj], acc[bi][bj], 0, 0, 0);
@@ -304,60 +319,6 @@ __device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][RB], const GOp& X,
         __builtin_amdgcn_sched_barrier(0);
     };
     // (reads past the last chunk repeat it and are not used)
-    const int last = nchunks - 1;
-    load(xa, ya, 0);
-    int ch = 0;
-    for (; ch + 2 <= nchunks; ch += 2) {
-        load(xb, yb, ch + 1);
-        mma(xa, ya);
-        load(xa, ya, min(ch + 2, last));
-        mma(xb, yb);
-    }
-    if (ch < nchunks) mma(xa, ya);
-}
-
-// L D L^T update products (FP64): acc += X (Y D)^T, the facing operand Y
-// scaled by d_p (read through Dg: element p at p * Dg.sk, the diagonal of the
-// source panel) just before the products, so its loads stay in flight; two
-// register buffers of 8 inner indices as in wave_gemm.
-template <int NB, int RB = 4>
-__device__ __forceinline__ void wave_gemm_d(d4 (&acc)[NB][RB], const GOp& X, const GOp& Y, const GOp& Dg, int K)
-{
-    const int lane = threadIdx.x & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int nchunks = (K + 7) >> 3;
-    if (nchunks <= 0) return;
-    int xo[2][RB], yo[2][NB];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-#pragma unroll
-        for (int b = 0; b < RB; ++b) xo[u][b] = X.off + (16 * b + li) * X.si + (4 * u + lk) * X.sk;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) yo[u][b] = Y.off + (16 * b + li) * Y.si + (4 * u + lk) * Y.sk;
-    }
-    const int dx = 8 * X.sk, dy = 8 * Y.sk;
-    double xa[2][RB], ya[2][NB], da[2], xb[2][RB], yb[2][NB], db[2];
-    auto load = [&](double (&xs)[2][RB], double (&ys)[2][NB], double (&ds)[2], int ch) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-#pragma unroll
-            for (int b = 0; b < RB; ++b) xs[u][b] = gload<double>(X, xo[u][b] + ch * dx);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) ys[u][b] = gload<double>(Y, yo[u][b] + ch * dy);
-            ds[u] = gload<double>(Dg, Dg.off + (8 * ch + 4 * u + lk) * Dg.sk);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    };
-    auto mma = [&](const double (&xs)[2][RB], const double (&ys)[2][NB], const double (&ds)[2]) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < RB; ++bj)
-                    acc[bi][bj] = MM<double>::mfma(ys[u][bi] * ds[u], xs[u][bj], acc[bi][bj]);
-        __builtin_amdgcn_sched_barrier(0);
-    };
     const int last = nchunks - 1;
     load(xa, ya, da, 0);
     int ch = 0;
@@ -371,17 +332,24 @@ __device__ __forceinline__ void wave_gemm_d(d4 (&acc)[NB][RB], const GOp& X, con
 }
 
 // acc += X Y^T over K inner indices: FP64 or FP32 products, or (FP32 panels
-// with the split option) split-BF16 products
-template <int NB, class T, int RB = 4>
-__device__ __forceinline__ void tile_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K, bool split)
+// with the split option) split-BF16 products; DS: acc += X (Y D)^T with the
+// d_p read through Dg
+template <int NB, class T, int RB = 4, bool DS = false>
+__device__ __forceinline__ void tile_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K, bool split,
+                                          const GOp& Dg)
 {
     if constexpr (sizeof(T) == 4) {
         if (split) {
-            wave_gemm_split<NB, RB>(acc, X, Y, K);
+            wave_gemm_split<NB, RB, DS>(acc, X, Y, K, Dg);
             return;
         }
     }
-    wave_gemm<NB, T, RB>(acc, X, Y, K);
+    wave_gemm<NB, T, RB, DS>(acc, X, Y, K, Dg);
+}
+template <int NB, class T, int RB = 4>
+__device__ __forceinline__ void tile_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K, bool split)
+{
+    tile_gemm<NB, T, RB, false>(acc, X, Y, K, split, X);
 }
 
 template <int NB, class A, int RB>
@@ -1092,8 +1060,8 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // mrows <= 128 (the waves form a 2x2 grid of 64x64 wave tiles).  A merged
 // item (np > 1, kind bits 8..) sums the products of the np consecutive
 // pieces k-np+1 .. k of a split supernode (piece p's rows are k's rows
-// shifted by fcol[k] - fcol[p]) before its one scatter.  LDL (FP64):
-// each piece's product is L_p[rows] D_p L_p[cols]^T, D_p on the diagonal of panel p.
+// shifted by fcol[k] - fcol[p]) before its one scatter.  LDL: each
+// piece's product is L_p[rows] D_p L_p[cols]^T, D_p on the diagonal of panel p.
 // LU: the tile covers the whole square of the facing rows (no triangle);
 // W_L = L_k[rows] U^T_k[cols]^T goes to j's L panel (its square diagonal
 // block included), and, for rows below j's diagonal block, W_U =
@@ -1132,8 +1100,9 @@ __device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, cons
                 const int64_t ld = pl.stride[p];
                 const T* A = static_cast<const T*>(a.panels) + pl.panel_off[p];
                 if constexpr (LDL)
-                    wave_gemm_d<4, RB>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld),
-                                       make_gop(A, ld * w, col0 + c0 + sh, 1, ld), make_gop(A, ld * w, 0, 0, ld + 1), w);
+                    tile_gemm<4, T, RB, true>(acc, make_gop(A, ld * w, row0 + r0 + sh, 1, ld),
+                                              make_gop(A, ld * w, col0 + c0 + sh, 1, ld), w, a.split != 0,
+                                              make_gop(A, ld * w, 0, 0, ld + 1));
                 else
                     tile_gemm<4, T, RB>(acc, make_gop(A + xo, ld * w, row0 + r0 + sh, 1, ld),
                                         make_gop(A + yo, ld * w, col0 + c0 + sh, 1, ld), w, a.split != 0);
@@ -1206,7 +1175,10 @@ __device__ __forceinline__ void finish_update(const SchedArgs& a, int j)
 // tree of small systems are a few columns wide: as separate factor, solve
 // and update items each paid several queue round trips and chains of
 // dependent metadata loads for a few hundred flops.  Products accumulate in
-// FP64 from the stored (type T) values.
+// FP64 from the stored (type T) values.  LDL: the tile is factored as
+// L D L^T (static pivoting as in FACT), the rows below become A_off Y^T with
+// Y = D^{-1} L^{-1}, and the update products take d_t (FP64, from the
+// factored tile) between the two rows.
 constexpr int kSLd = kSmallRows + 1;   // leading dimension of the LDS panel copy
 static_assert(kSLd * kNB * sizeof(float) + (kSmallMap + 8 * kSmallMaxUpd) * sizeof(int) +
                       kSmallMaxUpd * sizeof(int64_t) <= (kPbLd * kNB + 32) * sizeof(float),
@@ -1215,7 +1187,7 @@ static_assert((kSLd * kNB * sizeof(float) + (kSmallMap + 8 * kSmallMaxUpd) * siz
               "misaligned small-block offset table");
 static_assert(kSmallRows * kNB % kThreads == 0, "rows below per thread");
 
-template <class T>
+template <class T, bool LDL = false>
 __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const int4 d1, double* Lt, T* Dt, T* Pb)
 {
     const DevPlan& pl = a.pl;
@@ -1257,12 +1229,15 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
     }
     __syncthreads();
     if (wave == 0) {
+        const double thr = LDL && a.pivot_eps > 0.0
+                               ? a.pivot_eps * __longlong_as_double(*reinterpret_cast<const long long*>(a.status + kStAmax))
+                               : 0.0;
         if (w <= 8)
-            tile_chol_inv<T, 8>(Lt, bc, Dt, w, f, a.status);
+            tile_chol_inv<T, 8, LDL>(Lt, bc, Dt, w, f, a.status, thr);
         else if (w <= 16)
-            tile_chol_inv<T, 16>(Lt, bc, Dt, w, f, a.status);
+            tile_chol_inv<T, 16, LDL>(Lt, bc, Dt, w, f, a.status, thr);
         else
-            tile_chol_inv<T, 32>(Lt, bc, Dt, w, f, a.status);
+            tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, w, f, a.status, thr);
     }
     __syncthreads();
     for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
@@ -1297,7 +1272,11 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
         }
     }
     __syncthreads();
-    // update tiles: C_j[rmap(r), rmap(c)] -= P_r . P_c on the lower triangle of j
+    // update tiles: C_j[rmap(r), rmap(c)] -= P_r . P_c (L D L^T: P_r D P_c) on
+    // the lower triangle of j
+    double* dg = bc + 64;   // (L D L^T) the pivots d_t
+    if (LDL && tid < w) dg[tid] = Lt[tid * 34];
+    __syncthreads();
     for (int u = 0; u < nupd; ++u) {
         const int* e = dtab + 8 * u;
         const int row0 = e[1], mrows = e[2], col0 = e[3], ncols = e[4], mb = e[5], ldj = e[6];
@@ -1307,7 +1286,11 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
             const int tr = smap[mb + r], tc = smap[mb + c];
             if (tr >= tc) {
                 double acc = 0.0;
-                for (int t = 0; t < w; ++t) acc += (double)S[r + t * kSLd] * (double)S[c + t * kSLd];
+                if constexpr (LDL) {
+                    for (int t = 0; t < w; ++t) acc += (double)S[r + t * kSLd] * dg[t] * (double)S[c + t * kSLd];
+                } else {
+                    for (int t = 0; t < w; ++t) acc += (double)S[r + t * kSLd] * (double)S[c + t * kSLd];
+                }
                 __hip_atomic_fetch_add(Cg + (int64_t)tc * ldj + tr, (T)(-acc), __ATOMIC_RELAXED, AGENT);
             }
         }
@@ -1318,8 +1301,8 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
 }
 
 // ---------------------------------------------------------------- scheduler
-// LDL: the L D L^T factor (FP64; no fused small items).  LU: the L U factor
-// (two panel arrays; no fused small items).
+// LDL: the L D L^T factor.  LU: the L U factor (two panel arrays; no fused
+// small items).
 template <class T, bool LDL = false, bool LU = false>
 __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 {
@@ -1414,8 +1397,8 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         } else if (kind == kUpdate) {
             if (thin) task_update<T, LDL, LU, 1>(a, d0, d1, rpos, cpos);
             else task_update<T, LDL, LU>(a, d0, d1, rpos, cpos);
-        } else if constexpr (!LDL && !LU) {
-            task_small<T>(a, d0, d1, Lt, Dt, Pb);
+        } else if constexpr (!LU) {
+            task_small<T, LDL>(a, d0, d1, Lt, Dt, Pb);
         }
         // every wave's stores and atomics have completed before the barrier
         // (FACT and TRSM items ran at raised wave priority: they are on the
@@ -1661,6 +1644,8 @@ int sched_blocks_per_cu(bool f32, bool ldlt, bool lu)
     if (lu)
         e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<float, false, true>, kThreads, 0)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<double, false, true>, kThreads, 0);
+    else if (f32 && ldlt)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<float, true>, kThreads, 0);
     else if (f32)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sched_kernel<float>, kThreads, 0);
     else if (ldlt)
@@ -1675,6 +1660,7 @@ hipError_t launch_sched(const SchedArgs& a, bool f32, bool lu, int grid, hipStre
 {
     if (lu && f32) sched_kernel<float, false, true><<<grid, kThreads, 0, s>>>(a);
     else if (lu) sched_kernel<double, false, true><<<grid, kThreads, 0, s>>>(a);
+    else if (f32 && a.ldlt) sched_kernel<float, true><<<grid, kThreads, 0, s>>>(a);
     else if (f32) sched_kernel<float><<<grid, kThreads, 0, s>>>(a);
     else if (a.ldlt) sched_kernel<double, true><<<grid, kThreads, 0, s>>>(a);
     else sched_kernel<double><<<grid, kThreads, 0, s>>>(a);

@@ -66,12 +66,10 @@ def test_bad_options():
     # every precision mode and option set in range is accepted at analysis
     for prec in ["fp64", "fp32_ir", "bf16x3_ir"]:
         Solver(p.n, p.colptr, p.rowind, precision=prec, merge_split=16, fuse_small=False, tile=1)
-    # L D L^T: FP64 only; an unknown method code is rejected by the library
-    Solver(p.n, p.colptr, p.rowind, method="ldlt", merge_split=16)
-    for prec in ["fp32_ir", "bf16x3_ir"]:
-        with pytest.raises(SpxError):
-            Solver(p.n, p.colptr, p.rowind, method="ldlt", precision=prec)
-    # L U: every precision mode
+    # L D L^T and L U: every precision mode; an unknown method code is
+    # rejected by the library
+    for prec in ["fp64", "fp32_ir", "bf16x3_ir"]:
+        Solver(p.n, p.colptr, p.rowind, method="ldlt", precision=prec, merge_split=16)
     for prec in ["fp64", "fp32_ir", "bf16x3_ir"]:
         Solver(p.n, p.colptr, p.rowind, method="lu", precision=prec)
     with pytest.raises(ValueError):

@@ -176,3 +176,76 @@ def test_ldlt_batch(orc, torch):
             assert np.max(np.abs(xq - xo)) <= 1e-9 * np.max(np.abs(xo))
             nneg += orc.logabsdet_ldlt(sym, P)[1]
         assert s.info()["nneg"] == nneg
+
+
+@pytest.mark.parametrize("case", ["grid3", "qd_split"])
+def test_ldlt_parity_without_fused_small(orc, torch, case):
+    # the FACT / TRSM / UPDATE path for the small blocks too (fused small
+    # items are the default)
+    if case == "grid3":
+        _check(orc, torch, grid_laplacian((12, 11, 10), shift=1e-3), nrhs=2, fuse_small=False)
+    else:
+        _, nneg = _check(orc, torch, _quasi_definite(500, 200, 6), split_width=33, amalg_pct=40, fuse_small=False)
+        assert nneg == 200
+
+
+def _check_refined(orc, torch, p, precision, nrhs=1, **kw):
+    """FP32-storage factors: the backward-error bound of L D L^T in precision
+    u (2^-24; 2^-16 for the split-BF16 products hi*hi + hi*lo + lo*hi),
+    ||P A P^T - L D L^T||_F <= gamma_{m+1} || |L| |D| |L|^T ||_F with m the
+    largest column count (element growth of an indefinite factorization is
+    inside |L| |D| |L|^T), the oracle's inertia, and the refined solve to
+    omega <= 1e-14 and the oracle's x within 1e-9."""
+    from paper_1405_2636_amd import Solver
+    print("ldlt refined case n=%d nnz=%d prec=%s opts=%s" % (p.n, p.nnz, precision, kw), flush=True)
+    s = Solver(p.n, p.colptr, p.rowind, method="ldlt", precision=precision, **kw)
+    s.factorize(torch.tensor(p.values, dtype=torch.float64, device="cuda"))
+    F = s.factor_values().cpu().numpy().astype(np.float64)
+    sym = orc.analyze(p.n, p.colptr, p.rowind, leaf=kw.get("leaf_size", 64), amalg_pct=kw.get("amalg_pct", 12),
+                      split_width=kw.get("split_width", 256))
+    P = orc.factor_ldlt(sym, p.colptr, p.rowind, p.values)
+    ri, ci, v = orc.unpack(sym, F)
+    dg = ri == ci
+    D = np.zeros(p.n)
+    D[ri[dg]] = v[dg]
+    Lu = sp.csc_matrix((v[~dg], (ri[~dg], ci[~dg])), shape=(p.n, p.n)) + sp.identity(p.n, format="csc")
+    A = sp.csc_matrix((p.values, p.rowind, p.colptr), shape=(p.n, p.n))
+    PA = A[sym.perm][:, sym.perm]
+    u = 2.0 ** -24 if precision == "fp32_ir" else 2.0 ** -16
+    m = int(np.max(np.diff(Lu.tocsc().indptr)))
+    g = (m + 1) * u / (1 - (m + 1) * u)
+    absL = abs(Lu)
+    bound = g * sp.linalg.norm(absL @ sp.diags(np.abs(D)) @ absL.T)
+    res = sp.linalg.norm(PA - Lu @ sp.diags(D) @ Lu.T)
+    assert res <= bound, (res, bound)
+    lad, nneg = orc.logabsdet_ldlt(sym, P)
+    info = s.info()
+    assert info["nneg"] == nneg
+    assert abs(info["logdet"] - lad) <= 1e-4 * max(1.0, abs(lad))
+    rng = np.random.default_rng(p.n + 1)
+    B = rng.uniform(-1, 1, (p.n, nrhs))
+    b = torch.tensor(np.ascontiguousarray(B.T if nrhs > 1 else B[:, 0]), device="cuda")
+    x, sinfo = s.solve(b)
+    assert sinfo["omega"] <= 1e-14 and sinfo["converged"], sinfo
+    xo = orc.solve_ldlt(sym, P, B)
+    xo = xo + orc.solve_ldlt(sym, P, B - (A @ xo))    # one FP64 refinement step of the oracle's solve
+    xg = x.cpu().numpy()
+    xg = xg.T if nrhs > 1 else xg[:, None]
+    assert np.max(np.abs(xg - xo)) <= 1e-9 * np.max(np.abs(xo))
+    return nneg
+
+
+@pytest.mark.parametrize("precision", ["fp32_ir", "bf16x3_ir"])
+@pytest.mark.parametrize("case", ["qd", "qd_split_merge", "grid3", "dense", "qd_nofuse"])
+def test_ldlt_refinement_modes(orc, torch, precision, case):
+    if case == "qd":
+        assert _check_refined(orc, torch, _quasi_definite(300, 150, 5), precision, nrhs=3) == 150
+    elif case == "qd_split_merge":
+        assert _check_refined(orc, torch, _quasi_definite(500, 200, 6), precision, split_width=16,
+                              merge_split=4) == 200
+    elif case == "grid3":
+        _check_refined(orc, torch, grid_laplacian((12, 11, 10), shift=1e-3), precision, nrhs=4)
+    elif case == "dense":
+        assert _check_refined(orc, torch, _dense_quasi_definite(150, 107, 11), precision, split_width=100) == 107
+    else:
+        assert _check_refined(orc, torch, _quasi_definite(400, 160, 8), precision, fuse_small=False) == 160
