@@ -13,10 +13,12 @@ value = algorithmic factorization flops (sum of squared exact column counts)
         / FP64 factorization time (HIP events around the factorize call).
 
 Order of the run: the FP64 headline leg, then the oracle's CPU baseline,
-then the other legs (FP32 + refinement, split-BF16 + refinement, L D L^T,
+then the other legs (FP32 + refinement, split-BF16 + refinement, L D L^T in
+FP64 and FP32 + refinement, the deterministic accumulation mode in FP64,
 the 512-system batch, then L U with static pivoting on the 80^3
 convection-diffusion stencil with 4 right-hand sides in the three precision
-modes) while the wall-clock budget (--budget-s, counted from
+modes, then L D L^T on the 40^3 clamped elasticity mesh with 8 right-hand
+sides in FP64 and FP32 + refinement) while the wall-clock budget (--budget-s, counted from
 the start of the process) leaves room for them; a leg that does not fit is
 listed under "skipped".  Progress lines with the elapsed time go to stderr;
 the one JSON line goes to stdout at the end.
@@ -119,14 +121,15 @@ def copy_probe():
     print("copied 3 x %d bytes" % (n * 8), flush=True)
 
 
-def run_leg(torch, np, Solver, p, vals, b0, precision, steps, warmup, method="llt", adjoint=True):
+def run_leg(torch, np, Solver, p, vals, b0, precision, steps, warmup, method="llt", adjoint=True,
+            deterministic=False):
     """Warm-up, then `steps` timed passes of factorize + refined solve in one
-    precision mode (and method: L L^T, or L D L^T).  Times are HIP events on
-    the torch stream the library is called on; the kernel time is the
+    precision mode (and method: L L^T, L D L^T or L U).  Times are HIP events
+    on the torch stream the library is called on; the kernel time is the
     library's own event pair around the scheduler kernel, on the same stream."""
-    name = precision if method == "llt" else precision + " " + method
+    name = (precision if method == "llt" else precision + " " + method) + (" det" if deterministic else "")
     t0 = time.perf_counter()
-    s = Solver(p.n, p.colptr, p.rowind, precision=precision, method=method)
+    s = Solver(p.n, p.colptr, p.rowind, precision=precision, method=method, deterministic=deterministic)
     t_an = time.perf_counter() - t0
     info = s.info()
     log("[%s] analyze %.1f s: ncblk %d nnz(L) %d flops %.3e tasks %d"
@@ -227,6 +230,41 @@ def run_batch(torch, np, Solver, steps):
     return out
 
 
+def run_update_bench(torch, np, ks, ms, precisions, streams, calls, gapped_modes, methods):
+    """The update-kernel study of Section V-B (Fig. 2): `calls` updates
+    C -= A B^T of a synthetic panel (A: m x k rows of inner dimension k, B
+    its first k rows) into a dense m-row target or a gapped 2m-row one, per
+    launch mode (1-3 streams round-robin, or 0 = all calls in one grid).
+    GFLOP/s counts 2 k (m k - k (k - 1) / 2) flops per call (the target's
+    diagonal block is updated on its lower triangle only)."""
+    from gen import update_panels
+    from paper_1405_2636_amd.spx import update_bench
+    rows = []
+    for prec in precisions:
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        for method in methods:
+            for gapped in gapped_modes:
+                for k in ks:
+                    for m in ms:
+                        if m < k:
+                            continue
+                        P, rmap, ldc = update_panels(k, m, k, gapped, seed=m + k)
+                        buf = torch.tensor(np.concatenate([P, np.zeros(ldc * k)]), dtype=dt, device="cuda")
+                        rm = torch.tensor(rmap, device="cuda")
+                        flops = 2.0 * k * (m * k - k * (k - 1) / 2)
+                        row = {"precision": prec, "method": method, "gapped": gapped, "k": k, "m": m, "ldc": ldc}
+                        for ns in streams:
+                            update_bench(buf, rm, k, m, k, ldc, prec, method, 0, 2, ns)   # warm-up
+                            t = update_bench(buf, rm, k, m, k, ldc, prec, method, 0, calls, ns)
+                            row["gflops_%s" % ("grid" if ns == 0 else "s%d" % ns)] = calls * flops / (t * 1e-3) / 1e9
+                        rows.append(row)
+                        log("[update %s %s %s] k %d m %d: %s" % (
+                            prec, method, "gapped" if gapped else "dense", k, m,
+                            " ".join("%s %.0f" % (key[7:], v) for key, v in row.items() if key.startswith("gflops_"))))
+                        del buf, rm
+    return {"calls": calls, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +280,16 @@ def main():
                     help="only the 512-system batch leg (its JSON object on one line; for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run three plain device copies of 512 MiB (scale for the HBM byte counters)")
+    ap.add_argument("--update-bench", action="store_true",
+                    help="only the update-kernel study (Fig. 2 recipe): GFLOP/s per inner size k, height m, target "
+                         "kind and launch mode, as one JSON line")
+    ap.add_argument("--update-k", default="64,128,256")
+    ap.add_argument("--update-m", default="256,512,1024,2048,4096,8192,16384")
+    ap.add_argument("--update-precision", default="fp64,fp32_ir")
+    ap.add_argument("--update-method", default="llt")
+    ap.add_argument("--update-streams", default="1,2,3,0", help="streams per sweep point (0: all calls in one grid)")
+    ap.add_argument("--update-target", default="dense,gapped")
+    ap.add_argument("--update-calls", type=int, default=100)
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -258,6 +306,13 @@ def main():
     from paper_1405_2636_amd import Solver
 
     log("imports done")
+    if args.update_bench:
+        ints = lambda t: [int(x) for x in t.split(",") if x]
+        res = run_update_bench(torch, np, ints(args.update_k), ints(args.update_m), args.update_precision.split(","),
+                               ints(args.update_streams), args.update_calls,
+                               [t == "gapped" for t in args.update_target.split(",")], args.update_method.split(","))
+        print(json.dumps({"update_bench": res}), flush=True)
+        return
     if args.batch_only:
         print(json.dumps({"batch": run_batch(torch, np, Solver, args.steps)}), flush=True)
         return
@@ -309,9 +364,10 @@ def main():
     def speedup(r):
         return (r64["factor_ms"] + r64["solve_ms"]) / (r["factor_ms"] + r["solve_ms"])
 
-    legs = [] if args.headline_only else (["fp32_ir", "bf16x3_ir", "ldlt_fp64"] + ([] if args.no_batch else ["batch"])
-                                          + ["lu_fp64", "lu_fp32_ir", "lu_bf16x3_ir"])
-    c3 = {}
+    legs = [] if args.headline_only else (["fp32_ir", "bf16x3_ir", "ldlt_fp64", "ldlt_fp32_ir", "deterministic_fp64"]
+                                          + ([] if args.no_batch else ["batch"])
+                                          + ["lu_fp64", "lu_fp32_ir", "lu_bf16x3_ir", "c5_ldlt_fp64", "c5_ldlt_fp32_ir"])
+    c3, c5 = {}, {}
     for leg in legs:
         est = 1.3 * leg_s if leg != "batch" else 90.0
         if not fits(est):
@@ -323,13 +379,19 @@ def main():
             out[leg] = {"factor_ms": r["factor_ms"], "solve_ms": r["solve_ms"],
                         "factor_gflops": flops / (r["factor_ms"] * 1e-3) / 1e9, "omega": r["omega"],
                         "ir_iters": r["ir_iters"], "kernel_ms": r["kernel_ms"], "speedup_vs_fp64": speedup(r)}
-        elif leg == "ldlt_fp64":
-            r = run_leg(torch, np, Solver, p, vals, b0, "fp64", args.steps, args.warmup, method="ldlt",
-                        adjoint=False)
+        elif leg in ("ldlt_fp64", "ldlt_fp32_ir", "deterministic_fp64"):
+            prec = "fp32_ir" if leg == "ldlt_fp32_ir" else "fp64"
+            r = run_leg(torch, np, Solver, p, vals, b0, prec, args.steps, args.warmup,
+                        method="llt" if leg == "deterministic_fp64" else "ldlt", adjoint=False,
+                        deterministic=leg == "deterministic_fp64")
             out[leg] = {"factor_ms": r["factor_ms"], "solve_ms": r["solve_ms"],
                         "factor_gflops": flops / (r["factor_ms"] * 1e-3) / 1e9, "omega": r["omega"],
-                        "ir_iters": r["ir_iters"], "kernel_ms": r["kernel_ms"],
-                        "kernel_frac_of_fp64_peak": flops / (r["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+                        "ir_iters": r["ir_iters"], "kernel_ms": r["kernel_ms"]}
+            if prec == "fp64":
+                out[leg]["kernel_frac_of_fp64_peak"] = flops / (r["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS
+            if leg == "ldlt_fp32_ir" and "ldlt_fp64" in out:
+                out[leg]["speedup_vs_fp64"] = ((out["ldlt_fp64"]["factor_ms"] + out["ldlt_fp64"]["solve_ms"])
+                                               / (r["factor_ms"] + r["solve_ms"]))
         elif leg == "batch":
             out["batch"] = run_batch(torch, np, Solver, args.steps)
         elif leg.startswith("lu_"):
@@ -343,6 +405,26 @@ def main():
             r = run_leg(torch, np, Solver, c3["p"], c3["vals"], c3["b0"], prec, args.steps, args.warmup, method="lu",
                         adjoint=False)
             d = out["convdiff80_lu"]
+            d["flops_alg"] = r["flops"]
+            d[prec] = {"factor_ms": r["factor_ms"], "solve_ms": r["solve_ms"],
+                       "factor_gflops": r["flops"] / (r["factor_ms"] * 1e-3) / 1e9, "omega": r["omega"],
+                       "ir_iters": r["ir_iters"], "kernel_ms": r["kernel_ms"]}
+            if prec == "fp64":
+                d[prec]["kernel_frac_of_fp64_peak"] = r["flops"] / (r["kernel_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS
+            elif "fp64" in d:
+                d[prec]["speedup_vs_fp64"] = ((d["fp64"]["factor_ms"] + d["fp64"]["solve_ms"])
+                                              / (r["factor_ms"] + r["solve_ms"]))
+        elif leg.startswith("c5_"):
+            # L D L^T on the 40^3 clamped elasticity mesh, 8 RHS
+            if not c5:
+                q = make_config(5)
+                c5.update(p=q, vals=torch.tensor(q.values, device="cuda"),
+                          b0=torch.tensor(np.ascontiguousarray(q.b.T), device="cuda"))
+                out["elasticity40_ldlt"] = {"workload": q.name, "n": q.n, "nnz_a": int(q.nnz), "nrhs": 8}
+            prec = leg[len("c5_ldlt_"):]
+            r = run_leg(torch, np, Solver, c5["p"], c5["vals"], c5["b0"], prec, args.steps, args.warmup,
+                        method="ldlt", adjoint=False)
+            d = out["elasticity40_ldlt"]
             d["flops_alg"] = r["flops"]
             d[prec] = {"factor_ms": r["factor_ms"], "solve_ms": r["solve_ms"],
                        "factor_gflops": r["flops"] / (r["factor_ms"] * 1e-3) / 1e9, "omega": r["omega"],

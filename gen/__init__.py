@@ -16,3 +16,4 @@ from .stencils import (  # noqa: F401
     CONFIG_NAMES,
 )
 from .elasticity import elasticity3d, element_stiffness, material_matrix, strain_matrix  # noqa: F401
+from .update_panels import update_panels  # noqa: F401

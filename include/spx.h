@@ -290,6 +290,34 @@ int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip
  * item count, or a negative status. */
 int64_t spx_get_trace(spx_handle* h, int64_t* dst, int64_t cap, int32_t* kinds);
 
+/* Update-kernel microbenchmark (Section V-B's study of the update kernel:
+ * C = C - A B^T with B the first k rows of A, into a dense or a gapped
+ * target panel, over many calls on one or several streams).  Runs the
+ * scheduler's update tiles (the same device code; 256 x 64 tiles, or
+ * 128 x 128 with tile = 1) of one synthetic source panel into one target
+ * panel, calls times, and returns the elapsed time in *ms (HIP events).
+ *   precision: SPX_FP64 (double panels), SPX_FP32_IR (float panels, FP32
+ *     products) or SPX_BF16X3_IR (float panels, split-BF16 products);
+ *   method: SPX_LLT, or SPX_LDLT (C = C - A D B^T, D the diagonal of the
+ *     source panel's diagonal block);
+ *   panels: device array of the element type holding the source panel at
+ *     offset 0 (column-major, leading dimension n_inner + m, n_inner columns:
+ *     an n_inner x n_inner diagonal block, then the m rows of A) and the
+ *     target panel at offset (n_inner + m) * n_inner (column-major, leading
+ *     dimension ldc >= m, k columns);
+ *   rmap: device int32[m], the target row of source row i of A: rmap[i] = i
+ *     for i < k (the target's columns), then increasing values in [k, ldc)
+ *     (checked; a dense target has rmap[i] = i and ldc = m);
+ *   only the lower triangle of the target's k x k diagonal block is
+ *     updated (the factorization's symmetric update);
+ *   nstreams: 1..3 = one grid per call, the calls round-robin over that many
+ *     streams (default priority); 0 = all calls in one grid.
+ * The call is synchronous; the target accumulates every call's update.
+ * Returns SPX_OK, SPX_EINVAL (the message in spx_last_error(NULL)),
+ * SPX_ENOMEM or SPX_EDEVICE. */
+int spx_update_bench(int32_t precision, int32_t method, int32_t n_inner, int32_t m, int32_t k, void* panels,
+                     const int32_t* rmap, int32_t ldc, int32_t tile, int32_t calls, int32_t nstreams, double* ms);
+
 /* Free everything owned by the handle.  NULL is allowed. */
 void spx_destroy(spx_handle* h);
 
@@ -297,7 +325,8 @@ void spx_destroy(spx_handle* h);
 const char* spx_strerror(int status);
 
 /* Text of the last error raised on h ("" if none); valid until the next call.
- * With h == NULL: the message of the last failed spx_analyze of this thread. */
+ * With h == NULL: the message of the last failed spx_analyze or
+ * spx_update_bench of this thread. */
 const char* spx_last_error(const spx_handle* h);
 
 #ifdef __cplusplus

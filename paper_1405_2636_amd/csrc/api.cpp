@@ -31,6 +31,8 @@ hipError_t launch_sched_init(const SchedArgs& a, const int32_t* ready, int32_t n
                              const int32_t* fact_dep0, int32_t ncblk, hipStream_t s);
 int sched_blocks_per_cu(bool f32, bool ldlt, bool lu);
 hipError_t launch_sched(const SchedArgs& a, bool f32, bool lu, int grid, hipStream_t s);
+hipError_t launch_update_bench(const SchedArgs& a, bool f32, bool ldl, const int4* tiles, int ntiles, int mbase,
+                               int copies, hipStream_t s);
 hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s);
 hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
 hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
@@ -237,7 +239,7 @@ struct spx_handle {
 
 namespace {
 
-thread_local std::string g_analyze_err;   // message of the last failed spx_analyze in this thread
+thread_local std::string g_analyze_err;   // message of the last failed handle-less call in this thread
 
 int fail(spx_handle* h, int code, const std::string& msg)
 {
@@ -1293,6 +1295,106 @@ int64_t spx_get_trace(spx_handle* h, int64_t* dst, int64_t cap, int32_t* kinds)
         }
         return h->total;
     });
+}
+
+int spx_update_bench(int32_t precision, int32_t method, int32_t n_inner, int32_t m, int32_t k, void* panels,
+                     const int32_t* rmap, int32_t ldc, int32_t tile, int32_t calls, int32_t nstreams, double* ms)
+{
+    using namespace spx;
+    std::vector<hipStream_t> st;
+    std::vector<hipEvent_t> ev;
+    auto cleanup = [&]() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto q : st) (void)hipStreamDestroy(q);
+    };
+    try {
+        if (precision != SPX_FP64 && precision != SPX_FP32_IR && precision != SPX_BF16X3_IR)
+            throw InvalidArgument("unsupported precision");
+        if (method != SPX_LLT && method != SPX_LDLT) throw InvalidArgument("method must be SPX_LLT or SPX_LDLT");
+        if (n_inner < 1 || k < 1 || m < k || !panels || !rmap || !ms) throw InvalidArgument("bad sizes or pointers");
+        if (ldc < m || tile < 0 || tile > 1 || calls < 1 || nstreams < 0 || nstreams > 3)
+            throw InvalidArgument("bad ldc, tile, calls or stream count");
+        if (static_cast<int64_t>(n_inner + m) * n_inner + static_cast<int64_t>(ldc) * k > INT32_MAX)
+            throw InvalidArgument("panels exceed 2^31 elements");
+        // the row map: source row n_inner + i goes to target row rmap[i]; the
+        // first k are the target's columns, the others distinct rows below
+        std::vector<int32_t> rm(static_cast<size_t>(m));
+        HIPCHK(hipMemcpy(rm.data(), rmap, rm.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int32_t i = 0; i < m; ++i)
+            if ((i < k && rm[i] != i) || (i >= k && (rm[i] < k || rm[i] >= ldc || (i > k && rm[i] <= rm[i - 1]))))
+                throw InvalidArgument("row map: the first k rows must be 0..k-1, the others increasing in [k, ldc)");
+        const bool f32 = precision != SPX_FP64;
+        const int32_t tr = tile ? 128 : 256, tc = tile ? 128 : 64;
+        std::vector<int4> tiles;
+        for (int32_t r0 = n_inner; r0 < n_inner + m; r0 += tr)
+            for (int32_t c0 = n_inner; c0 < n_inner + k; c0 += tc) {
+                const int32_t mr = std::min(tr, n_inner + m - r0);
+                if (r0 + mr - 1 < c0) continue;   // strictly above the target's diagonal
+                tiles.push_back(int4{r0, mr, c0, std::min(tc, n_inner + k - c0)});
+            }
+        DevBuf<int32_t> fcol, lcol, stride;
+        DevBuf<int64_t> poff;
+        DevBuf<int4> dt;
+        fcol.upload(std::vector<int32_t>{0, n_inner});
+        lcol.upload(std::vector<int32_t>{n_inner - 1, n_inner + k - 1});
+        stride.upload(std::vector<int32_t>{n_inner + m, ldc});
+        poff.upload(std::vector<int64_t>{0, static_cast<int64_t>(n_inner + m) * n_inner});
+        dt.upload(tiles);
+        SchedArgs a{};
+        a.pl.ncblk = 2;
+        a.pl.fcol = fcol.p;
+        a.pl.lcol = lcol.p;
+        a.pl.stride = stride.p;
+        a.pl.panel_off = poff.p;
+        a.panels = panels;
+        a.rmap = rmap;
+        a.split = precision == SPX_BF16X3_IR ? 1 : 0;
+        a.ldlt = method == SPX_LDLT ? 1 : 0;
+        const int nt = static_cast<int>(tiles.size());
+        const int ns = std::max(1, nstreams);
+        for (int i = 0; i < ns; ++i) {
+            hipStream_t q;
+            HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+            st.push_back(q);
+        }
+        for (int i = 0; i < 2 + ns; ++i) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipEventRecord(ev[0], st[0]));
+        for (int i = 1; i < ns; ++i) HIPCHK(hipStreamWaitEvent(st[i], ev[0], 0));
+        if (nstreams == 0) {   // all calls as one grid
+            HIPCHK(launch_update_bench(a, f32, method == SPX_LDLT, dt.p, nt, -n_inner, calls, st[0]));
+        } else {               // one grid per call, round-robin over the streams
+            for (int c = 0; c < calls; ++c)
+                HIPCHK(launch_update_bench(a, f32, method == SPX_LDLT, dt.p, nt, -n_inner, 1, st[c % ns]));
+        }
+        for (int i = 1; i < ns; ++i) {
+            HIPCHK(hipEventRecord(ev[2 + i], st[i]));
+            HIPCHK(hipStreamWaitEvent(st[0], ev[2 + i], 0));
+        }
+        HIPCHK(hipEventRecord(ev[1], st[0]));
+        HIPCHK(hipEventSynchronize(ev[1]));
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+        *ms = t;
+        cleanup();
+        return SPX_OK;
+    } catch (const InvalidArgument& e) {
+        cleanup();
+        g_analyze_err = e.what();
+        return SPX_EINVAL;
+    } catch (const std::bad_alloc&) {
+        cleanup();
+        g_analyze_err = "out of memory";
+        return SPX_ENOMEM;
+    } catch (const std::exception& e) {
+        cleanup();
+        g_analyze_err = e.what();
+        return SPX_EDEVICE;
+    }
 }
 
 void spx_destroy(spx_handle* h) { delete h; }

@@ -165,11 +165,84 @@ __device__ __forceinline__ void gstore_s(const GOp& g, int voff, int soff, float
 // 128 accumulator registers and the operands exceed the 256 registers of a
 // wave at two workgroups per CU, and the spilled operands each cost a wait
 // for every outstanding load.
-// DS (L D L^T updates): acc += X (Y D)^T, the facing operand Y scaled by d_p
-// (element p of Dg at p * Dg.sk: the diagonal of the source panel) just
-// before the products, so its loads stay in flight with the others.
-template <int NB, class T, int RB = 4, bool DS = false>
-__device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K,
+template <int NB, class T, int RB = 4>
+__device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K)
+{
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nchunks = (K + 7) >> 3;
+    if (nchunks <= 0) return;
+    int xo[2][RB], yo[2][NB];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b) xo[u][b] = X.off + (16 * b + li) * X.si + (4 * u + lk) * X.sk;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) yo[u][b] = Y.off + (16 * b + li) * Y.si + (4 * u + lk) * Y.sk;
+    }
+    const int dx = 8 * X.sk, dy = 8 * Y.sk;
+    T xa[2][RB], ya[2][NB], xb[2][RB], yb[2][NB], xc[2][RB], yc[2][NB];
+    // (scheduling barriers keep every group of loads ahead of the products
+    // it is meant to overlap; left alone, the compiler sinks the FP32 loads
+    // next to their uses and waits for them)
+    auto load = [&](T (&xs)[2][RB], T (&ys)[2][NB], int ch) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) xs[u][b] = gload<T>(X, xo[u][b] + ch * dx);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) ys[u][b] = gload<T>(Y, yo[u][b] + ch * dy);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto mma = [&](const T (&xs)[2][RB], const T (&ys)[2][NB]) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < RB; ++bj) acc[bi][bj] = MM<T>::mfma(ys[u][bi], xs[u][bj], acc[bi][bj]);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // (reads past the last chunk repeat it and are not used)
+    const int last = nchunks - 1;
+    if constexpr (sizeof(T) == 8) {
+        (void)xc;
+        (void)yc;
+        load(xa, ya, 0);
+        int ch = 0;
+        for (; ch + 2 <= nchunks; ch += 2) {
+            load(xb, yb, ch + 1);
+            mma(xa, ya);
+            load(xa, ya, min(ch + 2, last));
+            mma(xb, yb);
+        }
+        if (ch < nchunks) mma(xa, ya);
+    } else {
+        load(xa, ya, 0);
+        load(xb, yb, min(1, last));
+        int ch = 0;
+        for (; ch + 3 <= nchunks; ch += 3) {
+            load(xc, yc, min(ch + 2, last));
+            mma(xa, ya);
+            load(xa, ya, min(ch + 3, last));
+            mma(xb, yb);
+            load(xb, yb, min(ch + 4, last));
+            mma(xc, yc);
+        }
+        if (ch < nchunks) mma(xa, ya);
+        if (ch + 1 < nchunks) mma(xb, yb);
+    }
+}
+
+// L D L^T update products: acc += X (Y D)^T, the facing operand Y scaled by
+// d_p (element p of Dg at p * Dg.sk: the diagonal of the source panel) just
+// before the products, so its loads stay in flight with the others; two
+// register buffers of 8 inner indices in both precisions (a separate
+// function: the extra operand registers would change the allocation of the
+// plain product, and a third FP32 buffer spills).
+template <int NB, class T, int RB = 4>
+__device__ __forceinline__ void wave_gemm_d(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K,
                                           const GOp& Dg)
 {
     const int lane = threadIdx.x & 63;
@@ -185,7 +258,7 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], co
         for (int b = 0; b < NB; ++b) yo[u][b] = Y.off + (16 * b + li) * Y.si + (4 * u + lk) * Y.sk;
     }
     const int dx = 8 * X.sk, dy = 8 * Y.sk;
-    T xa[2][RB], ya[2][NB], da[2], xb[2][RB], yb[2][NB], db[2], xc[2][RB], yc[2][NB], dc[2];
+    T xa[2][RB], ya[2][NB], da[2], xb[2][RB], yb[2][NB], db[2];
     // (scheduling barriers keep every group of loads ahead of the products
     // it is meant to overlap; left alone, the compiler sinks the FP32 loads
     // next to their uses and waits for them)
@@ -196,7 +269,7 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], co
             for (int b = 0; b < RB; ++b) xs[u][b] = gload<T>(X, xo[u][b] + ch * dx);
 #pragma unroll
             for (int b = 0; b < NB; ++b) ys[u][b] = gload<T>(Y, yo[u][b] + ch * dy);
-            if constexpr (DS) ds[u] = gload<T>(Dg, Dg.off + (8 * ch + 4 * u + lk) * Dg.sk);
+            ds[u] = gload<T>(Dg, Dg.off + (8 * ch + 4 * u + lk) * Dg.sk);
         }
         __builtin_amdgcn_sched_barrier(0);
     };
@@ -205,7 +278,7 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], co
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int bi = 0; bi < NB; ++bi) {
-                const T yv = DS ? ys[u][bi] * ds[u] : ys[u][bi];
+                const T yv = ys[u][bi] * ds[u];
 #pragma unroll
                 for (int bj = 0; bj < RB; ++bj) acc[bi][bj] = MM<T>::mfma(yv, xs[u][bj], acc[bi][bj]);
             }
@@ -213,34 +286,15 @@ __device__ __forceinline__ void wave_gemm(typename MM<T>::acc (&acc)[NB][RB], co
     };
     // (reads past the last chunk repeat it and are not used)
     const int last = nchunks - 1;
-    if constexpr (sizeof(T) == 8) {
-        (void)xc;
-        (void)yc;
-        (void)dc;
-        load(xa, ya, da, 0);
-        int ch = 0;
-        for (; ch + 2 <= nchunks; ch += 2) {
-            load(xb, yb, db, ch + 1);
-            mma(xa, ya, da);
-            load(xa, ya, da, min(ch + 2, last));
-            mma(xb, yb, db);
-        }
-        if (ch < nchunks) mma(xa, ya, da);
-    } else {
-        load(xa, ya, da, 0);
-        load(xb, yb, db, min(1, last));
-        int ch = 0;
-        for (; ch + 3 <= nchunks; ch += 3) {
-            load(xc, yc, dc, min(ch + 2, last));
-            mma(xa, ya, da);
-            load(xa, ya, da, min(ch + 3, last));
-            mma(xb, yb, db);
-            load(xb, yb, db, min(ch + 4, last));
-            mma(xc, yc, dc);
-        }
-        if (ch < nchunks) mma(xa, ya, da);
-        if (ch + 1 < nchunks) mma(xb, yb, db);
+    load(xa, ya, da, 0);
+    int ch = 0;
+    for (; ch + 2 <= nchunks; ch += 2) {
+        load(xb, yb, db, ch + 1);
+        mma(xa, ya, da);
+        load(xa, ya, da, min(ch + 2, last));
+        mma(xb, yb, db);
     }
+    if (ch < nchunks) mma(xa, ya, da);
 }
 
 // Split-BF16 products (FP32 panels): each FP32 operand x is split into
@@ -270,10 +324,64 @@ __device__ __forceinline__ void split_bf16(const float (&v)[4], s16x4& hi, s16x4
     lo = __builtin_bit_cast(s16x4, l);
 }
 
-// DS: the facing operand scaled by d_p in FP32 before it is split (as in
-// wave_gemm).
-template <int NB, int RB = 4, bool DS = false>
-__device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][RB], const GOp& X, const GOp& Y, int K, const GOp& Dg)
+template <int NB, int RB = 4>
+__device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][RB], const GOp& X, const GOp& Y, int K)
+{
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nchunks = (K + 15) >> 4;
+    if (nchunks <= 0) return;
+    int xo[RB], yo[NB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) xo[b] = X.off + (16 * b + li) * X.si + lk * X.sk;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) yo[b] = Y.off + (16 * b + li) * Y.si + lk * Y.sk;
+    const int dx = 4 * X.sk, dy = 4 * Y.sk;
+    float xa[RB][4], ya[NB][4], xb[RB][4], yb[NB][4];
+    auto load = [&](float (&xs)[RB][4], float (&ys)[NB][4], int ch) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) xs[b][s] = gload<float>(X, xo[b] + (4 * ch + s) * dx);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) ys[b][s] = gload<float>(Y, yo[b] + (4 * ch + s) * dy);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto mma = [&](const float (&xs)[RB][4], const float (&ys)[NB][4]) {
+        s16x4 xh[RB], xl[RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) split_bf16(xs[b], xh[b], xl[b]);
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+            s16x4 yh, yl;
+            split_bf16(ys[bi], yh, yl);
+#pragma unroll
+            for (int bj = 0; bj < RB; ++bj) {
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yh, xh[bj], acc[bi][bj], 0, 0, 0);
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yh, xl[bj], acc[bi][bj], 0, 0, 0);
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(yl, xh[bj], acc[bi][bj], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // (reads past the last chunk repeat it and are not used)
+    const int last = nchunks - 1;
+    load(xa, ya, 0);
+    int ch = 0;
+    for (; ch + 2 <= nchunks; ch += 2) {
+        load(xb, yb, ch + 1);
+        mma(xa, ya);
+        load(xa, ya, min(ch + 2, last));
+        mma(xb, yb);
+    }
+    if (ch < nchunks) mma(xa, ya);
+}
+
+// Split-BF16 L D L^T update products: the facing operand scaled by d_p in
+// FP32 before it is split (as in wave_gemm_d).
+template <int NB, int RB = 4>
+__device__ __forceinline__ void wave_gemm_split_d(f4 (&acc)[NB][RB], const GOp& X, const GOp& Y, int K, const GOp& Dg)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -294,7 +402,7 @@ __device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][RB], const GOp& X,
 #pragma unroll
             for (int b = 0; b < NB; ++b) ys[b][s] = gload<float>(Y, yo[b] + (4 * ch + s) * dy);
             // inner index 16 ch + 4 s + l/16
-            if constexpr (DS) ds[s] = gload<float>(Dg, Dg.off + (16 * ch + 4 * s + lk) * Dg.sk);
+            ds[s] = gload<float>(Dg, Dg.off + (16 * ch + 4 * s + lk) * Dg.sk);
         }
         __builtin_amdgcn_sched_barrier(0);
     };
@@ -307,7 +415,7 @@ __device__ __forceinline__ void wave_gemm_split(f4 (&acc)[NB][RB], const GOp& X,
             s16x4 yh, yl;
             float yv[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) yv[q] = DS ? ys[bi][q] * ds[q] : ys[bi][q];
+            for (int q = 0; q < 4; ++q) yv[q] = ys[bi][q] * ds[q];
             split_bf16(yv, yh, yl);
 #pragma unroll
             for (int bj = 0; bj < RB; ++bj) {
@@ -340,11 +448,13 @@ __device__ __forceinline__ void tile_gemm(typename MM<T>::acc (&acc)[NB][RB], co
 {
     if constexpr (sizeof(T) == 4) {
         if (split) {
-            wave_gemm_split<NB, RB, DS>(acc, X, Y, K, Dg);
+            if constexpr (DS) wave_gemm_split_d<NB, RB>(acc, X, Y, K, Dg);
+            else wave_gemm_split<NB, RB>(acc, X, Y, K);
             return;
         }
     }
-    wave_gemm<NB, T, RB, DS>(acc, X, Y, K, Dg);
+    if constexpr (DS) wave_gemm_d<NB, T, RB>(acc, X, Y, K, Dg);
+    else wave_gemm<NB, T, RB>(acc, X, Y, K);
 }
 template <int NB, class T, int RB = 4>
 __device__ __forceinline__ void tile_gemm(typename MM<T>::acc (&acc)[NB][RB], const GOp& X, const GOp& Y, int K, bool split)
@@ -407,6 +517,7 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
                                            double thr = 0.0)
 {
     static_assert(NC == 8 || NC == 16 || NC == 32, "tile width");
+    thr = readlane_d(thr, 0);   // wave-uniform: scalar registers, not two VGPRs for the whole loop
     const int lane = threadIdx.x & 63;
     const int r = lane & 31;
     const bool upper = lane >= 32;
@@ -424,7 +535,7 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
     auto pivot = [&](int c, double& s, double& inv) {
         double d = readlane_d(v[c], c);
         if constexpr (LDL) {
-            if (c < jb && fabs(d) < thr) {
+            if (c < jb && fabs(d) < thr) {   // static pivoting (a uniform branch)
                 d = d < 0.0 ? -thr : thr;
                 ++nrep;
             }
@@ -763,6 +874,7 @@ template <class T>
 __device__ __noinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, int ldy, int jb, int col0,
                                          int32_t* status, double thr)
 {
+    thr = readlane_d(thr, 0);   // wave-uniform: scalar registers
     const int lane = threadIdx.x & 63;
     const int r = lane & 31;
     const bool colh = lane >= 32;
@@ -772,12 +884,14 @@ __device__ __noinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, i
     int nrep = 0;
 #pragma unroll
     for (int c = 0; c < 32; ++c) {
-        double d = readlane_d(v[c], c);   // row lane c: u_cc
-        if (c < jb && fabs(d) < thr) {     // static pivoting: the pivot replaced in both copies
-            d = d < 0.0 ? -thr : thr;
-            if (r == c) v[c] = d;
-            ++nrep;
-        }
+        // row lane c: u_cc; static pivoting replaces it in both copies (row
+        // lane c and column lane c hold it); selects only, so that the loop
+        // stays fully unrolled and the arrays in registers
+        const double d0 = readlane_d(v[c], c);
+        const bool rp = c < jb && fabs(d0) < thr;
+        const double d = rp ? (d0 < 0.0 ? -thr : thr) : d0;
+        nrep += rp ? 1 : 0;
+        v[c] = r == c ? d : v[c];
         double y = __builtin_amdgcn_rcp(d);
         y = y * __builtin_fma(-d, y, 2.0);
         y = y * __builtin_fma(-d, y, 2.0);
@@ -1471,6 +1585,31 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         __syncthreads();
         if (tid == 0) s_rel = -1;
     }
+}
+
+// ---------------------------------------------------------------- update microbenchmark
+// The update tiles of one synthetic (source, target) pair, as a plain grid:
+// block b runs tile b % ntiles ({row0, mrows, col0, ncols}) of source 0 into
+// target 1 through the same task_update as the scheduler (row map base
+// mbase).  Several calls of the grid, or one grid of several calls, measure
+// the update kernel alone (the paper's update-kernel study).
+template <class T, bool LDL>
+__global__ void __launch_bounds__(kThreads, 2) update_bench_kernel(SchedArgs a, const int4* tiles, int ntiles, int mbase)
+{
+    __shared__ int rpos[256], cpos[128];
+    const int4 t = tiles[blockIdx.x % ntiles];
+    task_update<T, LDL, false>(a, int4{kUpdate, 0, 1, t.x}, int4{t.y, t.z, t.w, mbase}, rpos, cpos);
+}
+
+hipError_t launch_update_bench(const SchedArgs& a, bool f32, bool ldl, const int4* tiles, int ntiles, int mbase,
+                               int copies, hipStream_t s)
+{
+    const int grid = ntiles * copies;
+    if (f32 && ldl) update_bench_kernel<float, true><<<grid, kThreads, 0, s>>>(a, tiles, ntiles, mbase);
+    else if (f32) update_bench_kernel<float, false><<<grid, kThreads, 0, s>>>(a, tiles, ntiles, mbase);
+    else if (ldl) update_bench_kernel<double, true><<<grid, kThreads, 0, s>>>(a, tiles, ntiles, mbase);
+    else update_bench_kernel<double, false><<<grid, kThreads, 0, s>>>(a, tiles, ntiles, mbase);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- set-up kernels

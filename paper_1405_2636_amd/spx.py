@@ -78,7 +78,7 @@ class SymView(C.Structure):
 
 EXPORTED = ["spx_default_options", "spx_analyze", "spx_factorize", "spx_solve", "spx_get_info",
             "spx_export_symbolic", "spx_copy_factor", "spx_get_trace", "spx_destroy", "spx_strerror",
-            "spx_last_error", "spx_values_grad", "spx_analyze_batch", "spx_solve_noalloc"]
+            "spx_last_error", "spx_values_grad", "spx_analyze_batch", "spx_solve_noalloc", "spx_update_bench"]
 
 _lib = None
 
@@ -114,6 +114,9 @@ def load_library():
     L.spx_analyze_batch.argtypes = [C.c_int32, vp, vp, vp, vp, vp]
     L.spx_values_grad.restype = C.c_int
     L.spx_values_grad.argtypes = [vp, C.c_int32, vp, vp, C.c_int64, vp, vp]
+    L.spx_update_bench.restype = C.c_int
+    L.spx_update_bench.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, C.c_int32,
+                                   C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     L.spx_destroy.restype = None
     L.spx_destroy.argtypes = [vp]
     L.spx_strerror.restype = C.c_char_p
@@ -386,6 +389,31 @@ class Solver:
                                        C.c_void_p(grad.data_ptr()), _stream_ptr(stream))
         self._check(rc, "values_grad")
         return grad[:self.nnz]
+
+
+def update_bench(panels, rmap, n_inner, m, k, ldc, precision="fp64", method="llt", tile=0, calls=1, nstreams=1):
+    """The library's update-kernel microbenchmark (spx_update_bench): calls
+    updates C -= A B^T (L D L^T: A D B^T) of the synthetic source panel into
+    the target panel, both in the device tensor `panels` (float64 for
+    "fp64", float32 otherwise; layout in include/spx.h), through the int32
+    device row map `rmap`.  Returns the elapsed milliseconds."""
+    import torch
+    L = load_library()
+    if precision not in PRECISIONS or method not in ("llt", "ldlt"):
+        raise ValueError("precision or method")
+    want = torch.float64 if precision == "fp64" else torch.float32
+    if panels.dtype != want or not panels.is_cuda or not panels.is_contiguous():
+        raise ValueError("panels must be a contiguous %s device tensor" % want)
+    if rmap.dtype != torch.int32 or not rmap.is_cuda or rmap.numel() != m:
+        raise ValueError("rmap must be an int32 device tensor of m entries")
+    if panels.numel() < (n_inner + m) * n_inner + ldc * k:
+        raise ValueError("panels too small")
+    ms = C.c_double()
+    rc = L.spx_update_bench(PRECISIONS[precision], METHODS[method], n_inner, m, k, C.c_void_p(panels.data_ptr()),
+                            C.c_void_p(rmap.data_ptr()), ldc, tile, calls, nstreams, C.byref(ms))
+    if rc != 0:
+        raise SpxError(rc, L.spx_last_error(None).decode())
+    return ms.value
 
 
 def _solve_function():
