@@ -489,6 +489,21 @@ __device__ __forceinline__ void wave_store(const typename MM<T>::acc (&acc)[NB][
 }
 
 // ---------------------------------------------------------------- FACT(k)
+// 1/d from the hardware estimate and two Newton-Raphson steps
+__device__ __forceinline__ double recip_nr(double d)
+{
+    double y = __builtin_amdgcn_rcp(d);
+    y = y * __builtin_fma(-d, y, 2.0);
+    return y * __builtin_fma(-d, y, 2.0);
+}
+
+// The static pivoting threshold eps * max |a_ij| (0: off) sits in LDS after
+// the 64-entry broadcast buffer bc and the 32-entry pivot buffer of the
+// fused small items, written once by each worker at its start: a global
+// load at the start of every tile factorization would wait for memory
+// (each item begins with a cache invalidation) on the elimination chain.
+constexpr int kThrSlot = 3 * kNB;   // offset from bc
+
 // Cholesky factor and inverse of one 32x32 diagonal tile, in FP64, by one
 // wave.  Lt (column-major, ld 33) holds the lower triangle of the tile; rows
 // and columns >= jb hold the identity.  Lane r < 32 keeps row r of the tile,
@@ -512,12 +527,19 @@ __device__ __forceinline__ void wave_store(const typename MM<T>::acc (&acc)[NB][
 // unscaled value t of column c for its update (a_ri -= t l_ic) and stores
 // t / d (d itself on the diagonal); on the identity rows the same steps give
 // Y = D^{-1} L^{-1}.  Out: L (unit, d on the diagonal) in Lt, Y in Dt.
-template <class T, int NC = 32, bool LDL = false>
-__device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb, int col0, int32_t* status,
-                                           double thr = 0.0)
+//
+// Static pivoting (L D L^T): the common form (PIV false) only tracks the
+// smallest |d| (one min per column, beside the dependency chain) and
+// returns false before writing anything when it is below the threshold;
+// the tile, still intact in Lt, is then factored again by the form with the
+// replacement (PIV true).  With the test and replacement in every step, the
+// scalar registers of the loop spill and each step waits longer.
+template <class T, int NC, bool LDL, bool PIV>
+__device__ __noinline__ bool tile_chol_inv_k(double* Lt, double* bc, T* Dt, int jb, int col0, int32_t* status)
 {
     static_assert(NC == 8 || NC == 16 || NC == 32, "tile width");
-    thr = readlane_d(thr, 0);   // wave-uniform: scalar registers, not two VGPRs for the whole loop
+    const double thr = LDL ? readlane_d(bc[kThrSlot], 0) : 0.0;
+    double dmin = __builtin_inf();
     const int lane = threadIdx.x & 63;
     const int r = lane & 31;
     const bool upper = lane >= 32;
@@ -535,14 +557,15 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
     auto pivot = [&](int c, double& s, double& inv) {
         double d = readlane_d(v[c], c);
         if constexpr (LDL) {
-            if (c < jb && fabs(d) < thr) {   // static pivoting (a uniform branch)
-                d = d < 0.0 ? -thr : thr;
-                ++nrep;
+            if constexpr (PIV) {
+                if (c < jb && fabs(d) < thr) {   // static pivoting (a uniform branch)
+                    d = d < 0.0 ? -thr : thr;
+                    ++nrep;
+                }
+            } else {
+                dmin = fmin(dmin, fabs(d));   // (identity padding: pivots 1)
             }
-            // 1/d from the hardware estimate and two Newton-Raphson steps
-            double y = __builtin_amdgcn_rcp(d);
-            y = y * __builtin_fma(-d, y, 2.0);
-            y = y * __builtin_fma(-d, y, 2.0);
+            const double y = recip_nr(d);
             inv = y;
             s = d;
         } else {
@@ -583,6 +606,9 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
         // keep the scheduler from interleaving column steps (register pressure)
         __builtin_amdgcn_sched_barrier(0);
     }
+    if constexpr (LDL && !PIV) {
+        if (dmin < thr) return false;   // a pivot to replace: the caller runs the PIV form
+    }
     if constexpr (LDL) {   // breakdown: a zero or non-finite pivot among the first jb
         double dd = 0.0;
 #pragma unroll
@@ -601,6 +627,14 @@ __device__ __noinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb
 #pragma unroll
         for (int c = 0; c < NC; ++c) Dt[c + r * 33] = c >= r ? (T)v[c] : T(0);
     }
+    return true;
+}
+
+template <class T, int NC = 32, bool LDL = false>
+__device__ __forceinline__ void tile_chol_inv(double* Lt, double* bc, T* Dt, int jb, int col0, int32_t* status)
+{
+    if (!tile_chol_inv_k<T, NC, LDL, false>(Lt, bc, Dt, jb, col0, status))
+        tile_chol_inv_k<T, NC, LDL, true>(Lt, bc, Dt, jb, col0, status);
 }
 
 // Small product of the diagonal-block factorization: acc += X Y^T with
@@ -720,10 +754,6 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
     __shared__ int s_next;   // next trailing tile to deal
     __shared__ double dcur[kNB];   // (L D L^T) this step's pivots
     bool ready = false;      // Lt/Dt already hold this step's factored tile
-    // (L D L^T) static pivoting threshold
-    const double thr = LDL && a.pivot_eps > 0.0
-                           ? a.pivot_eps * __longlong_as_double(*reinterpret_cast<const long long*>(a.status + kStAmax))
-                           : 0.0;
     for (int J = 0; J < w; J += kNB) {
         const int jb = min(kNB, w - J);
         const int R = w - J - jb;   // rows below the tile inside the block
@@ -736,7 +766,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                                                     : (r == c ? 1.0 : 0.0);
             }
             __syncthreads();
-            if (wave == 0) tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jb, f + J, a.status, thr);
+            if (wave == 0) tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jb, f + J, a.status);
         }
         if (tid == 0) s_next = 0;
         __syncthreads();
@@ -824,7 +854,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
                         ldx, ldyd, mv, nv, cA, [&](int r, int c) { return r >= c; }, sub, [&](int r, int c, T v) {
                             if (r < jn && c < jn && c <= r) Lt[r + c * 33] = (double)v;
                         });
-                    tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jn, f + J + jb, a.status, thr);
+                    tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, jn, f + J + jb, a.status);
                 } else {
                     wave_mm_rmw<2, T>(
                         ldx, ldyd, mv, nv, cA, [&](int r, int c) { return i0 + r >= c0 + c; }, sub,
@@ -870,31 +900,39 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
 // strictly below the diagonal, U on and above), X in Dt (column-major, ld
 // 33), Y (rounded to T) in Yg[i + q*ldy] for q <= i < jb.  A zero or
 // non-finite pivot among the first jb records its column with atomicMin.
-template <class T>
-__device__ __noinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, int ldy, int jb, int col0,
-                                         int32_t* status, double thr)
+//
+// Static pivoting as in tile_chol_inv: the common form (PIV false) tracks
+// the smallest |u_cc| and returns false, with Lt intact, when one is below
+// the threshold; the PIV form replaces.
+template <class T, bool PIV>
+__device__ __noinline__ bool tile_lu_inv_k(double* Lt, double* bc, T* Dt, T* Yg, int ldy, int jb, int col0,
+                                           int32_t* status)
 {
-    thr = readlane_d(thr, 0);   // wave-uniform: scalar registers
+    const double thr = readlane_d(bc[kThrSlot], 0);
+    double dmin = __builtin_inf();
     const int lane = threadIdx.x & 63;
     const int r = lane & 31;
     const bool colh = lane >= 32;
     double v[32], invp[32];   // invp: the inverse pivots (uniform), for pass 2
 #pragma unroll
     for (int c = 0; c < 32; ++c) v[c] = colh ? Lt[c + r * 33] : Lt[r + c * 33];
-    int nrep = 0;
+    // PIV: a replaced pivot only changes 1/u_cc here (the entries u_cc of
+    // lanes r == c are not read again by the loop) and is written to the
+    // tile's diagonal after it (uniform selects: a branch in the body stops
+    // the full unroll and sends the arrays to scratch)
+    const double ithr = PIV ? recip_nr(thr) : 0.0;
+    uint32_t repmask = 0;
 #pragma unroll
     for (int c = 0; c < 32; ++c) {
-        // row lane c: u_cc; static pivoting replaces it in both copies (row
-        // lane c and column lane c hold it); selects only, so that the loop
-        // stays fully unrolled and the arrays in registers
-        const double d0 = readlane_d(v[c], c);
-        const bool rp = c < jb && fabs(d0) < thr;
-        const double d = rp ? (d0 < 0.0 ? -thr : thr) : d0;
-        nrep += rp ? 1 : 0;
-        v[c] = r == c ? d : v[c];
-        double y = __builtin_amdgcn_rcp(d);
-        y = y * __builtin_fma(-d, y, 2.0);
-        y = y * __builtin_fma(-d, y, 2.0);
+        const double d = readlane_d(v[c], c);   // row lane c: u_cc
+        double y = recip_nr(d);
+        if constexpr (PIV) {
+            const bool rp = c < jb && fabs(d) < thr;
+            y = rp ? (d < 0.0 ? -ithr : ithr) : y;
+            repmask |= rp ? 1u << c : 0u;
+        } else {
+            dmin = fmin(dmin, fabs(d));   // (identity padding: pivots 1)
+        }
         invp[c] = y;
         if (!colh && r > c) v[c] *= y;   // l_rc
         // row lanes: l_rc (meaningful for r > c); column lanes: u_cq
@@ -913,17 +951,23 @@ __device__ __noinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, i
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_sched_barrier(0);
     }
-    // breakdown: a zero or non-finite pivot among the first jb
+    if constexpr (!PIV) {
+        if (dmin < thr) return false;   // a pivot to replace: the caller runs the PIV form
+    }
+    // breakdown: a zero or non-finite pivot among the first jb (after replacement)
     double dd = 0.0;
 #pragma unroll
     for (int c = 0; c < 32; ++c) dd = (r == c) ? v[c] : dd;
+    const bool replaced = (repmask >> r) & 1u;
+    if (replaced) dd = dd < 0.0 ? -thr : thr;
     const bool bad = !colh && r < jb && !(dd != 0.0 && dd - dd == 0.0);
     const uint64_t m = __ballot(bad);
     if (lane == 0 && m) atomicMin(status, col0 + (int)__builtin_ctzll(m));
-    if (lane == 0 && nrep > 0) atomicAdd(status + kStReplaced, nrep);
+    if (lane == 0 && repmask) atomicAdd(status + kStReplaced, (int)__builtin_popcount(repmask));
     if (!colh) {
 #pragma unroll
         for (int c = 0; c < 32; ++c) Lt[r + c * 33] = v[c];
+        if (replaced) Lt[r + r * 33] = dd;
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     // pass 2: X (lanes < 32) and Y (lanes >= 32), column r of each
@@ -947,6 +991,15 @@ __device__ __noinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, i
         for (int c = 0; c < 32; ++c)
             if (c >= r && c < jb) Yg[c + (int64_t)r * ldy] = (T)v[c];
     }
+    return true;
+}
+
+template <class T>
+__device__ __forceinline__ void tile_lu_inv(double* Lt, double* bc, T* Dt, T* Yg, int ldy, int jb, int col0,
+                                            int32_t* status)
+{
+    if (!tile_lu_inv_k<T, false>(Lt, bc, Dt, Yg, ldy, jb, col0, status))
+        tile_lu_inv_k<T, true>(Lt, bc, Dt, Yg, ldy, jb, col0, status);
 }
 
 // L U factorization of the w x w diagonal block (w <= 256) of panel k, in
@@ -986,9 +1039,6 @@ __device__ __noinline__ void task_fact_lu(const SchedArgs& a, int k, double* Lt,
     double* bc = Lt + kNB * 33;
     __shared__ int s_next;
     bool ready = false;
-    const double thr = a.pivot_eps > 0.0
-                           ? a.pivot_eps * __longlong_as_double(*reinterpret_cast<const long long*>(a.status + kStAmax))
-                           : 0.0;
     for (int J = 0; J < w; J += kNB) {
         const int jb = min(kNB, w - J);
         const int R = w - J - jb;
@@ -998,7 +1048,7 @@ __device__ __noinline__ void task_fact_lu(const SchedArgs& a, int k, double* Lt,
                 Lt[r + c * 33] = (r < jb && c < jb) ? (double)A[(J + r) + (int64_t)(J + c) * ld] : (r == c ? 1.0 : 0.0);
             }
             __syncthreads();
-            if (wave == 0) tile_lu_inv<T>(Lt, bc, Dt, Y + J + (int64_t)J * w, w, jb, f + J, a.status, thr);
+            if (wave == 0) tile_lu_inv<T>(Lt, bc, Dt, Y + J + (int64_t)J * w, w, jb, f + J, a.status);
         }
         if (tid == 0) s_next = 0;
         __syncthreads();
@@ -1087,7 +1137,7 @@ __device__ __noinline__ void task_fact_lu(const SchedArgs& a, int k, double* Lt,
                         ldx, ldq, mv, nv, cA, [](int, int) { return true; }, sub, [&](int r, int c, T v) {
                             if (r < jn && c < jn) Lt[r + c * 33] = (double)v;
                         });
-                    tile_lu_inv<T>(Lt, bc, Dt, Y + (J + jb) + (int64_t)(J + jb) * w, w, jn, f + J + jb, a.status, thr);
+                    tile_lu_inv<T>(Lt, bc, Dt, Y + (J + jb) + (int64_t)(J + jb) * w, w, jn, f + J + jb, a.status);
                 } else {
                     wave_mm_rmw<2, T>(ldx, ldq, mv, nv, cA, [](int, int) { return true; }, sub, [](int, int, T) {});
                 }
@@ -1266,6 +1316,15 @@ __device__ __forceinline__ void push_pair(const SchedArgs& a, int p)
     }
 }
 
+// Deterministic mode: the pairs of source k lose their panel dependency
+// (all threads of the workgroup; out of line, so that the scheduler loop
+// does not keep its registers).
+__device__ __noinline__ void release_pairs(const SchedArgs& a, int k)
+{
+    for (int p = a.kpair[k] + threadIdx.x; p < a.kpair[k + 1]; p += kThreads)
+        if (__hip_atomic_fetch_add(&a.pdep[p], -1, __ATOMIC_RELAXED, AGENT) == 1) push_pair(a, p);
+}
+
 // Count down one update tile of target j (any lane); queue j when it was the
 // last one.
 __device__ __forceinline__ void finish_update(const SchedArgs& a, int j)
@@ -1343,15 +1402,12 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
     }
     __syncthreads();
     if (wave == 0) {
-        const double thr = LDL && a.pivot_eps > 0.0
-                               ? a.pivot_eps * __longlong_as_double(*reinterpret_cast<const long long*>(a.status + kStAmax))
-                               : 0.0;
         if (w <= 8)
-            tile_chol_inv<T, 8, LDL>(Lt, bc, Dt, w, f, a.status, thr);
+            tile_chol_inv<T, 8, LDL>(Lt, bc, Dt, w, f, a.status);
         else if (w <= 16)
-            tile_chol_inv<T, 16, LDL>(Lt, bc, Dt, w, f, a.status, thr);
+            tile_chol_inv<T, 16, LDL>(Lt, bc, Dt, w, f, a.status);
         else
-            tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, w, f, a.status, thr);
+            tile_chol_inv<T, 32, LDL>(Lt, bc, Dt, w, f, a.status);
     }
     __syncthreads();
     for (int idx = tid; idx < kNB * kNB; idx += kThreads) {
@@ -1420,7 +1476,7 @@ __device__ __noinline__ void task_small(const SchedArgs& a, const int4 d0, const
 template <class T, bool LDL = false, bool LU = false>
 __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
 {
-    __shared__ double Lt[kNB * 33 + 3 * kNB];
+    __shared__ double Lt[kNB * 33 + 3 * kNB + 1];   // tile, bc, small-item pivots, pivot threshold
     __shared__ T Dt[kNB * 33];
     __shared__ __align__(16) T Pb[kPbLd * kNB + 32];   // + padding: tile row indices up to 255; small-block tables
     __shared__ int rpos[256], cpos[128];
@@ -1438,7 +1494,13 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
     // Items served by this worker are counted in a register and added to the
     // done count once, at exit.
     int my_slot = -1, hp_slot = -1, ndone = 0;
-    if (tid == 0) s_rel = -1;
+    if (tid == 0) {
+        s_rel = -1;
+        double thr = 0.0;   // (read after the first barrier of the loop)
+        if ((LDL || LU) && a.pivot_eps > 0.0)
+            thr = a.pivot_eps * __longlong_as_double(*reinterpret_cast<const long long*>(a.status + kStAmax));
+        Lt[kNB * 33 + kThrSlot] = thr;
+    }
     for (;;) {
         if (tid == 0) {
             int item = -1;
@@ -1578,10 +1640,7 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         __syncthreads();
         if (s_push[1] > 0) push_items(a, true, s_push[2], s_push[0], s_push[1]);
         if (s_push[4] > 0) push_items(a, false, s_push[5], s_push[3], s_push[4]);
-        if (s_rel >= 0) {   // deterministic mode: the source's pairs lose their panel dependency
-            for (int p = a.kpair[s_rel] + tid; p < a.kpair[s_rel + 1]; p += kThreads)
-                if (__hip_atomic_fetch_add(&a.pdep[p], -1, __ATOMIC_RELAXED, AGENT) == 1) push_pair(a, p);
-        }
+        if (s_rel >= 0) release_pairs(a, s_rel);   // deterministic mode
         __syncthreads();
         if (tid == 0) s_rel = -1;
     }
