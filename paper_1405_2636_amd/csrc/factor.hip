@@ -46,6 +46,14 @@ __device__ __forceinline__ typename Glob<T>::type* glob(T* p)
 {
     return (typename Glob<T>::type*)p;
 }
+// A generic pointer known to point into LDS, as an LDS pointer (never null:
+// the cast then needs no null test)
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(3))) T* lds(T* p)
+{
+    if (p == nullptr) __builtin_unreachable();
+    return (__attribute__((address_space(3))) T*)p;
+}
 
 // The 16x16x4 matrix-core product of one element type.  Operand A lane l
 // holds A[l%16][l/16], operand B lane l holds B[l/16][l%16]; the four result
@@ -1233,8 +1241,13 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
 // RB = 1: a thin tile of an elimination chain, at most 64 x 64, each wave
 // 16 rows of it (a quarter of the work of a 64-row wave tile).
 template <class T, bool LDL = false, bool LU = false, int RB = 4>
-__device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos, int* cpos)
+__device__ __noinline__ void task_update(const SchedArgs& a, const int4 d0, const int4 d1, int* rpos_g, int* cpos_g)
 {
+    // the row and column maps are LDS arrays of the calling kernel: stated,
+    // so that their accesses are LDS operations without a generic-address
+    // test (whether the compiler derives it depends on the set of callers)
+    auto rpos = lds(rpos_g);
+    auto cpos = lds(cpos_g);
     const DevPlan& pl = a.pl;
     const int k = d0.y, j = d0.z, row0 = d0.w, np = ((d0.x >> 8) & 15) + 1;
     const int mrows = d1.x, col0 = d1.y, ncols = d1.z, mbase = d1.w;
