@@ -284,7 +284,8 @@ int spx_copy_factor(spx_handle* h, double* dst, int32_t dst_on_device, void* hip
 /* Task trace of the last factorization (trace option on): 4 int64 per work
  * item in dst {claimed, started, finished: device wall-clock ticks; hardware
  * id register of the executing wave}, and, if kinds is not NULL, 4 int32 per
- * item {kind 0 factor / 1 triangular solve / 2 update / 3 fused small block,
+ * item {kind 0 factor / 1 triangular solve / 2 update / 3 fused small block /
+ * 4 off-diagonal tiles of a chain block's inverse,
  * source cblk, target cblk, rows*cols of an update tile or rows of a solve
  * tile}.  cap = number of items dst can hold (info.ntasks).  Returns the
  * item count, or a negative status. */

@@ -139,6 +139,8 @@ struct spx_handle {
     DevBuf<int4> ftab;
     // deterministic mode: update pairs (see SchedArgs)
     int32_t npair = 0, ubase = 0;
+    int32_t ninv = 0;                 // INV items (chain blocks, L L^T)
+    DevBuf<int32_t> inv_item;
     DevBuf<int32_t> upair, kpair, pdep0, pdep, pleft;
     DevBuf<int4> pairs;
     DevBuf<int64_t> trace;   // per-item task trace, allocated when the trace option is on
@@ -303,6 +305,16 @@ void build_tasks(spx_handle* h)
     std::vector<char> chain(nc, 0);
     for (int32_t k = 0; k < nc; ++k)
         chain[k] = per_level[lvl[k]] <= kChainLevel && P.lcol[k] - P.fcol[k] + 1 >= 128;
+    // L L^T blocks of width >= 128 in levels of at most kInvLevel blocks
+    // (high priority): FACT stores L_kk and the diagonal tiles of its inverse
+    // only, the panel solves are block substitutions with those tiles (64
+    // rows, 16 per wave), and an INV item in the normal queue forms the rest
+    // of the inverse (needed by the triangular sweeps only): the chain runs
+    // through about half the FACT products and none of the inverse's
+    constexpr int kInvLevel = 1;
+    std::vector<char> inv(nc, 0);
+    for (int32_t k = 0; k < nc; ++k)
+        inv[k] = h->opt.method == SPX_LLT && hp[k] && per_level[lvl[k]] <= kInvLevel && P.lcol[k] - P.fcol[k] + 1 >= 128;
     // update tiles of source k into target group [b, b2) (blocks facing one
     // cblk), tr x tcl each
     auto for_tiles = [&](int32_t k, int32_t b, int32_t b2, int32_t tr, int32_t tcl, auto&& fn) {
@@ -384,9 +396,10 @@ void build_tasks(spx_handle* h)
         tf[k] = id;
         // 64 rows per wave tile (chains: 16); panels narrower than 256
         // columns stack 4/ceil(w/64) of them
-        const int32_t trows = (chain[k] ? 16 : kTrsmRows) * (4 / ((w + 63) / 64));
+        const int32_t trows = inv[k] ? 64 : (chain[k] ? 16 : kTrsmRows) * (4 / ((w + 63) / 64));
+        const int32_t tflag = inv[k] ? kSubstItem : (chain[k] ? kThinItem : 0);
         for (int32_t r = w; r < ld && !small[k]; r += trows) {
-            desc.push_back(int4{kTrsm | (chain[k] ? kThinItem : 0), k, r, std::min(trows, ld - r)});
+            desc.push_back(int4{kTrsm | tflag, k, r, std::min(trows, ld - r)});
             desc.push_back(int4{0, 0, 0, 0});
             ++id;
         }
@@ -472,12 +485,20 @@ void build_tasks(spx_handle* h)
         }
     }
     kpair[nc] = static_cast<int32_t>(pairs.size());
+    const int32_t uend = id;   // end of the update items
+    std::vector<int32_t> inv_item(nc, -1);
+    for (int32_t k = 0; k < nc; ++k)
+        if (inv[k] && !small[k]) {
+            desc.push_back(int4{kInv, k, 0, 0});
+            desc.push_back(int4{0, 0, 0, 0});
+            inv_item[k] = id++;
+        }
     h->total = id;
     h->npair = static_cast<int32_t>(pairs.size());
     h->ubase = ubase;
     if (det) {
         if (nsmall > 0) throw std::runtime_error("fused small items in the deterministic mode");
-        if (static_cast<int64_t>(upair.size()) != id - ubase) throw std::runtime_error("update items outside pairs");
+        if (static_cast<int64_t>(upair.size()) != uend - ubase) throw std::runtime_error("update items outside pairs");
         h->pairs.upload(pairs);
         h->kpair.upload(kpair);
         h->pdep0.upload(pdep0);
@@ -489,7 +510,7 @@ void build_tasks(spx_handle* h)
     h->nfused_tiles = static_cast<int32_t>(ftab.size() / 3);
     int64_t hp_items = nhp_upd;
     for (int32_t k = 0; k < nc; ++k)
-        if (hp[k]) hp_items += 1 + tc[k];
+        if (hp[k]) hp_items += 1 + tc[k];   // (INV items: normal queue)
     h->hp_total = static_cast<int32_t>(hp_items);
     h->total_normal = h->total - h->hp_total;
     std::vector<int32_t> ready;   // high-priority ones first
@@ -504,6 +525,9 @@ void build_tasks(spx_handle* h)
     if (ftab.empty()) ftab.push_back(int4{0, 0, 0, 0});
     h->ftab.upload(ftab);
     h->rmap.upload(rmap);
+    h->ninv = 0;
+    for (int32_t k = 0; k < nc; ++k) h->ninv += inv_item[k] >= 0 ? 1 : 0;
+    h->inv_item.upload(inv_item);
     h->trsm_first.upload(tf);
     h->trsm_count.upload(tc);
     h->upd_first.upload(uf);
@@ -742,6 +766,7 @@ SchedArgs sched_args(spx_handle* h)
     a.status = h->status.p;
     a.timeout_ticks = h->timeout_ticks;
     a.trace = h->opt.trace ? h->trace.p : nullptr;
+    a.inv_item = h->ninv > 0 ? h->inv_item.p : nullptr;
     a.npair = h->npair;
     a.ubase = h->ubase;
     a.upair = h->upair.p;

@@ -23,8 +23,9 @@ struct DevPlan {
 // Work-item kinds of the device scheduler (low byte of the first word; an
 // update keeps its merged piece count - 1 in bits 8..11; bit 12 marks a thin
 // TRSM or update item of an elimination chain: 16-row wave tiles).
-enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2, kSmall = 3 };
+enum ItemKind : int32_t { kFact = 0, kTrsm = 1, kUpdate = 2, kSmall = 3, kInv = 4 };
 constexpr int32_t kThinItem = 1 << 12;
+constexpr int32_t kSubstItem = 1 << 13;   // TRSM of a chain block: substitution with the diagonal tiles of D
 
 // Two int4 per item: {kind, k, a, b}, {c, d, e, f}
 //   kFact:   k
@@ -33,6 +34,7 @@ constexpr int32_t kThinItem = 1 << 12;
 //            mrows, col0 (first facing panel row), ncols, mbase (row-map base)
 //   kSmall:  k; first tile of k in the fused-tile table, tile count, first
 //            row-map entry of k, row-map entries of k
+//   kInv:    k (the off-diagonal tiles of L_kk^{-1} after a FACT that left them)
 // Fused-tile table: three int4 per update tile of a fused block,
 //   {j, row0, mrows, col0}, {ncols, mbase, stride of j, 0},
 //   {panel offset of j: low word, high word, 0, 0}
@@ -69,6 +71,10 @@ struct SchedArgs {
     // Deterministic mode (npair > 0): the update items of one (source,
     // target) pair are released when the source's panel solves are done and
     // the previous pair into the same target (ascending source) has finished.
+    // Blocks of elimination chains (L L^T): FACT leaves the off-diagonal tiles
+    // of the inverse to an INV item, released with the panel solves (which
+    // use the diagonal tiles only) and off the chain.
+    const int32_t* inv_item;   // INV item of block k, or -1 (FACT computes the whole inverse)
     int32_t npair;          // update pairs (0: any-order mode)
     int32_t ubase;          // id of the first update item
     const int32_t* upair;   // pair of update item ubase + i

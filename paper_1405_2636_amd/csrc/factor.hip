@@ -762,6 +762,9 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
     __shared__ int s_next;   // next trailing tile to deal
     __shared__ double dcur[kNB];   // (L D L^T) this step's pivots
     bool ready = false;      // Lt/Dt already hold this step's factored tile
+    // the off-diagonal tiles of the inverse here, or (a chain block with an
+    // INV item) only its diagonal tiles, D_JJ
+    const bool full = LDL || a.inv_item == nullptr || a.inv_item[k] < 0;
     for (int J = 0; J < w; J += kNB) {
         const int jb = min(kNB, w - J);
         const int R = w - J - jb;   // rows below the tile inside the block
@@ -802,7 +805,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
         }
         // 2b. block row J of D for columns < J (transposed: rows c of the
         // product are columns of D), each wave a 64-column slice, in place
-        for (int c0 = 64 * wave; c0 < J; c0 += 64 * (kThreads / 64)) {
+        for (int c0 = 64 * wave; full && c0 < J; c0 += 64 * (kThreads / 64)) {
             acc_t acc[2][4];
             zero_acc(acc);
             // with jb < 32 (last step) the inner indices p >= jb read entries
@@ -824,7 +827,7 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
         const int nrt = (R + 63) >> 6, ncs = (R + 31) >> 5, nci = (J + jb + 31) >> 5;
         int nsyrk = 0;
         for (int rt = 0; rt < nrt; ++rt) nsyrk += min(ncs, 2 * rt + 2);
-        const int ntiles = nsyrk + nrt * nci;
+        const int ntiles = nsyrk + (full ? nrt * nci : 0);
         const int jn = min(kNB, R);   // width of the next tile
         for (;;) {
             int t = 0;
@@ -886,6 +889,69 @@ __device__ __noinline__ void task_fact(const SchedArgs& a, int k, double* Lt, T*
         }
         __syncthreads();
         ready = true;
+    }
+}
+
+// ---------------------------------------------------------------- INV(k)
+// The off-diagonal tiles of D = L_kk^{-1} after a FACT that stored L_kk and
+// the diagonal tiles D_JJ = L_JJ^{-1} only (blocks of elimination chains: the
+// inverse is then built beside the chain instead of inside FACT).  Block
+// forward substitution on L D = I, column block c of D at a time:
+//   D_Jc = -D_JJ (sum_{c <= K < J} L_JK D_Kc),   J = c+1 .. nb-1,
+// one column block per wave (c = wave, wave + 4, ...).  Per step: S = the
+// sum (32 x 32, inner dimension 32 (J - c), operands read from the panel and
+// from D, the D_Kc written by this wave's earlier steps), S to LDS, then
+// -D_JJ S on the matrix cores, written to D.  Rows of a partial last block
+// beyond w only reach results that are not stored (operands past the
+// arrays read zeros).
+template <class T>
+__device__ __noinline__ void task_inv(const SchedArgs& a, int k, T* Pb)
+{
+    typedef typename MM<T>::acc acc_t;
+    const DevPlan& pl = a.pl;
+    const int w = pl.lcol[k] - pl.fcol[k] + 1;
+    const int64_t ld = pl.stride[k];
+    const T* A = static_cast<const T*>(a.panels) + pl.panel_off[k];
+    T* D = static_cast<T*>(a.dinv) + pl.dinv_off[k];
+    const int nb = (w + kNB - 1) / kNB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    T* Sl = Pb + wave * (kNB * 33);   // this wave's S (32 x 32, ld 33)
+    for (int c = wave; c + 1 < nb; c += kThreads / 64) {
+        for (int J = c + 1; J < nb; ++J) {
+            // S(r, q) = sum_p L(32J + r, 32c + p) D(32c + p, 32c + q)
+            acc_t acc[2][2];
+            zero_acc(acc);
+            wave_gemm<2, T, 2>(acc, make_gop(A, ld * w, kNB * J + (int64_t)kNB * c * ld, 1, ld),
+                               make_gop(D, (int64_t)w * w, kNB * c + (int64_t)kNB * c * w, w, 1), kNB * (J - c));
+            wave_store<T>(acc, kNB, kNB, [&](int r, int q, T v) { Sl[r + q * 33] = v; });
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);   // (LDS operations of a wave complete in order)
+            // D_Jc(r, q) = -sum_t D_JJ(r, t) S(t, q)
+            const GOp gJ = make_gop(D, (int64_t)w * w, kNB * J + (int64_t)kNB * J * w, 1, w);
+            acc_t acc2[2][2];
+            zero_acc(acc2);
+#pragma unroll
+            for (int st = 0; st < kNB / 4; ++st) {
+                const int t = 4 * st + lk;
+                T xs[2], ys[2];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    xs[b] = gload<T>(gJ, gJ.off + (16 * b + li) * gJ.si + t * gJ.sk);
+                    ys[b] = Sl[t + (16 * b + li) * 33];
+                }
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj) acc2[bi][bj] = MM<T>::mfma(ys[bi], xs[bj], acc2[bi][bj]);
+            }
+            const int jb = min(kNB, w - kNB * J);
+            wave_store<T>(acc2, jb, kNB, [&](int r, int q, T v) {
+                D[(kNB * J + r) + (int64_t)(kNB * c + q) * w] = -v;
+            });
+            // this wave's next steps read D_Jc: stores complete before their loads
+            __builtin_amdgcn_s_waitcnt(0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
     }
 }
 
@@ -1220,6 +1286,115 @@ __device__ __noinline__ void task_trsm(const SchedArgs& a, int k, int row0, int 
     if (on)
         wave_store<T>(acc, min(TR, nrows - r0), nv,
                       [&](int r, int c, T v) { B[(r0 + r) + (int64_t)(c0 + c) * ld] = v; });
+}
+
+// Rows [row0, row0+nrows) (nrows <= 64) of a chain block's panel below its
+// diagonal block, by block forward substitution with the diagonal tiles of
+// the inverse only (the rest of L_kk^{-1} is formed beside the chain, by the
+// INV item):
+//   X_J = (B_J - sum_{K<J} X_K L_JK^T) D_JJ^T,   J = 0 .. NBK-1   (X = B L_kk^{-T}),
+// wave v taking rows 16v .. 16v+15.  The finished column blocks X_K stay in
+// registers in the operand layout of the products (xop[K][s] = X(r, 32K + 4s
+// + l/16), r = l%16); each new block passes once through LDS from the
+// result layout to the operand layout.  NBK = number of 32-column blocks
+// (every loop fully unrolled: a branch in them sends xop to scratch).
+// Entries past a partial last block read zeros (operands past the arrays)
+// or finite panel entries that only meet zeros of D.
+template <class T, int NBK>
+__device__ __noinline__ void task_trsm_subst(const SchedArgs& a, int k, int row0, int nrows, T* Pb)
+{
+    typedef typename MM<T>::acc acc_t;
+    const DevPlan& pl = a.pl;
+    const int w = pl.lcol[k] - pl.fcol[k] + 1;
+    const int64_t ld = pl.stride[k];
+    T* P = static_cast<T*>(a.panels) + pl.panel_off[k];
+    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int r0 = 16 * wave;
+    if (r0 >= nrows) return;
+    const int mv = min(16, nrows - r0);
+    const GOp gP = make_gop(P, ld * w, row0 + r0, 1, ld);   // rows of this wave: X(r, j) at r + j*ld
+    const GOp gL = make_gop(P, ld * w, 0, 1, ld);           // L_kk(i, j) at i + j*ld
+    const GOp gD = make_gop(D, (int64_t)w * w, 0, 1, w);    // D(i, j) at i + j*w
+    T* Sl = Pb + wave * (kNB * 17);   // this wave's 16 x 32 staging block (ld 17)
+    T xop[NBK][8];
+#pragma unroll
+    for (int J = 0; J < NBK; ++J) {
+        acc_t acc[2][1];
+        zero_acc(acc);
+        // the block of B, in the result layout: row li, column 16 bi + drow(v, l/16)
+        T bj[2][4];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                bj[bi][v] = gload<T>(gP, gP.off + li * gP.si + (kNB * J + 16 * bi + MM<T>::drow(v, lk)) * gP.sk);
+        // S = sum_{K<J} X_K L_JK^T: Y(c, p) = L(32J + c, 32K + p), X(r, p) = X_K
+#pragma unroll
+        for (int K = 0; K < J; ++K) {
+            T y0[8], y1[8];
+#pragma unroll
+            for (int st = 0; st < 8; ++st) {
+                const int pcol = kNB * K + 4 * st + lk;
+                y0[st] = gload<T>(gL, (kNB * J + li) * gL.si + pcol * gL.sk);
+                y1[st] = gload<T>(gL, (kNB * J + 16 + li) * gL.si + pcol * gL.sk);
+            }
+#pragma unroll
+            for (int st = 0; st < 8; ++st) {
+                acc[0][0] = MM<T>::mfma(y0[st], xop[K][st], acc[0][0]);
+                acc[1][0] = MM<T>::mfma(y1[st], xop[K][st], acc[1][0]);
+            }
+        }
+        // T_J = B_J - S, to the operand layout through LDS
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Sl[li + (16 * bi + MM<T>::drow(v, lk)) * 17] = bj[bi][v] - acc[bi][0][v];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);   // (LDS operations of a wave complete in order)
+        T tj[8];
+#pragma unroll
+        for (int st = 0; st < 8; ++st) tj[st] = Sl[li + (4 * st + lk) * 17];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // X_J = T_J D_JJ^T: Y(c, t) = D(32J + c, 32J + t)
+        acc_t acc2[2][1];
+        zero_acc(acc2);
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int t = kNB * J + 4 * st + lk;
+            const T d0 = gload<T>(gD, (kNB * J + li) * gD.si + t * gD.sk);
+            const T d1 = gload<T>(gD, (kNB * J + 16 + li) * gD.si + t * gD.sk);
+            acc2[0][0] = MM<T>::mfma(d0, tj[st], acc2[0][0]);
+            acc2[1][0] = MM<T>::mfma(d1, tj[st], acc2[1][0]);
+        }
+        // X_J to the panel and, in the operand layout, to xop[J]
+        auto out = glob(P);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = 16 * bi + MM<T>::drow(v, lk);
+                const T x = acc2[bi][0][v];
+                Sl[li + c * 17] = x;
+                if (li < mv && kNB * J + c < w) out[(row0 + r0 + li) + (int64_t)(kNB * J + c) * ld] = x;
+            }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+        for (int st = 0; st < 8; ++st) xop[J][st] = Sl[li + (4 * st + lk) * 17];
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void trsm_subst(const SchedArgs& a, int k, int row0, int nrows, T* Pb)
+{
+    switch ((a.pl.lcol[k] - a.pl.fcol[k] + kNB) / kNB) {
+    case 4: task_trsm_subst<T, 4>(a, k, row0, nrows, Pb); break;
+    case 5: task_trsm_subst<T, 5>(a, k, row0, nrows, Pb); break;
+    case 6: task_trsm_subst<T, 6>(a, k, row0, nrows, Pb); break;
+    case 7: task_trsm_subst<T, 7>(a, k, row0, nrows, Pb); break;
+    default: task_trsm_subst<T, 8>(a, k, row0, nrows, Pb); break;
+    }
 }
 
 // ---------------------------------------------------------------- UPDATE
@@ -1579,13 +1754,24 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
                     task_trsm<T>(a, d0.y, d0.z, d0.w, a.upanel, 0);
                 }
             } else {
-                if (thin) task_trsm<T, 1>(a, d0.y, d0.z, d0.w);
-                else task_trsm<T>(a, d0.y, d0.z, d0.w);
+                if (d0.x & kSubstItem) {
+                    if constexpr (!LDL) trsm_subst<T>(a, d0.y, d0.z, d0.w, Pb);
+                } else if (thin) {
+                    task_trsm<T, 1>(a, d0.y, d0.z, d0.w);
+                } else {
+                    task_trsm<T>(a, d0.y, d0.z, d0.w);
+                }
             }
             __builtin_amdgcn_s_setprio(0);
         } else if (kind == kUpdate) {
             if (thin) task_update<T, LDL, LU, 1>(a, d0, d1, rpos, cpos);
             else task_update<T, LDL, LU>(a, d0, d1, rpos, cpos);
+        } else if (kind == kInv) {
+            if constexpr (!LDL && !LU) {
+                __builtin_amdgcn_s_setprio(2);
+                task_inv<T>(a, d0.y, Pb);
+                __builtin_amdgcn_s_setprio(0);
+            }
         } else if constexpr (!LU) {
             task_small<T, LDL>(a, d0, d1, Lt, Dt, Pb);
         }
@@ -1594,13 +1780,17 @@ __global__ void __launch_bounds__(kThreads, 2) sched_kernel(SchedArgs a)
         // elimination chain and share their CU with update tiles)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (tid < 64 && (kind == kFact || kind == kTrsm)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (tid < 64 && (kind == kFact || kind == kTrsm || kind == kInv)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (tid == 0) {
             int hf = 0, hc = 0, nf = 0, nc = 0;
             if (kind == kFact) {
+                // the panel solves; a chain block (high priority) also its
+                // INV item, in the normal queue
                 if (a.hp_cblk[d0.y]) {
                     hf = a.trsm_first[d0.y];
                     hc = a.trsm_count[d0.y];
+                    const int ii = a.inv_item ? a.inv_item[d0.y] : -1;
+                    if (ii >= 0) { nf = ii; nc = 1; }
                 } else {
                     nf = a.trsm_first[d0.y];
                     nc = a.trsm_count[d0.y];
