@@ -311,7 +311,7 @@ void build_tasks(spx_handle* h)
     // rows, 16 per wave), and an INV item in the normal queue forms the rest
     // of the inverse (needed by the triangular sweeps only): the chain runs
     // through about half the FACT products and none of the inverse's
-    constexpr int kInvLevel = 1;
+    constexpr int kInvLevel = 4;
     std::vector<char> inv(nc, 0);
     for (int32_t k = 0; k < nc; ++k)
         inv[k] = h->opt.method == SPX_LLT && hp[k] && per_level[lvl[k]] <= kInvLevel && P.lcol[k] - P.fcol[k] + 1 >= 128;
