@@ -158,6 +158,10 @@ typedef struct spx_info {
                                * A = (-1)^nneg); 0 for SPX_LLT */
     int32_t pivots_replaced;  /* SPX_LDLT, SPX_LU: pivots replaced by static pivoting in the
                                * last factorization (see static_pivot_eps) */
+    int32_t solve_levels;     /* dependency levels of each triangular sweep */
+    int32_t solve_pairs;      /* pairs of consecutive pieces of split supernodes solved as one
+                               * block in the sweeps (SPX_LLT, SPX_LU; on levels of at most 16
+                               * blocks): each pair's inverse is formed after the factorization */
 } spx_info;
 
 typedef struct spx_solve_info {

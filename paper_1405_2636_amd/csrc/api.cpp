@@ -33,10 +33,12 @@ int sched_blocks_per_cu(bool f32, bool ldlt, bool lu);
 hipError_t launch_sched(const SchedArgs& a, bool f32, bool lu, int grid, hipStream_t s);
 hipError_t launch_update_bench(const SchedArgs& a, bool f32, bool ldl, const int4* tiles, int ntiles, int mbase,
                                int copies, hipStream_t s);
-hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s);
-hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
-hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s);
-hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s);
+hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s);
+hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s);
+hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s);
+hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s);
+hipError_t launch_pair_inv(const void* panels, void* dinv, bool f32, const PairItem* items, int count, int maxnb,
+                           hipStream_t s);
 hipError_t launch_fwd_small(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
 hipError_t launch_bwd_small(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
 hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,
@@ -105,9 +107,13 @@ struct Level {
     std::vector<int32_t> cptr;   // cblks of level l: cblk[cptr[l]..cptr[l+1])
     std::vector<int32_t> cblk;   // (each level's small blocks first: cblk[cptr[l]..cptr[l]+nsmall[l]))
     std::vector<int32_t> nsmall; // blocks of width <= 32 with at most 128 panel rows, per level
-    std::vector<int32_t> maxw;   // widest cblk of level l
-    std::vector<int32_t> kptr;   // chunks of level l
-    std::vector<int2> chunk;
+    std::vector<int32_t> dptr;   // diagonal items of level l: ditem[dptr[l]..dptr[l+1])
+    std::vector<DiagItem> ditem;
+    std::vector<uint8_t> narrow; // level l's diagonal items are 16-row parts (16 lanes per row), else 64-row
+    std::vector<int32_t> kptr;   // off-diagonal items of level l: chunk[kptr[l]..kptr[l+1])
+    std::vector<OffItem> chunk;
+    std::vector<PairItem> pair;  // paired pieces (one unit of the sweeps each)
+    int32_t maxnb = 0;           // widest pair in 16-column blocks, plus one
 };
 
 }  // namespace spx
@@ -147,7 +153,9 @@ struct spx_handle {
     // levels for the sweeps
     Level lv;
     DevBuf<int32_t> lv_cblk;
-    DevBuf<int2> lv_chunk;
+    DevBuf<DiagItem> lv_ditem;
+    DevBuf<OffItem> lv_chunk;
+    DevBuf<PairItem> lv_pair;
     // numeric: FP64 panels and inverses, or their FP32 counterparts
     DevBuf<double> panels, dinv, vals, rv;   // rv: values in the order of the residual's row lists
     DevBuf<float> panels_f, dinv_f;
@@ -545,49 +553,150 @@ void build_tasks(spx_handle* h)
 
 // Dependency levels for the sweeps: level(k) = 1 + max level of the cblks
 // updating k.  Off-diagonal rows are cut into chunks of 64 rows.
-void build_levels(spx_handle* h)
+// Pairs: on the narrow levels (at most kPairLevel blocks: the elimination
+// chains of the split separators, one piece per level), consecutive pieces
+// p, q = p + 1 of a split supernode are solved as one block through the
+// pair's inverse (built after each factorization): the chain's levels, each
+// a diagonal and an off-diagonal launch bound by latency, are halved.  p's
+// rows facing q are then covered by the pair's inverse, so p's off-diagonal
+// items start below q's rows.  (Not for L D L^T, whose sweeps scale by the
+// pivots of each piece.)
+void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::vector<int64_t>& rgo)
 {
     const Plan& P = h->plan;
     const int32_t nc = P.ncblk;
-    std::vector<int32_t> lvl(nc, 0);
-    int32_t nl = nc > 0 ? 1 : 0;
-    for (int32_t k = 0; k < nc; ++k) {
-        for (int32_t q = P.uptr[k]; q < P.uptr[k + 1]; ++q) {
-            const int32_t j = P.utgt[q];
-            lvl[j] = std::max(lvl[j], lvl[k] + 1);
+    auto width = [&](int32_t k) { return P.lcol[k] - P.fcol[k] + 1; };
+    auto small = [&](int32_t k) { return width(k) <= kNB && P.stride[k] <= kSmallRows; };
+    // levels over units (a unit: a cblk, or a pair led by its first piece)
+    std::vector<int32_t> unit(nc);
+    for (int32_t k = 0; k < nc; ++k) unit[k] = k;
+    auto levels = [&](std::vector<int32_t>& lvl) {
+        lvl.assign(nc, 0);
+        int32_t nl = nc > 0 ? 1 : 0;
+        for (int32_t k = 0; k < nc; ++k) {
+            const int32_t uk = unit[k];
+            for (int32_t q = P.uptr[k]; q < P.uptr[k + 1]; ++q) {
+                const int32_t uj = unit[P.utgt[q]];
+                if (uj != uk) lvl[uj] = std::max(lvl[uj], lvl[uk] + 1);
+            }
+            nl = std::max(nl, lvl[uk] + 1);
         }
-        nl = std::max(nl, lvl[k] + 1);
+        return nl;
+    };
+    std::vector<int32_t> lvl;
+    int32_t nl = levels(lvl);
+    std::vector<int32_t> pairs;   // first pieces of the pairs
+    if (h->opt.method != SPX_LDLT && nc > 1) {
+        constexpr int32_t kPairLevel = 16;
+        std::vector<int32_t> pop(nl, 0);
+        for (int32_t k = 0; k < nc; ++k) ++pop[lvl[k]];
+        std::vector<int32_t> snof(nc);
+        for (int32_t k = 0; k < nc; ++k)
+            snof[k] = static_cast<int32_t>(std::upper_bound(P.snptr.begin(), P.snptr.end(), P.fcol[k]) -
+                                           P.snptr.begin()) - 1;
+        for (int32_t k0 = 0; k0 < nc;) {
+            int32_t k1 = k0;
+            while (k1 + 1 < nc && snof[k1 + 1] == snof[k0]) ++k1;
+            bool any_small = false;
+            for (int32_t k = k0; k <= k1; ++k) any_small = any_small || small(k);
+            for (int32_t k = k0; k + 1 <= k1 && !any_small; k += 2)
+                if (pop[lvl[k]] <= kPairLevel && pop[lvl[k + 1]] <= kPairLevel &&
+                    width(k) + width(k + 1) <= kMaxPairWidth && P.stride[k] == P.stride[k + 1] + width(k)) {
+                    unit[k + 1] = k;
+                    pairs.push_back(k);
+                }
+            k0 = k1 + 1;
+        }
+        if (!pairs.empty()) nl = levels(lvl);
     }
+    // pair inverses after the pieces' own, in each side's inverse region
     Level& L = h->lv;
     L = Level();
+    std::vector<int64_t> pofs(nc, -1);
+    int64_t dsz = doff[nc];
+    for (int32_t p : pairs) {
+        const int64_t W = width(p) + width(p + 1);
+        pofs[p] = dsz;
+        L.pair.push_back(PairItem{P.panel_off[p] + width(p), doff[p], doff[p + 1], dsz, P.stride[p], width(p),
+                                  width(p + 1), 0});
+        L.maxnb = std::max(L.maxnb, static_cast<int32_t>((W + 15) / 16 + 1));
+        dsz += W * W;
+    }
+    h->dinv_size = dsz;
     L.cptr.assign(nl + 1, 0);
-    for (int32_t k = 0; k < nc; ++k) ++L.cptr[lvl[k] + 1];
+    for (int32_t k = 0; k < nc; ++k)
+        if (unit[k] == k) ++L.cptr[lvl[k] + 1];
     for (int32_t l = 0; l < nl; ++l) L.cptr[l + 1] += L.cptr[l];
-    L.cblk.resize(nc);
+    L.cblk.resize(L.cptr[nl]);
     // small blocks (one 16-lane group each in the sweeps) first in their level
-    auto small = [&](int32_t k) { return P.lcol[k] - P.fcol[k] + 1 <= kNB && P.stride[k] <= kSmallRows; };
     L.nsmall.assign(nl, 0);
     std::vector<int32_t> pos(L.cptr.begin(), L.cptr.end() - 1);
     for (int32_t k = 0; k < nc; ++k)
-        if (small(k)) {
+        if (small(k) && unit[k] == k) {
             L.cblk[pos[lvl[k]]++] = k;
             ++L.nsmall[lvl[k]];
         }
     for (int32_t k = 0; k < nc; ++k)
-        if (!small(k)) L.cblk[pos[lvl[k]]++] = k;
-    L.kptr.assign(nl + 1, 0);
-    L.maxw.assign(nl, 1);
+        if (!small(k) && unit[k] == k) L.cblk[pos[lvl[k]]++] = k;
+    // diagonal items: 16-row parts on levels with fewer than kNarrowLevel
+    // blocks (16 lanes per row: fewer dependent load rounds), else 64-row
+    constexpr int32_t kNarrowLevel = 64;
+    L.dptr.assign(nl + 1, 0);
+    L.narrow.assign(nl, 0);
     for (int32_t l = 0; l < nl; ++l) {
+        const int32_t nb = L.cptr[l + 1] - L.cptr[l] - L.nsmall[l];
+        L.narrow[l] = nb < kNarrowLevel ? 1 : 0;
+        const int32_t rows = L.narrow[l] ? 16 : 64;
         for (int32_t q = L.cptr[l] + L.nsmall[l]; q < L.cptr[l + 1]; ++q) {
             const int32_t k = L.cblk[q];
-            const int32_t w = P.lcol[k] - P.fcol[k] + 1;
-            L.maxw[l] = std::max(L.maxw[l], w);
-            for (int32_t r = w; r < P.stride[k]; r += 64) L.chunk.push_back(int2{k, r});
+            const bool pr = pofs[k] >= 0;
+            const int32_t w = pr ? width(k) + width(k + 1) : width(k);
+            for (int32_t r0 = 0; r0 < w; r0 += rows)
+                L.ditem.push_back(DiagItem{pr ? pofs[k] : doff[k], P.panel_off[k], P.fcol[k], w, r0, P.stride[k]});
+        }
+        L.dptr[l + 1] = static_cast<int32_t>(L.ditem.size());
+    }
+    // off-diagonal items: up to 64 rows by a column range.  A level with
+    // fewer than kOffTarget 64-row chunks splits the columns of each chunk
+    // into 64-column parts (as many as bring the level towards kOffTarget
+    // workgroups): the top levels hold one or two column blocks, and one
+    // workgroup per 64 rows would leave most compute units idle while each
+    // walks its columns serially.
+    constexpr int64_t kOffTarget = 1024;
+    L.kptr.assign(nl + 1, 0);
+    std::vector<int32_t> members;
+    for (int32_t l = 0; l < nl; ++l) {
+        // the blocks of the level's units, with the first off-diagonal row of each
+        members.clear();
+        for (int32_t q = L.cptr[l] + L.nsmall[l]; q < L.cptr[l + 1]; ++q) {
+            const int32_t k = L.cblk[q];
+            members.push_back(k);
+            if (pofs[k] >= 0) members.push_back(k + 1);
+        }
+        auto first_row = [&](int32_t k) { return pofs[k] >= 0 ? width(k) + width(k + 1) : width(k); };
+        int64_t nch = 0;
+        for (int32_t k : members) nch += (P.stride[k] - first_row(k) + 63) / 64;
+        const int64_t want = nch > 0 ? (kOffTarget + nch - 1) / nch : 1;
+        for (int32_t k : members) {
+            const int32_t w = width(k);
+            const int32_t units = (w + 63) / 64;
+            const int32_t parts = static_cast<int32_t>(std::min<int64_t>(units, std::max<int64_t>(1, want)));
+            const int32_t pw = 64 * ((units + parts - 1) / parts);
+            for (int32_t r = first_row(k); r < P.stride[k]; r += 64) {
+                const int32_t nr = std::min(64, P.stride[k] - r);
+                for (int32_t c0 = 0; c0 < w; c0 += pw) {
+                    const int32_t c1 = std::min(w, c0 + pw);
+                    L.chunk.push_back(OffItem{P.panel_off[k] + r, rgo[k] + (r - w), P.stride[k], P.fcol[k], r,
+                                              c0 | (c1 << 9) | (nr << 18)});
+                }
+            }
         }
         L.kptr[l + 1] = static_cast<int32_t>(L.chunk.size());
     }
     h->lv_cblk.upload(L.cblk);
+    h->lv_ditem.upload(L.ditem);
     h->lv_chunk.upload(L.chunk);
+    h->lv_pair.upload(L.pair);
 }
 
 void upload_plan(spx_handle* h)
@@ -648,7 +757,7 @@ void upload_plan(spx_handle* h)
         h->ecol.upload(ec);
     }
     build_tasks(h);
-    build_levels(h);
+    build_levels(h, doff, rgo);
     for (auto& e : h->ev)
         if (!e) HIPCHK(hipEventCreate(&e));
     int ncu = 0, clk_khz = 0;
@@ -695,17 +804,17 @@ void sweeps(spx_handle* h, const SweepBufs& w, int32_t nrhs, hipStream_t s)
     const int nl = static_cast<int>(L.cptr.size()) - 1;
     for (int l = 0; l < nl; ++l) {
         const int32_t* sm = h->lv_cblk.p + L.cptr[l];
-        const int ns = L.nsmall[l], nb = L.cptr[l + 1] - L.cptr[l] - ns;
+        const int ns = L.nsmall[l];
         HIPCHK(launch_fwd_small(a, sm, ns, s));
-        HIPCHK(launch_fwd_diag(a, sm + ns, nb, L.maxw[l], s));
+        HIPCHK(launch_fwd_diag(a, h->lv_ditem.p + L.dptr[l], L.dptr[l + 1] - L.dptr[l], L.narrow[l] != 0, s));
         HIPCHK(launch_fwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
     }
     HIPCHK(launch_fill_f64(w.tacc, static_cast<int64_t>(h->n) * nrhs, 0.0, s));
     for (int l = nl - 1; l >= 0; --l) {
         const int32_t* sm = h->lv_cblk.p + L.cptr[l];
-        const int ns = L.nsmall[l], nb = L.cptr[l + 1] - L.cptr[l] - ns;
+        const int ns = L.nsmall[l];
         HIPCHK(launch_bwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
-        HIPCHK(launch_bwd_diag(a, sm + ns, nb, L.maxw[l], s));
+        HIPCHK(launch_bwd_diag(a, h->lv_ditem.p + L.dptr[l], L.dptr[l + 1] - L.dptr[l], L.narrow[l] != 0, s));
         HIPCHK(launch_bwd_small(a, sm, ns, s));
     }
 }
@@ -778,6 +887,22 @@ SchedArgs sched_args(spx_handle* h)
     return a;
 }
 
+// The inverses of the paired pieces of the sweeps, from the factor (for
+// L U also from the U^T panels and U_kk^{-T}, for the backward sweep).
+void pair_part(spx_handle* h, hipStream_t s)
+{
+    const Level& L = h->lv;
+    if (L.pair.empty()) return;
+    const bool f32 = h->f32();
+    const size_t esz = f32 ? sizeof(float) : sizeof(double);
+    const int np = static_cast<int>(L.pair.size());
+    HIPCHK(launch_pair_inv(h->panel_ptr(), h->dinv_ptr(), f32, h->lv_pair.p, np, L.maxnb, s));
+    if (h->lu())
+        HIPCHK(launch_pair_inv(static_cast<const char*>(h->panel_ptr()) + h->plan.panel_entries * esz,
+                               static_cast<char*>(h->dinv_ptr()) + h->dinv_size * esz, f32, h->lv_pair.p, np, L.maxnb,
+                               s));
+}
+
 // One factorization of the values in h->vals: eagerly, or (graph option) by
 // replaying the captured sequence (captured on first use and after any
 // change of the work decomposition); then the status read-back.
@@ -799,6 +924,7 @@ void run_factorization(spx_handle* h, hipStream_t s)
         else factor_part(h, part, s);
     }
     HIPCHK(hipEventRecord(h->ev[2], s));
+    pair_part(h, s);
     const Plan& P = h->plan;
     int32_t sw[kStatusWords];
     HIPCHK(hipMemcpyAsync(sw, h->status.p, sizeof sw, hipMemcpyDeviceToHost, s));
@@ -1233,6 +1359,8 @@ int spx_get_info(const spx_handle* hc, spx_info* info)
         o.logdet = h->logdet_valid ? h->logdet : 0.0;
         o.nneg = h->logdet_valid ? h->nneg : 0;
         o.pivots_replaced = h->factorized ? h->nrep : 0;
+        o.solve_levels = h->lv.cptr.empty() ? 0 : static_cast<int32_t>(h->lv.cptr.size()) - 1;
+        o.solve_pairs = static_cast<int32_t>(h->lv.pair.size());
         o.factor_kernel_ms = h->factor_ms;
         o.assemble_ms = h->assemble_ms;
         o.tile_rows = h->tile_rows;

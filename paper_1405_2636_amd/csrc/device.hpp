@@ -106,6 +106,37 @@ struct SweepArgs {
     int32_t nrhs;
 };
 
+// Work items of the sweeps, built once per analysis.  Each holds everything
+// its workgroup needs to address its part of the factor and the vectors,
+// so that the loads of the panel, the kept inverse and the vectors go out
+// together after one scalar load of the item (instead of behind a chain of
+// dependent loads through the plan arrays).
+struct DiagItem {          // rows (forward) or columns (backward) r0 .. of the diagonal block of k
+    int64_t dofs;          // start of k's kept inverse (w x w, column-major)
+    int64_t pofs;          // start of k's panel (L D L^T: d_c at pofs + c * (ld + 1))
+    int32_t f, w, r0, ld;  // first column of k, its width, first row of the part, panel stride
+};
+struct OffItem {           // panel rows row0 .. row0 + nr - 1 of k by the columns c0 .. c1 - 1
+    int64_t pofs;          // panel element (row0, 0) of k
+    int64_t gofs;          // position of panel row row0's global row in the row list
+    int32_t ld, f, row0;   // panel stride, first column of k, first panel row
+    int32_t cnr;           // c0 | c1 << 9 | nr << 18 (widths are at most 256, nr at most 64)
+};
+
+// Two consecutive pieces p, q of a split supernode solved as one block in
+// the sweeps: the pair's inverse [[D_p, 0], [X, D_q]] with
+// X = -D_q L_qp D_p (the inverse of the block lower-triangular diagonal
+// block of the pair; D_p, D_q the pieces' kept inverses, L_qp the rows of
+// p's panel that face q), stored column-major with leading dimension
+// W = w_p + w_q after the pieces' own inverses.
+constexpr int kMaxPairWidth = 512;   // widest diagonal block of the sweeps (a pair of pieces)
+struct PairItem {
+    int64_t lofs;          // panel element (w_p, 0) of p: L_qp, w_q x w_p, stride ldp
+    int64_t dp, dq;        // kept inverses of p and q
+    int64_t out;           // the pair's inverse
+    int32_t ldp, wp, wq, pad;
+};
+
 // Scheduler counters and status words sit 256 bytes apart: every worker
 // polls the queue heads and the abort flag, and a shared line would put the
 // polls in the way of the claims.

@@ -36,7 +36,7 @@
 
 namespace spx {
 
-constexpr int kChunk = 64;   // off-diagonal rows per chunk of the level lists
+constexpr int kChunk = 64;     // off-diagonal rows per chunk of the level lists
 
 // sum over the LANES consecutive lanes of a group (LANES = 4 or 16)
 template <int LANES>
@@ -56,26 +56,26 @@ __device__ __forceinline__ double group_sum(double v)
 // entries: a value read from unwritten LDS may be NaN)
 
 // ---- forward, diagonal block: z_k = D y_k, D = L_kk^{-1} (lower, w x w,
-// column-major).  LANES lanes per row, 256/LANES rows per workgroup
-// (workgroup g of a block: rows g*256/LANES ..); lane q of a row takes the
+// column-major).  LANES lanes per row, one workgroup per item: the rows
+// r0 .. r0 + 256/LANES - 1 of one block; lane q of a row takes the
 // columns p = q, q+LANES, ..., sixteen loads at a time (p > row clamped and
 // multiplied by zero).  Narrow levels (few blocks) use 16 lanes: fewer
-// dependent load rounds; wide levels 4.  grid = blocks * parts.
+// dependent load rounds; wide levels 4 (the items of a level are cut to
+// match).
 template <class T, int LANES, int NR>
-__global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblks, int parts)
+__global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const DiagItem* items)
 {
-    constexpr int ROWS = 256 / LANES;
-    __shared__ double ys[256 * NR];
-    const int k = cblks[blockIdx.x / parts];
-    const DevPlan& pl = a.pl;
-    const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
-    const int r0 = ROWS * (blockIdx.x % parts);
-    if (r0 >= w) return;
-    const T* D = static_cast<const T*>(a.dinv) + pl.dinv_off[k];
+    __shared__ double ys[kMaxPairWidth * NR];
+    const DiagItem it = items[blockIdx.x];
+    const int f = it.f, w = it.w, r0 = it.r0;
+    const T* D = static_cast<const T*>(a.dinv) + it.dofs;
     const int tid = threadIdx.x, q = tid % LANES, row = min(r0 + tid / LANES, w - 1);
     const T* Dr = D + row;
     for (int rb = 0; rb < a.nrhs; rb += NR) {
         const int nv = min(NR, a.nrhs - rb);
+        T d[16];   // the first sixteen loads are issued before the staging barrier
+#pragma unroll
+        for (int u = 0; u < 16; ++u) d[u] = Dr[(int64_t)min(q + LANES * u, row) * w];
         for (int idx = tid; idx < w * NR; idx += 256) {
             const int c = idx / NR, j = idx - c * NR;
             ys[idx] = j < nv ? a.y[(int64_t)(rb + j) * a.n + f + c] : 0.0;
@@ -85,9 +85,10 @@ __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblk
 #pragma unroll
         for (int j = 0; j < NR; ++j) v[j] = 0.0;
         for (int pb = 0; pb <= row; pb += 16 * LANES) {
-            T d[16];
+            if (pb != 0) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) d[u] = Dr[(int64_t)min(pb + q + LANES * u, row) * w];
+                for (int u = 0; u < 16; ++u) d[u] = Dr[(int64_t)min(pb + q + LANES * u, row) * w];
+            }
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int p = pb + q + LANES * u;
@@ -106,29 +107,34 @@ __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const int32_t* cblk
 }
 
 // ---- forward, off-diagonal rows: y[g(r)] -= sum_c L[r, c] z_k[c].  One
-// workgroup per chunk of 64 rows: lane = row (each load covers 64
-// consecutive rows of one column), wave v = quarter v of the columns (at
-// most 64, issued 16 at a time); the four partial sums meet in LDS.
+// workgroup per item: up to 64 panel rows from row0 by the columns
+// c0..c1-1 (levels with few row chunks split each chunk's columns over
+// several items so that the launch fills the chip; their partial sums meet
+// in the atomics).  Lane = row (each load covers 64 consecutive rows of one
+// column), wave v = quarter v of the columns, issued 16 at a time, the
+// first sixteen before the staging barrier; the four partial sums meet in
+// LDS.
 template <class T, int NR>
-__global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
+__global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const OffItem* items)
 {
     __shared__ double zk[256 * NR];
     __shared__ double part[4 * 64 * NR];
-    const int2 it = chunks[blockIdx.x];
-    const int k = it.x, row0 = it.y;
-    const DevPlan& pl = a.pl;
-    const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
-    const int64_t ld = pl.stride[k];
-    const int nr = min(kChunk, (int)ld - row0);
+    const OffItem it = items[blockIdx.x];
+    const int f = it.f, c0 = it.cnr & 511, c1 = (it.cnr >> 9) & 511, nr = it.cnr >> 18;
+    const int64_t ld = it.ld;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = min(lane, nr - 1);
-    const int qw = (w + 3) >> 2, cb = wave * qw, ce = min(w, cb + qw);
-    const T* Lr = static_cast<const T*>(a.panels) + pl.panel_off[k] + row0 + r;
-    const T* Pd = static_cast<const T*>(a.panels) + pl.panel_off[k];   // d_c at c * (ld + 1) (L D L^T)
+    const int gi = a.rowg[it.gofs + r];   // global row of the lane's panel row (read ahead of the products)
+    const int qw = (c1 - c0 + 3) >> 2, cb = c0 + wave * qw, ce = min(c1, cb + qw);
+    const T* Lr = static_cast<const T*>(a.panels) + it.pofs + r;
+    const T* Pd = static_cast<const T*>(a.panels) + (it.pofs - it.row0);   // d_c at c * (ld + 1) (L D L^T)
     for (int rb = 0; rb < a.nrhs; rb += NR) {
         const int nv = min(NR, a.nrhs - rb);
-        for (int idx = tid; idx < w * NR; idx += 256) {
-            const int c = idx / NR, j = idx - c * NR;
+        T l[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) l[u] = Lr[(int64_t)min(cb + u, c1 - 1) * ld];
+        for (int idx = tid; idx < (c1 - c0) * NR; idx += 256) {
+            const int c = c0 + idx / NR, j = idx % NR;
             zk[idx] = j < nv ? a.z[(int64_t)(rb + j) * a.n + f + c] * (a.ldlt ? (double)Pd[c * (ld + 1)] : 1.0) : 0.0;
         }
         __syncthreads();
@@ -136,13 +142,14 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
 #pragma unroll
         for (int j = 0; j < NR; ++j) v[j] = 0.0;
         for (int c = cb; c < ce; c += 16) {
-            T l[16];
+            if (c != cb) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) l[u] = Lr[(int64_t)min(c + u, ce - 1) * ld];
+                for (int u = 0; u < 16; ++u) l[u] = Lr[(int64_t)min(c + u, ce - 1) * ld];
+            }
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const double lv = c + u < ce ? (double)l[u] : 0.0;
-                const double* zc = zk + min(c + u, w - 1) * NR;
+                const double* zc = zk + (min(c + u, ce - 1) - c0) * NR;
 #pragma unroll
                 for (int j = 0; j < NR; ++j) v[j] += lv * zc[j];
             }
@@ -151,7 +158,6 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
         for (int j = 0; j < NR; ++j) part[(wave * 64 + lane) * NR + j] = v[j];
         __syncthreads();
         if (wave == 0 && lane < nr) {
-            const int gi = a.rowg[a.rowg_off[k] + (row0 - w) + lane];
             for (int j = 0; j < nv; ++j) {
                 const double sum = (part[lane * NR + j] + part[(64 + lane) * NR + j]) +
                                    (part[(128 + lane) * NR + j] + part[(192 + lane) * NR + j]);
@@ -163,36 +169,41 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const int2* chunks)
 }
 
 // ---- backward, off-diagonal rows: tacc[f + c] += sum_r L[r, c] x[g(r)].
-// One workgroup per chunk of 64 rows; four lanes per column (columns
-// tid/4, tid/4 + 64, ...), lane q takes the rows q, q+4, ..., q+60 with all
-// sixteen loads in flight; each load instruction covers four consecutive
-// rows of sixteen columns.
+// One workgroup per item (the forward kernel's items);
+// four lanes per column (columns c0 + tid/4, c0 + tid/4 + 64, ...), lane q
+// takes the rows q, q+4, ..., q+60 with all sixteen loads in flight, the
+// first block's before the staging barrier; each load instruction covers
+// four consecutive rows of sixteen columns.
 template <class T, int NR>
-__global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
+__global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const OffItem* items)
 {
     __shared__ double xr[kChunk * NR];
-    const int2 it = chunks[blockIdx.x];
-    const int k = it.x, row0 = it.y;
-    const DevPlan& pl = a.pl;
-    const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
-    const int64_t ld = pl.stride[k];
-    const int nr = min(kChunk, (int)ld - row0);
-    const int32_t* g = a.rowg + a.rowg_off[k] + (row0 - w);
+    const OffItem it = items[blockIdx.x];
+    const int f = it.f, c0 = it.cnr & 511, c1 = (it.cnr >> 9) & 511, nr = it.cnr >> 18;
+    const int64_t ld = it.ld;
+    const int32_t* g = a.rowg + it.gofs;
     const int tid = threadIdx.x, q = tid & 3;
-    const T* L = static_cast<const T*>(a.panels_b) + pl.panel_off[k] + row0;
+    const T* L = static_cast<const T*>(a.panels_b) + it.pofs;
     for (int rb = 0; rb < a.nrhs; rb += NR) {
         const int nv = min(NR, a.nrhs - rb);
+        T l[16];
+        {
+            const T* Lc = L + (int64_t)min(c0 + (tid >> 2), c1 - 1) * ld;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) l[u] = Lc[min(q + 4 * u, nr - 1)];
+        }
         for (int idx = tid; idx < nr * NR; idx += 256) {
-            const int r = idx / NR, j = idx - r * NR;
+            const int r = idx / NR, j = idx % NR;
             xr[idx] = j < nv ? a.x[(int64_t)(rb + j) * a.n + g[r]] : 0.0;
         }
         __syncthreads();
-        for (int cb = 0; cb < w; cb += 64) {
-            const int c = min(cb + (tid >> 2), w - 1);
-            const T* Lc = L + (int64_t)c * ld;
-            T l[16];
+        for (int cb = c0; cb < c1; cb += 64) {
+            const int c = min(cb + (tid >> 2), c1 - 1);
+            if (cb != c0) {
+                const T* Lc = L + (int64_t)c * ld;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) l[u] = Lc[min(q + 4 * u, nr - 1)];
+                for (int u = 0; u < 16; ++u) l[u] = Lc[min(q + 4 * u, nr - 1)];
+            }
             double v[NR];
 #pragma unroll
             for (int j = 0; j < NR; ++j) v[j] = 0.0;
@@ -205,7 +216,7 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
             }
 #pragma unroll
             for (int j = 0; j < NR; ++j) v[j] = group_sum<4>(v[j]);
-            if (cb + (tid >> 2) < w && q == 0)
+            if (cb + (tid >> 2) < c1 && q == 0)
                 for (int j = 0; j < nv; ++j) unsafeAtomicAdd(a.tacc + (int64_t)(rb + j) * a.n + f + c, v[j]);
         }
         __syncthreads();
@@ -214,24 +225,24 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const int2* chunks)
 
 // ---- backward, diagonal block: x_k = D^T (z_k - t_k); LANES lanes per
 // column c of D, lane q takes the rows p = c+q, c+q+LANES, ... (p >= w
-// clamped and multiplied by zero); same grid as the forward kernel
+// clamped and multiplied by zero); the forward kernel's items, columns
+// r0 .. r0 + 256/LANES - 1
 template <class T, int LANES, int NR>
-__global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblks, int parts)
+__global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const DiagItem* items)
 {
-    constexpr int ROWS = 256 / LANES;
-    __shared__ double zs[256 * NR];
-    const int k = cblks[blockIdx.x / parts];
-    const DevPlan& pl = a.pl;
-    const int f = pl.fcol[k], w = pl.lcol[k] - f + 1;
-    const int c0 = ROWS * (blockIdx.x % parts);
-    if (c0 >= w) return;
-    const T* D = static_cast<const T*>(a.dinv_b) + pl.dinv_off[k];
+    __shared__ double zs[kMaxPairWidth * NR];
+    const DiagItem it = items[blockIdx.x];
+    const int f = it.f, w = it.w, c0 = it.r0;
+    const T* D = static_cast<const T*>(a.dinv_b) + it.dofs;
     const int tid = threadIdx.x, q = tid % LANES, col = min(c0 + tid / LANES, w - 1);
     const T* Dc = D + (int64_t)col * w;
-    const T* Pd = static_cast<const T*>(a.panels) + pl.panel_off[k];   // d_c at c * (ld + 1) (L D L^T)
-    const int64_t ld = pl.stride[k];
+    const T* Pd = static_cast<const T*>(a.panels) + it.pofs;   // d_c at c * (ld + 1) (L D L^T)
+    const int64_t ld = it.ld;
     for (int rb = 0; rb < a.nrhs; rb += NR) {
         const int nv = min(NR, a.nrhs - rb);
+        T d[16];   // the first sixteen loads are issued before the staging barrier
+#pragma unroll
+        for (int u = 0; u < 16; ++u) d[u] = Dc[min(col + q + LANES * u, w - 1)];
         for (int idx = tid; idx < w * NR; idx += 256) {
             const int c = idx / NR, j = idx - c * NR;
             const int64_t o = (int64_t)(rb + j) * a.n + f + c;
@@ -242,9 +253,10 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const int32_t* cblk
 #pragma unroll
         for (int j = 0; j < NR; ++j) v[j] = 0.0;
         for (int pb = col; pb < w; pb += 16 * LANES) {
-            T d[16];
+            if (pb != col) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) d[u] = Dc[min(pb + q + LANES * u, w - 1)];
+                for (int u = 0; u < 16; ++u) d[u] = Dc[min(pb + q + LANES * u, w - 1)];
+            }
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int p = pb + q + LANES * u;
@@ -568,11 +580,120 @@ __global__ void values_grad_kernel(const int32_t* erow, const int32_t* ecol, int
     }
 }
 
+// ---- inverses of paired pieces (built after the factorization): the pair's
+// inverse [[D_p, 0], [X, D_q]], X = -D_q (L_qp D_p), on the matrix cores
+// (16x16x4 products; operand A lane l holds A[l%16][l/16], operand B lane l
+// holds B[l/16][l%16], result slot v of lane l holds D[row(v, l/16)][l%16]).
+// Workgroup (pair, jb): for jb < ceil(w_p/16) the columns j0 = 16 jb ..
+// j0 + 15 of p: D_p's columns staged in LDS (zero above the diagonal) and
+// copied, T = L_qp D_p[:, cols] (inner indices from j0: D_p is lower
+// triangular) into LDS, then X[:, cols] = -D_q T (inner indices up to each
+// row tile's end: D_q is lower triangular); for the remaining jb the columns
+// of q: zeros above, D_q below.  Each wave takes the 16-row tiles
+// wave, wave + 4, ...; the loads of sixteen inner steps go out together.
+template <class T>
+struct PairMM;
+template <>
+struct PairMM<double> {
+    typedef double acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc mfma(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int v, int lk) { return 4 * v + lk; }
+};
+template <>
+struct PairMM<float> {
+    typedef float acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc mfma(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
+};
+
+constexpr int kPairLd = 17;   // LDS leading dimension of the staged 16-column blocks
+
+template <class T>
+__global__ void __launch_bounds__(256) pair_inv(const T* panels, T* dinv, const PairItem* items)
+{
+    typedef typename PairMM<T>::acc acc;
+    __shared__ T dps[256 * kPairLd];   // D_p[kk][n]
+    __shared__ T ts[256 * kPairLd];    // T[kk][n]
+    const PairItem it = items[blockIdx.x];
+    const int wp = it.wp, wq = it.wq, W = wp + wq;
+    const int nbp = (wp + 15) / 16, nbq = (wq + 15) / 16;
+    const int jb = blockIdx.y;
+    if (jb >= nbp + nbq) return;
+    T* P = dinv + it.out;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    if (jb >= nbp) {
+        const int j0 = 16 * (jb - nbp);
+        const T* Dq = dinv + it.dq;
+        for (int idx = tid; idx < 16 * W; idx += 256) {
+            const int j = j0 + idx / W, r = idx % W;
+            if (j < wq) P[(int64_t)(wp + j) * W + r] = (r >= wp + j) ? Dq[(int64_t)j * wq + (r - wp)] : T(0);
+        }
+        return;
+    }
+    const int j0 = 16 * jb;
+    const T* Dp = dinv + it.dp;
+    for (int idx = tid; idx < 16 * wp; idx += 256) {
+        const int c = idx / wp, r = idx % wp, j = j0 + c;
+        const T v = (j < wp && r >= j) ? Dp[(int64_t)j * wp + r] : T(0);
+        dps[r * kPairLd + c] = v;
+        if (j < wp) P[(int64_t)j * W + r] = v;
+    }
+    __syncthreads();
+    const int ntile = (wq + 15) / 16;
+    const T* Lq = panels + it.lofs;   // L_qp[i][kk] at Lq[i + kk * ldp]
+    const int64_t ldp = it.ldp;
+    for (int t = wave; t < ntile; t += 4) {
+        acc c = {0, 0, 0, 0};
+        const int i = min(16 * t + li, wq - 1);
+        for (int kk0 = j0; kk0 < wp; kk0 += 64) {
+            T av[16], bv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int kk = kk0 + 4 * u + lk;
+                av[u] = Lq[i + (int64_t)min(kk, wp - 1) * ldp];
+                bv[u] = kk < wp ? dps[kk * kPairLd + li] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) c = PairMM<T>::mfma(av[u], bv[u], c);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ts[(16 * t + PairMM<T>::row(v, lk)) * kPairLd + li] = c[v];
+    }
+    __syncthreads();
+    const T* Dq = dinv + it.dq;   // D_q[i][kk] at Dq[i + kk * wq]
+    for (int t = wave; t < ntile; t += 4) {
+        acc c = {0, 0, 0, 0};
+        const int irow = 16 * t + li, i = min(irow, wq - 1);
+        const int kend = min(16 * t + 16, wq);
+        for (int kk0 = 0; kk0 < kend; kk0 += 64) {
+            T av[16], bv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int kk = kk0 + 4 * u + lk;
+                const T d = Dq[i + (int64_t)min(kk, wq - 1) * wq];
+                av[u] = kk <= irow ? d : T(0);
+                bv[u] = kk < kend ? ts[kk * kPairLd + li] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) c = PairMM<T>::mfma(av[u], bv[u], c);
+        }
+        if (j0 + li < wp)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * t + PairMM<T>::row(v, lk);
+                if (r < wq) P[(int64_t)(j0 + li) * W + wp + r] = -c[v];
+            }
+    }
+}
+
 // ---- host launchers
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
-
-// levels with fewer blocks than this use 16 lanes per row in the diagonal kernels
-constexpr int kNarrowLevel = 64;
 
 // right-hand sides per pass over a panel: 1, 4 or 8 (16-lane small-block
 // kernels, whose lanes each keep up to 8 rows: 1 or 2)
@@ -585,48 +706,55 @@ static int nr_block(int nrhs) { return nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 8); }
         else { constexpr int NR = 8; CALL; } \
     } while (0)
 
-hipError_t launch_fwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s)
+hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     const int nrv = nr_block(a.nrhs);
-    if (count < kNarrowLevel) {
-        const int parts = (maxw + 15) / 16;
-        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 16, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)
-                                    : fwd_diag<double, 16, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)));
+    if (narrow) {
+        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 16, NR><<<count, 256, 0, s>>>(a, items)
+                                    : fwd_diag<double, 16, NR><<<count, 256, 0, s>>>(a, items)));
     } else {
-        const int parts = (maxw + 63) / 64;
-        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 4, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)
-                                    : fwd_diag<double, 4, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)));
+        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 4, NR><<<count, 256, 0, s>>>(a, items)
+                                    : fwd_diag<double, 4, NR><<<count, 256, 0, s>>>(a, items)));
     }
     return hipGetLastError();
 }
-hipError_t launch_fwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s)
+hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? fwd_off<float, NR><<<count, 256, 0, s>>>(a, chunks)
-                                             : fwd_off<double, NR><<<count, 256, 0, s>>>(a, chunks)));
+    SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? fwd_off<float, NR><<<count, 256, 0, s>>>(a, items)
+                                             : fwd_off<double, NR><<<count, 256, 0, s>>>(a, items)));
     return hipGetLastError();
 }
-hipError_t launch_bwd_off(const SweepArgs& a, const int2* chunks, int count, hipStream_t s)
+hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, NR><<<count, 256, 0, s>>>(a, chunks)
-                                             : bwd_off<double, NR><<<count, 256, 0, s>>>(a, chunks)));
+    SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, NR><<<count, 256, 0, s>>>(a, items)
+                                             : bwd_off<double, NR><<<count, 256, 0, s>>>(a, items)));
     return hipGetLastError();
 }
-hipError_t launch_bwd_diag(const SweepArgs& a, const int32_t* cblks, int count, int maxw, hipStream_t s)
+hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     const int nrv = nr_block(a.nrhs);
-    if (count < kNarrowLevel) {
-        const int parts = (maxw + 15) / 16;
-        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 16, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)
-                                    : bwd_diag<double, 16, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)));
+    if (narrow) {
+        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 16, NR><<<count, 256, 0, s>>>(a, items)
+                                    : bwd_diag<double, 16, NR><<<count, 256, 0, s>>>(a, items)));
     } else {
-        const int parts = (maxw + 63) / 64;
-        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 4, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)
-                                    : bwd_diag<double, 4, NR><<<parts * count, 256, 0, s>>>(a, cblks, parts)));
+        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 4, NR><<<count, 256, 0, s>>>(a, items)
+                                    : bwd_diag<double, 4, NR><<<count, 256, 0, s>>>(a, items)));
     }
+    return hipGetLastError();
+}
+hipError_t launch_pair_inv(const void* panels, void* dinv, bool f32, const PairItem* items, int count, int maxnb,
+                          hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const dim3 grid(count, maxnb);
+    if (f32)
+        pair_inv<float><<<grid, 256, 0, s>>>(static_cast<const float*>(panels), static_cast<float*>(dinv), items);
+    else
+        pair_inv<double><<<grid, 256, 0, s>>>(static_cast<const double*>(panels), static_cast<double*>(dinv), items);
     return hipGetLastError();
 }
 hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,

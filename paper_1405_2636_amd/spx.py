@@ -56,7 +56,7 @@ class Info(C.Structure):
                 ("logdet", C.c_double), ("factor_kernel_ms", C.c_double), ("assemble_ms", C.c_double),
                 ("tile_rows", C.c_int32), ("tile_cols", C.c_int32), ("hp_policy", C.c_int32), ("nsys", C.c_int32),
                 ("nfused_tiles", C.c_int64), ("nsmall", C.c_int32), ("nneg", C.c_int32),
-                ("pivots_replaced", C.c_int32)]
+                ("pivots_replaced", C.c_int32), ("solve_levels", C.c_int32), ("solve_pairs", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
