@@ -160,8 +160,8 @@ typedef struct spx_info {
                                * last factorization (see static_pivot_eps) */
     int32_t solve_levels;     /* dependency levels of each triangular sweep */
     int32_t solve_pairs;      /* pairs of consecutive pieces of split supernodes solved as one
-                               * block in the sweeps (SPX_LLT, SPX_LU; on levels of at most 16
-                               * blocks): each pair's inverse is formed after the factorization */
+                               * block in the sweeps (on levels of at most 16 blocks): each
+                               * pair's inverse is formed after the factorization */
 } spx_info;
 
 typedef struct spx_solve_info {

@@ -37,8 +37,8 @@ hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count,
 hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s);
 hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s);
 hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s);
-hipError_t launch_pair_inv(const void* panels, void* dinv, bool f32, const PairItem* items, int count, int maxnb,
-                           hipStream_t s);
+hipError_t launch_pair_inv(const void* panels, void* dinv, bool f32, bool ldlt, const PairItem* items, int count,
+                           int maxnb, hipStream_t s);
 hipError_t launch_fwd_small(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
 hipError_t launch_bwd_small(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
 hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,
@@ -559,8 +559,7 @@ void build_tasks(spx_handle* h)
 // pair's inverse (built after each factorization): the chain's levels, each
 // a diagonal and an off-diagonal launch bound by latency, are halved.  p's
 // rows facing q are then covered by the pair's inverse, so p's off-diagonal
-// items start below q's rows.  (Not for L D L^T, whose sweeps scale by the
-// pivots of each piece.)
+// items start below q's rows.
 void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::vector<int64_t>& rgo)
 {
     const Plan& P = h->plan;
@@ -586,7 +585,7 @@ void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::ve
     std::vector<int32_t> lvl;
     int32_t nl = levels(lvl);
     std::vector<int32_t> pairs;   // first pieces of the pairs
-    if (h->opt.method != SPX_LDLT && nc > 1) {
+    if (nc > 1) {
         constexpr int32_t kPairLevel = 16;
         std::vector<int32_t> pop(nl, 0);
         for (int32_t k = 0; k < nc; ++k) ++pop[lvl[k]];
@@ -652,7 +651,8 @@ void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::ve
             const bool pr = pofs[k] >= 0;
             const int32_t w = pr ? width(k) + width(k + 1) : width(k);
             for (int32_t r0 = 0; r0 < w; r0 += rows)
-                L.ditem.push_back(DiagItem{pr ? pofs[k] : doff[k], P.panel_off[k], P.fcol[k], w, r0, P.stride[k]});
+                L.ditem.push_back(DiagItem{pr ? pofs[k] : doff[k], P.panel_off[k], pr ? P.panel_off[k + 1] : 0,
+                                           P.fcol[k], w, r0, P.stride[k], width(k), pr ? P.stride[k + 1] : 0});
         }
         L.dptr[l + 1] = static_cast<int32_t>(L.ditem.size());
     }
@@ -896,11 +896,11 @@ void pair_part(spx_handle* h, hipStream_t s)
     const bool f32 = h->f32();
     const size_t esz = f32 ? sizeof(float) : sizeof(double);
     const int np = static_cast<int>(L.pair.size());
-    HIPCHK(launch_pair_inv(h->panel_ptr(), h->dinv_ptr(), f32, h->lv_pair.p, np, L.maxnb, s));
+    HIPCHK(launch_pair_inv(h->panel_ptr(), h->dinv_ptr(), f32, h->ldlt(), h->lv_pair.p, np, L.maxnb, s));
     if (h->lu())
         HIPCHK(launch_pair_inv(static_cast<const char*>(h->panel_ptr()) + h->plan.panel_entries * esz,
-                               static_cast<char*>(h->dinv_ptr()) + h->dinv_size * esz, f32, h->lv_pair.p, np, L.maxnb,
-                               s));
+                               static_cast<char*>(h->dinv_ptr()) + h->dinv_size * esz, f32, false, h->lv_pair.p, np,
+                               L.maxnb, s));
 }
 
 // One factorization of the values in h->vals: eagerly, or (graph option) by

@@ -111,10 +111,12 @@ struct SweepArgs {
 // so that the loads of the panel, the kept inverse and the vectors go out
 // together after one scalar load of the item (instead of behind a chain of
 // dependent loads through the plan arrays).
-struct DiagItem {          // rows (forward) or columns (backward) r0 .. of the diagonal block of k
-    int64_t dofs;          // start of k's kept inverse (w x w, column-major)
-    int64_t pofs;          // start of k's panel (L D L^T: d_c at pofs + c * (ld + 1))
-    int32_t f, w, r0, ld;  // first column of k, its width, first row of the part, panel stride
+struct DiagItem {          // rows (forward) or columns (backward) r0 .. of the diagonal block of a unit
+    int64_t dofs;          // start of the unit's kept inverse (w x w, column-major)
+    int64_t pofs;          // start of the (first) block's panel: L D L^T d_c at pofs + c * (ld + 1), c < w1
+    int64_t pofs2;         // a pair's second piece's panel: d_c at pofs2 + (c - w1) * (ld2 + 1), c >= w1
+    int32_t f, w, r0, ld;  // first column, width, first row of the part, panel stride of the first block
+    int32_t w1, ld2;       // width of the first block (w for a single block), panel stride of the second
 };
 struct OffItem {           // panel rows row0 .. row0 + nr - 1 of k by the columns c0 .. c1 - 1
     int64_t pofs;          // panel element (row0, 0) of k

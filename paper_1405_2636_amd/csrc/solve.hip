@@ -236,8 +236,10 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const DiagItem* ite
     const T* D = static_cast<const T*>(a.dinv_b) + it.dofs;
     const int tid = threadIdx.x, q = tid % LANES, col = min(c0 + tid / LANES, w - 1);
     const T* Dc = D + (int64_t)col * w;
-    const T* Pd = static_cast<const T*>(a.panels) + it.pofs;   // d_c at c * (ld + 1) (L D L^T)
-    const int64_t ld = it.ld;
+    const T* Pd = static_cast<const T*>(a.panels) + it.pofs;    // L D L^T: d_c, c < w1, at c * (ld + 1)
+    const T* Pd2 = static_cast<const T*>(a.panels) + it.pofs2;  // and c >= w1 at (c - w1) * (ld2 + 1)
+    const int64_t ld = it.ld, ld2 = it.ld2;
+    const int w1 = it.w1;
     for (int rb = 0; rb < a.nrhs; rb += NR) {
         const int nv = min(NR, a.nrhs - rb);
         T d[16];   // the first sixteen loads are issued before the staging barrier
@@ -246,7 +248,8 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const DiagItem* ite
         for (int idx = tid; idx < w * NR; idx += 256) {
             const int c = idx / NR, j = idx - c * NR;
             const int64_t o = (int64_t)(rb + j) * a.n + f + c;
-            zs[idx] = j < nv ? (a.z[o] - a.tacc[o]) * (a.ldlt ? (double)Pd[c * (ld + 1)] : 1.0) : 0.0;
+            const double dc = !a.ldlt ? 1.0 : (double)(c < w1 ? Pd[c * (ld + 1)] : Pd2[(c - w1) * (ld2 + 1)]);
+            zs[idx] = j < nv ? (a.z[o] - a.tacc[o]) * dc : 0.0;
         }
         __syncthreads();
         double v[NR];
@@ -589,7 +592,9 @@ __global__ void values_grad_kernel(const int32_t* erow, const int32_t* ecol, int
 // copied, T = L_qp D_p[:, cols] (inner indices from j0: D_p is lower
 // triangular) into LDS, then X[:, cols] = -D_q T (inner indices up to each
 // row tile's end: D_q is lower triangular); for the remaining jb the columns
-// of q: zeros above, D_q below.  Each wave takes the 16-row tiles
+// of q: zeros above, D_q below.  L D L^T (kept inverses Y = D^{-1} L^{-1},
+// unit L): X = -Y_q L_qp D_p Y_p, the staged rows of Y_p scaled by p's
+// pivots.  Each wave takes the 16-row tiles
 // wave, wave + 4, ...; the loads of sixteen inner steps go out together.
 template <class T>
 struct PairMM;
@@ -615,7 +620,7 @@ struct PairMM<float> {
 constexpr int kPairLd = 17;   // LDS leading dimension of the staged 16-column blocks
 
 template <class T>
-__global__ void __launch_bounds__(256) pair_inv(const T* panels, T* dinv, const PairItem* items)
+__global__ void __launch_bounds__(256) pair_inv(const T* panels, T* dinv, const PairItem* items, int ldlt)
 {
     typedef typename PairMM<T>::acc acc;
     __shared__ T dps[256 * kPairLd];   // D_p[kk][n]
@@ -638,10 +643,11 @@ __global__ void __launch_bounds__(256) pair_inv(const T* panels, T* dinv, const 
     }
     const int j0 = 16 * jb;
     const T* Dp = dinv + it.dp;
+    const T* Pp = panels + (it.lofs - wp);   // p's panel: L D L^T pivot d_r at r * (ldp + 1)
     for (int idx = tid; idx < 16 * wp; idx += 256) {
         const int c = idx / wp, r = idx % wp, j = j0 + c;
         const T v = (j < wp && r >= j) ? Dp[(int64_t)j * wp + r] : T(0);
-        dps[r * kPairLd + c] = v;
+        dps[r * kPairLd + c] = ldlt ? v * Pp[(int64_t)r * (it.ldp + 1)] : v;
         if (j < wp) P[(int64_t)j * W + r] = v;
     }
     __syncthreads();
@@ -746,15 +752,17 @@ hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count,
     }
     return hipGetLastError();
 }
-hipError_t launch_pair_inv(const void* panels, void* dinv, bool f32, const PairItem* items, int count, int maxnb,
-                          hipStream_t s)
+hipError_t launch_pair_inv(const void* panels, void* dinv, bool f32, bool ldlt, const PairItem* items, int count,
+                          int maxnb, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     const dim3 grid(count, maxnb);
     if (f32)
-        pair_inv<float><<<grid, 256, 0, s>>>(static_cast<const float*>(panels), static_cast<float*>(dinv), items);
+        pair_inv<float><<<grid, 256, 0, s>>>(static_cast<const float*>(panels), static_cast<float*>(dinv), items,
+                                             ldlt ? 1 : 0);
     else
-        pair_inv<double><<<grid, 256, 0, s>>>(static_cast<const double*>(panels), static_cast<double*>(dinv), items);
+        pair_inv<double><<<grid, 256, 0, s>>>(static_cast<const double*>(panels), static_cast<double*>(dinv), items,
+                                              ldlt ? 1 : 0);
     return hipGetLastError();
 }
 hipError_t launch_permute_in(double* y, const double* b, int64_t ldb, const int32_t* perm, int32_t n, int32_t nrhs,

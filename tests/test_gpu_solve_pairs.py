@@ -13,9 +13,11 @@ single chain of pieces; elsewhere pairs off the longest path leave the
 count unchanged).
 Inputs: dense SPD matrices (one supernode in 3 to 5 balanced pieces; with
 split_width 160 the pieces are about 140 wide, so the pairs' widths are
-not multiples of 16), a 3-D grid Laplacian (the separators' chains) and
-convection-diffusion L U (pairs of the L and of the U^T side).  L D L^T
-keeps its pieces apart (its sweeps scale by each piece's pivots)."""
+not multiples of 16), a 3-D grid Laplacian (the separators' chains),
+convection-diffusion L U (pairs of the L and of the U^T side) and
+L D L^T of dense quasi-definite matrices (the pair's inverse
+-Y_q L_qp D_p Y_p of the kept Y = D^{-1} L^{-1}, and the backward step's
+scaling by the pivots of both pieces)."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -41,6 +43,18 @@ def _dense_spd(n, seed):
     return Problem(n, Ac.indptr.astype(np.int64), Ac.indices.astype(np.int32), Ac.data.copy())
 
 
+def _quasi_definite(n1, n2, seed):
+    """[[H, B^T], [B, -C]], H and C dense SPD: L D L^T without pivoting exists."""
+    rng = np.random.default_rng(seed)
+    M = rng.uniform(-1, 1, (n1, n1))
+    N = rng.uniform(-1, 1, (n2, n2))
+    H = M @ M.T / n1 + np.eye(n1)
+    C = N @ N.T / n2 + np.eye(n2)
+    B = rng.uniform(-0.5, 0.5, (n2, n1))
+    A = sp.csc_matrix(np.block([[H, B.T], [B, -C]]))
+    return Problem(A.shape[0], A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.copy())
+
+
 def _unpaired_levels(sym):
     """Dependency levels of the column blocks: 1 + the deepest updating block."""
     nc = sym.stats["ncblk"]
@@ -62,6 +76,9 @@ CASES = {
     "lu_cd": (lambda: convection_diffusion((16, 15, 14), seed=5), dict(method="lu", split_width=64, leaf_size=32)),
     "lu_cd_fp32": (lambda: convection_diffusion((16, 15, 14), seed=6),
                    dict(method="lu", precision="fp32_ir", split_width=96)),
+    "dense_ldlt": (lambda: _quasi_definite(600, 500, 7), dict(method="ldlt")),
+    "dense_ldlt_160": (lambda: _quasi_definite(500, 400, 8), dict(method="ldlt", split_width=160)),
+    "dense_ldlt_fp32": (lambda: _quasi_definite(600, 500, 9), dict(method="ldlt", precision="fp32_ir")),
 }
 
 
@@ -91,20 +108,12 @@ def test_paired_sweeps(orc, torch, case, nrhs):
     if method == "lu":
         PL, PU = orc.factor_lu(sym, p.colptr, p.rowind, p.values)
         xo = orc.solve_lu(sym, PL, PU, B)
+    elif method == "ldlt":
+        P = orc.factor_ldlt(sym, p.colptr, p.rowind, p.values)
+        xo = orc.solve_ldlt(sym, P, B)
     else:
         P = orc.factor(sym, p.colptr, p.rowind, p.values)
         xo = orc.solve(sym, P, B)
     xo = xo.reshape(p.n, nrhs)
     tol = 1e-10 if kw.get("precision", "fp64") == "fp64" else 1e-4
     assert np.max(np.abs(xg - xo)) <= tol * np.max(np.abs(xo))
-
-
-def test_ldlt_unpaired(orc, torch):
-    from paper_1405_2636_amd import Solver
-    p = _dense_spd(1100, 6)
-    s = Solver(p.n, p.colptr, p.rowind, method="ldlt", ir_max_iter=0)
-    s.factorize(torch.tensor(p.values, device="cuda"))
-    inf = s.info()
-    sym = orc.analyze(p.n, p.colptr, p.rowind)
-    assert inf["solve_pairs"] == 0
-    assert inf["solve_levels"] == _unpaired_levels(sym)
