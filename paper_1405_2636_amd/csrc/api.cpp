@@ -35,7 +35,7 @@ hipError_t launch_update_bench(const SchedArgs& a, bool f32, bool ldl, const int
                                int copies, hipStream_t s);
 hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s);
 hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s);
-hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s);
+hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, bool tall, hipStream_t s);
 hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s);
 hipError_t launch_pair_inv(const void* panels, void* dinv, bool f32, bool ldlt, const PairItem* items, int count,
                            int maxnb, hipStream_t s);
@@ -112,6 +112,8 @@ struct Level {
     std::vector<uint8_t> narrow; // level l's diagonal items are 16-row parts (16 lanes per row), else 64-row
     std::vector<int32_t> kptr;   // off-diagonal items of level l: chunk[kptr[l]..kptr[l+1])
     std::vector<OffItem> chunk;
+    std::vector<int32_t> bptr;   // narrow levels: the backward sweep's own 256-row items, bchunk[bptr[l]..bptr[l+1])
+    std::vector<OffItem> bchunk;
     std::vector<PairItem> pair;  // paired pieces (one unit of the sweeps each)
     int32_t maxnb = 0;           // widest pair in 16-column blocks, plus one
 };
@@ -155,6 +157,7 @@ struct spx_handle {
     DevBuf<int32_t> lv_cblk;
     DevBuf<DiagItem> lv_ditem;
     DevBuf<OffItem> lv_chunk;
+    DevBuf<OffItem> lv_bchunk;
     DevBuf<PairItem> lv_pair;
     // numeric: FP64 panels and inverses, or their FP32 counterparts
     DevBuf<double> panels, dinv, vals, rv;   // rv: values in the order of the residual's row lists
@@ -664,6 +667,7 @@ void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::ve
     // walks its columns serially.
     constexpr int64_t kOffTarget = 1024;
     L.kptr.assign(nl + 1, 0);
+    L.bptr.assign(nl + 1, 0);
     std::vector<int32_t> members;
     for (int32_t l = 0; l < nl; ++l) {
         // the blocks of the level's units, with the first off-diagonal row of each
@@ -692,10 +696,23 @@ void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::ve
             }
         }
         L.kptr[l + 1] = static_cast<int32_t>(L.chunk.size());
+        // the backward sweep on narrow levels: 256 rows by 16 columns
+        if (L.narrow[l])
+            for (int32_t k : members) {
+                const int32_t w = width(k);
+                for (int32_t r = first_row(k); r < P.stride[k]; r += 256) {
+                    const int32_t nr = std::min(256, P.stride[k] - r);
+                    for (int32_t c0 = 0; c0 < w; c0 += 16)
+                        L.bchunk.push_back(OffItem{P.panel_off[k] + r, rgo[k] + (r - w), P.stride[k], P.fcol[k], r,
+                                                   c0 | (std::min(w, c0 + 16) << 9) | (nr << 18)});
+                }
+            }
+        L.bptr[l + 1] = static_cast<int32_t>(L.bchunk.size());
     }
     h->lv_cblk.upload(L.cblk);
     h->lv_ditem.upload(L.ditem);
     h->lv_chunk.upload(L.chunk);
+    h->lv_bchunk.upload(L.bchunk);
     h->lv_pair.upload(L.pair);
 }
 
@@ -813,7 +830,12 @@ void sweeps(spx_handle* h, const SweepBufs& w, int32_t nrhs, hipStream_t s)
     for (int l = nl - 1; l >= 0; --l) {
         const int32_t* sm = h->lv_cblk.p + L.cptr[l];
         const int ns = L.nsmall[l];
-        HIPCHK(launch_bwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
+        // (256-row items for one right-hand side only: with a block of
+        // several, gathering a 256-row slice of x per 16 columns costs more
+        // than the atomics it saves)
+        if (L.narrow[l] && nrhs == 1)
+            HIPCHK(launch_bwd_off(a, h->lv_bchunk.p + L.bptr[l], L.bptr[l + 1] - L.bptr[l], true, s));
+        else HIPCHK(launch_bwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], false, s));
         HIPCHK(launch_bwd_diag(a, h->lv_ditem.p + L.dptr[l], L.dptr[l + 1] - L.dptr[l], L.narrow[l] != 0, s));
         HIPCHK(launch_bwd_small(a, sm, ns, s));
     }

@@ -122,7 +122,7 @@ struct OffItem {           // panel rows row0 .. row0 + nr - 1 of k by the colum
     int64_t pofs;          // panel element (row0, 0) of k
     int64_t gofs;          // position of panel row row0's global row in the row list
     int32_t ld, f, row0;   // panel stride, first column of k, first panel row
-    int32_t cnr;           // c0 | c1 << 9 | nr << 18 (widths are at most 256, nr at most 64)
+    int32_t cnr;           // c0 | c1 << 9 | nr << 18 (widths are at most 256, nr at most 256)
 };
 
 // Two consecutive pieces p, q of a split supernode solved as one block in

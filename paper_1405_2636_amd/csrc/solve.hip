@@ -169,54 +169,67 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const OffItem* items
 }
 
 // ---- backward, off-diagonal rows: tacc[f + c] += sum_r L[r, c] x[g(r)].
-// One workgroup per item (the forward kernel's items);
-// four lanes per column (columns c0 + tid/4, c0 + tid/4 + 64, ...), lane q
-// takes the rows q, q+4, ..., q+60 with all sixteen loads in flight, the
-// first block's before the staging barrier; each load instruction covers
-// four consecutive rows of sixteen columns.
-template <class T, int NR>
+// One workgroup per item: up to 16 LANES panel rows from row0 by the
+// columns c0 .. c1 - 1, 256 / LANES columns at a time; LANES lanes per
+// column, lane q takes the rows q, q + LANES, ... with all sixteen loads in
+// flight (the first block's before the staging barrier).  LANES = 4: 64-row
+// items, the forward kernel's (wide levels: many blocks, few rows each);
+// LANES = 16: 256-row items of 16 columns (narrow levels with one
+// right-hand side; their blocks have thousands of rows: a column of tacc
+// then takes one atomic add per 256 rows instead of per 64, and each load
+// instruction covers 16 consecutive rows of four columns instead of four
+// rows of sixteen).
+template <class T, int LANES, int NR>
 __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const OffItem* items)
 {
-    __shared__ double xr[kChunk * NR];
+    constexpr int COLS = 256 / LANES, ROWS = 16 * LANES, NST = (ROWS * NR + 255) / 256;
+    __shared__ double xr[ROWS * NR];
     const OffItem it = items[blockIdx.x];
     const int f = it.f, c0 = it.cnr & 511, c1 = (it.cnr >> 9) & 511, nr = it.cnr >> 18;
     const int64_t ld = it.ld;
     const int32_t* g = a.rowg + it.gofs;
-    const int tid = threadIdx.x, q = tid & 3;
+    const int tid = threadIdx.x, q = tid % LANES, cl = tid / LANES;
     const T* L = static_cast<const T*>(a.panels_b) + it.pofs;
+    // global rows of the thread's staged entries (staged entry idx = tid +
+    // 256 i holds row idx / NR), loaded ahead of the panel: the gather then
+    // waits for them only, not for the panel loads issued after them
+    int gv[NST];
+#pragma unroll
+    for (int i = 0; i < NST; ++i) gv[i] = g[min((tid + 256 * i) / NR, nr - 1)];
     for (int rb = 0; rb < a.nrhs; rb += NR) {
         const int nv = min(NR, a.nrhs - rb);
         T l[16];
         {
-            const T* Lc = L + (int64_t)min(c0 + (tid >> 2), c1 - 1) * ld;
+            const T* Lc = L + (int64_t)min(c0 + cl, c1 - 1) * ld;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) l[u] = Lc[min(q + 4 * u, nr - 1)];
+            for (int u = 0; u < 16; ++u) l[u] = Lc[min(q + LANES * u, nr - 1)];
         }
-        for (int idx = tid; idx < nr * NR; idx += 256) {
-            const int r = idx / NR, j = idx % NR;
-            xr[idx] = j < nv ? a.x[(int64_t)(rb + j) * a.n + g[r]] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NST; ++i) {
+            const int idx = tid + 256 * i, j = idx % NR;
+            if (idx < nr * NR) xr[idx] = j < nv ? a.x[(int64_t)(rb + j) * a.n + gv[i]] : 0.0;
         }
         __syncthreads();
-        for (int cb = c0; cb < c1; cb += 64) {
-            const int c = min(cb + (tid >> 2), c1 - 1);
+        for (int cb = c0; cb < c1; cb += COLS) {
+            const int c = min(cb + cl, c1 - 1);
             if (cb != c0) {
                 const T* Lc = L + (int64_t)c * ld;
 #pragma unroll
-                for (int u = 0; u < 16; ++u) l[u] = Lc[min(q + 4 * u, nr - 1)];
+                for (int u = 0; u < 16; ++u) l[u] = Lc[min(q + LANES * u, nr - 1)];
             }
             double v[NR];
 #pragma unroll
             for (int j = 0; j < NR; ++j) v[j] = 0.0;
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
-                const double lv = q + 4 * u < nr ? (double)l[u] : 0.0;
-                const double* xp = xr + min(q + 4 * u, nr - 1) * NR;
+                const double lv = q + LANES * u < nr ? (double)l[u] : 0.0;
+                const double* xp = xr + min(q + LANES * u, nr - 1) * NR;
 #pragma unroll
                 for (int j = 0; j < NR; ++j) v[j] += lv * xp[j];
             }
 #pragma unroll
-            for (int j = 0; j < NR; ++j) v[j] = group_sum<4>(v[j]);
-            if (cb + (tid >> 2) < c1 && q == 0)
+            for (int j = 0; j < NR; ++j) v[j] = group_sum<LANES>(v[j]);
+            if (cb + cl < c1 && q == 0)
                 for (int j = 0; j < nv; ++j) unsafeAtomicAdd(a.tacc + (int64_t)(rb + j) * a.n + f + c, v[j]);
         }
         __syncthreads();
@@ -732,11 +745,16 @@ hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, h
                                              : fwd_off<double, NR><<<count, 256, 0, s>>>(a, items)));
     return hipGetLastError();
 }
-hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s)
+hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, bool tall, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, NR><<<count, 256, 0, s>>>(a, items)
-                                             : bwd_off<double, NR><<<count, 256, 0, s>>>(a, items)));
+    if (tall) {
+        SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, 16, NR><<<count, 256, 0, s>>>(a, items)
+                                                 : bwd_off<double, 16, NR><<<count, 256, 0, s>>>(a, items)));
+    } else {
+        SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, 4, NR><<<count, 256, 0, s>>>(a, items)
+                                                 : bwd_off<double, 4, NR><<<count, 256, 0, s>>>(a, items)));
+    }
     return hipGetLastError();
 }
 hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s)
