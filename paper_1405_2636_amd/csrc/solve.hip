@@ -50,7 +50,11 @@ __device__ __forceinline__ double group_sum(double v)
 // Every sweep kernel handles the right-hand sides in blocks of NR (1, 4 or
 // 8, the small-block kernels 1 or 2; chosen from nrhs at launch): the panel and inverse entries a thread
 // loads serve all NR columns of the block, so a panel is read once per
-// block of right-hand sides instead of once per right-hand side.
+// block of right-hand sides instead of once per right-hand side.  The
+// diagonal and off-diagonal kernels take one block per grid row (a loop
+// over the blocks kept the loop-invariant addresses of the hoisted loads
+// live: 150-210 registers per lane instead of 85-135, and half the
+// resident waves).
 // (staged vectors: element c of right-hand side j at [c * NR + j]; a masked
 // term is formed as 0 * value, so clamped indices stay inside the staged
 // entries: a value read from unwritten LDS may be NaN)
@@ -70,12 +74,12 @@ __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const DiagItem* ite
     const int f = it.f, w = it.w, r0 = it.r0;
     const T* D = static_cast<const T*>(a.dinv) + it.dofs;
     const int tid = threadIdx.x, q = tid % LANES, row = min(r0 + tid / LANES, w - 1);
-    const T* Dr = D + row;
-    for (int rb = 0; rb < a.nrhs; rb += NR) {
+    {   // the grid row's block of right-hand sides
+        const int rb = blockIdx.y * NR;
         const int nv = min(NR, a.nrhs - rb);
         T d[16];   // the first sixteen loads are issued before the staging barrier
 #pragma unroll
-        for (int u = 0; u < 16; ++u) d[u] = Dr[(int64_t)min(q + LANES * u, row) * w];
+        for (int u = 0; u < 16; ++u) d[u] = D[(uint32_t)(row + min(q + LANES * u, row) * w)];
         for (int idx = tid; idx < w * NR; idx += 256) {
             const int c = idx / NR, j = idx - c * NR;
             ys[idx] = j < nv ? a.y[(int64_t)(rb + j) * a.n + f + c] : 0.0;
@@ -87,7 +91,7 @@ __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const DiagItem* ite
         for (int pb = 0; pb <= row; pb += 16 * LANES) {
             if (pb != 0) {
 #pragma unroll
-                for (int u = 0; u < 16; ++u) d[u] = Dr[(int64_t)min(pb + q + LANES * u, row) * w];
+                for (int u = 0; u < 16; ++u) d[u] = D[(uint32_t)(row + min(pb + q + LANES * u, row) * w)];
             }
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
@@ -128,7 +132,8 @@ __global__ void __launch_bounds__(256) fwd_off(SweepArgs a, const OffItem* items
     const int qw = (c1 - c0 + 3) >> 2, cb = c0 + wave * qw, ce = min(c1, cb + qw);
     const T* Lr = static_cast<const T*>(a.panels) + it.pofs + r;
     const T* Pd = static_cast<const T*>(a.panels) + (it.pofs - it.row0);   // d_c at c * (ld + 1) (L D L^T)
-    for (int rb = 0; rb < a.nrhs; rb += NR) {
+    {   // the grid row's block of right-hand sides
+        const int rb = blockIdx.y * NR;
         const int nv = min(NR, a.nrhs - rb);
         T l[16];
 #pragma unroll
@@ -196,7 +201,8 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const OffItem* items
     int gv[NST];
 #pragma unroll
     for (int i = 0; i < NST; ++i) gv[i] = g[min((tid + 256 * i) / NR, nr - 1)];
-    for (int rb = 0; rb < a.nrhs; rb += NR) {
+    {   // the grid row's block of right-hand sides
+        const int rb = blockIdx.y * NR;
         const int nv = min(NR, a.nrhs - rb);
         T l[16];
         {
@@ -248,16 +254,16 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const DiagItem* ite
     const int f = it.f, w = it.w, c0 = it.r0;
     const T* D = static_cast<const T*>(a.dinv_b) + it.dofs;
     const int tid = threadIdx.x, q = tid % LANES, col = min(c0 + tid / LANES, w - 1);
-    const T* Dc = D + (int64_t)col * w;
     const T* Pd = static_cast<const T*>(a.panels) + it.pofs;    // L D L^T: d_c, c < w1, at c * (ld + 1)
     const T* Pd2 = static_cast<const T*>(a.panels) + it.pofs2;  // and c >= w1 at (c - w1) * (ld2 + 1)
     const int64_t ld = it.ld, ld2 = it.ld2;
     const int w1 = it.w1;
-    for (int rb = 0; rb < a.nrhs; rb += NR) {
+    {   // the grid row's block of right-hand sides
+        const int rb = blockIdx.y * NR;
         const int nv = min(NR, a.nrhs - rb);
         T d[16];   // the first sixteen loads are issued before the staging barrier
 #pragma unroll
-        for (int u = 0; u < 16; ++u) d[u] = Dc[min(col + q + LANES * u, w - 1)];
+        for (int u = 0; u < 16; ++u) d[u] = D[(uint32_t)(col * w + min(col + q + LANES * u, w - 1))];
         for (int idx = tid; idx < w * NR; idx += 256) {
             const int c = idx / NR, j = idx - c * NR;
             const int64_t o = (int64_t)(rb + j) * a.n + f + c;
@@ -271,7 +277,7 @@ __global__ void __launch_bounds__(256) bwd_diag(SweepArgs a, const DiagItem* ite
         for (int pb = col; pb < w; pb += 16 * LANES) {
             if (pb != col) {
 #pragma unroll
-                for (int u = 0; u < 16; ++u) d[u] = Dc[min(pb + q + LANES * u, w - 1)];
+                for (int u = 0; u < 16; ++u) d[u] = D[(uint32_t)(col * w + min(pb + q + LANES * u, w - 1))];
             }
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
@@ -608,7 +614,7 @@ __global__ void values_grad_kernel(const int32_t* erow, const int32_t* ecol, int
 // of q: zeros above, D_q below.  L D L^T (kept inverses Y = D^{-1} L^{-1},
 // unit L): X = -Y_q L_qp D_p Y_p, the staged rows of Y_p scaled by p's
 // pivots.  Each wave takes the 16-row tiles
-// wave, wave + 4, ...; the loads of sixteen inner steps go out together.
+// wave, wave + 4, wave + 8, wave + 12 side by side.
 template <class T>
 struct PairMM;
 template <>
@@ -664,51 +670,68 @@ __global__ void __launch_bounds__(256) pair_inv(const T* panels, T* dinv, const 
         if (j < wp) P[(int64_t)j * W + r] = v;
     }
     __syncthreads();
+    // the wave's four 16-row tiles t = wave + 4 i side by side: per round
+    // the loads of sixteen inner steps of all four go out together (tiles
+    // past w_q load clamped rows and are not stored)
     const int ntile = (wq + 15) / 16;
     const T* Lq = panels + it.lofs;   // L_qp[i][kk] at Lq[i + kk * ldp]
     const int64_t ldp = it.ldp;
-    for (int t = wave; t < ntile; t += 4) {
-        acc c = {0, 0, 0, 0};
-        const int i = min(16 * t + li, wq - 1);
-        for (int kk0 = j0; kk0 < wp; kk0 += 64) {
-            T av[16], bv[16];
+    acc c[4];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int kk = kk0 + 4 * u + lk;
-                av[u] = Lq[i + (int64_t)min(kk, wp - 1) * ldp];
-                bv[u] = kk < wp ? dps[kk * kPairLd + li] : T(0);
-            }
+    for (int t = 0; t < 4; ++t) c[t] = acc{0, 0, 0, 0};
+    for (int kk0 = j0; kk0 < wp; kk0 += 64) {
+        T av[4][16], bv[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) c = PairMM<T>::mfma(av[u], bv[u], c);
+        for (int u = 0; u < 16; ++u) {
+            const int kk = kk0 + 4 * u + lk;
+            bv[u] = kk < wp ? dps[kk * kPairLd + li] : T(0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                av[t][u] = Lq[min(16 * (wave + 4 * t) + li, wq - 1) + (int64_t)min(kk, wp - 1) * ldp];
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ts[(16 * t + PairMM<T>::row(v, lk)) * kPairLd + li] = c[v];
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) c[t] = PairMM<T>::mfma(av[t][u], bv[u], c[t]);
     }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        if (wave + 4 * t < ntile)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ts[(16 * (wave + 4 * t) + PairMM<T>::row(v, lk)) * kPairLd + li] = c[t][v];
     __syncthreads();
     const T* Dq = dinv + it.dq;   // D_q[i][kk] at Dq[i + kk * wq]
-    for (int t = wave; t < ntile; t += 4) {
-        acc c = {0, 0, 0, 0};
-        const int irow = 16 * t + li, i = min(irow, wq - 1);
-        const int kend = min(16 * t + 16, wq);
-        for (int kk0 = 0; kk0 < kend; kk0 += 64) {
-            T av[16], bv[16];
+    // inner indices up to the end of the wave's last tile (each tile's
+    // entries past its rows are masked: D_q is lower triangular)
+    const int kend = min(16 * (wave + 12) + 16, wq);
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int kk = kk0 + 4 * u + lk;
-                const T d = Dq[i + (int64_t)min(kk, wq - 1) * wq];
-                av[u] = kk <= irow ? d : T(0);
-                bv[u] = kk < kend ? ts[kk * kPairLd + li] : T(0);
+    for (int t = 0; t < 4; ++t) c[t] = acc{0, 0, 0, 0};
+    for (int kk0 = 0; kk0 < kend; kk0 += 64) {
+        T av[4][16], bv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int kk = kk0 + 4 * u + lk;
+            bv[u] = kk < kend ? ts[kk * kPairLd + li] : T(0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int irow = 16 * (wave + 4 * t) + li;
+                const T d = Dq[min(irow, wq - 1) + (int64_t)min(kk, wq - 1) * wq];
+                av[t][u] = kk <= irow ? d : T(0);
             }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) c = PairMM<T>::mfma(av[u], bv[u], c);
         }
-        if (j0 + li < wp)
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) c[t] = PairMM<T>::mfma(av[t][u], bv[u], c[t]);
+    }
+    if (j0 + li < wp)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = 16 * t + PairMM<T>::row(v, lk);
-                if (r < wq) P[(int64_t)(j0 + li) * W + wp + r] = -c[v];
+                const int r = 16 * (wave + 4 * t) + PairMM<T>::row(v, lk);
+                if (r < wq) P[(int64_t)(j0 + li) * W + wp + r] = -c[t][v];
             }
-    }
 }
 
 // ---- host launchers
@@ -730,30 +753,30 @@ hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count,
     if (count <= 0) return hipSuccess;
     const int nrv = nr_block(a.nrhs);
     if (narrow) {
-        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 16, NR><<<count, 256, 0, s>>>(a, items)
-                                    : fwd_diag<double, 16, NR><<<count, 256, 0, s>>>(a, items)));
+        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
+                                    : fwd_diag<double, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
     } else {
-        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 4, NR><<<count, 256, 0, s>>>(a, items)
-                                    : fwd_diag<double, 4, NR><<<count, 256, 0, s>>>(a, items)));
+        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
+                                    : fwd_diag<double, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
     }
     return hipGetLastError();
 }
 hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? fwd_off<float, NR><<<count, 256, 0, s>>>(a, items)
-                                             : fwd_off<double, NR><<<count, 256, 0, s>>>(a, items)));
+    SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? fwd_off<float, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
+                                             : fwd_off<double, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
     return hipGetLastError();
 }
 hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, bool tall, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     if (tall) {
-        SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, 16, NR><<<count, 256, 0, s>>>(a, items)
-                                                 : bwd_off<double, 16, NR><<<count, 256, 0, s>>>(a, items)));
+        SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
+                                                 : bwd_off<double, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
     } else {
-        SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, 4, NR><<<count, 256, 0, s>>>(a, items)
-                                                 : bwd_off<double, 4, NR><<<count, 256, 0, s>>>(a, items)));
+        SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
+                                                 : bwd_off<double, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
     }
     return hipGetLastError();
 }
@@ -762,11 +785,11 @@ hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count,
     if (count <= 0) return hipSuccess;
     const int nrv = nr_block(a.nrhs);
     if (narrow) {
-        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 16, NR><<<count, 256, 0, s>>>(a, items)
-                                    : bwd_diag<double, 16, NR><<<count, 256, 0, s>>>(a, items)));
+        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
+                                    : bwd_diag<double, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
     } else {
-        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 4, NR><<<count, 256, 0, s>>>(a, items)
-                                    : bwd_diag<double, 4, NR><<<count, 256, 0, s>>>(a, items)));
+        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
+                                    : bwd_diag<double, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
     }
     return hipGetLastError();
 }
