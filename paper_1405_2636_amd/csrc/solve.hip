@@ -614,7 +614,7 @@ __global__ void values_grad_kernel(const int32_t* erow, const int32_t* ecol, int
 // of q: zeros above, D_q below.  L D L^T (kept inverses Y = D^{-1} L^{-1},
 // unit L): X = -Y_q L_qp D_p Y_p, the staged rows of Y_p scaled by p's
 // pivots.  Each wave takes the 16-row tiles
-// wave, wave + 4, wave + 8, wave + 12 side by side.
+// wave, wave + 4, ...; the loads of sixteen inner steps go out together.
 template <class T>
 struct PairMM;
 template <>
@@ -670,68 +670,51 @@ __global__ void __launch_bounds__(256) pair_inv(const T* panels, T* dinv, const 
         if (j < wp) P[(int64_t)j * W + r] = v;
     }
     __syncthreads();
-    // the wave's four 16-row tiles t = wave + 4 i side by side: per round
-    // the loads of sixteen inner steps of all four go out together (tiles
-    // past w_q load clamped rows and are not stored)
     const int ntile = (wq + 15) / 16;
     const T* Lq = panels + it.lofs;   // L_qp[i][kk] at Lq[i + kk * ldp]
     const int64_t ldp = it.ldp;
-    acc c[4];
+    for (int t = wave; t < ntile; t += 4) {
+        acc c = {0, 0, 0, 0};
+        const int i = min(16 * t + li, wq - 1);
+        for (int kk0 = j0; kk0 < wp; kk0 += 64) {
+            T av[16], bv[16];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) c[t] = acc{0, 0, 0, 0};
-    for (int kk0 = j0; kk0 < wp; kk0 += 64) {
-        T av[4][16], bv[16];
+            for (int u = 0; u < 16; ++u) {
+                const int kk = kk0 + 4 * u + lk;
+                av[u] = Lq[i + (int64_t)min(kk, wp - 1) * ldp];
+                bv[u] = kk < wp ? dps[kk * kPairLd + li] : T(0);
+            }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int kk = kk0 + 4 * u + lk;
-            bv[u] = kk < wp ? dps[kk * kPairLd + li] : T(0);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                av[t][u] = Lq[min(16 * (wave + 4 * t) + li, wq - 1) + (int64_t)min(kk, wp - 1) * ldp];
+            for (int u = 0; u < 16; ++u) c = PairMM<T>::mfma(av[u], bv[u], c);
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) c[t] = PairMM<T>::mfma(av[t][u], bv[u], c[t]);
+        for (int v = 0; v < 4; ++v) ts[(16 * t + PairMM<T>::row(v, lk)) * kPairLd + li] = c[v];
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-        if (wave + 4 * t < ntile)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) ts[(16 * (wave + 4 * t) + PairMM<T>::row(v, lk)) * kPairLd + li] = c[t][v];
     __syncthreads();
     const T* Dq = dinv + it.dq;   // D_q[i][kk] at Dq[i + kk * wq]
-    // inner indices up to the end of the wave's last tile (each tile's
-    // entries past its rows are masked: D_q is lower triangular)
-    const int kend = min(16 * (wave + 12) + 16, wq);
+    for (int t = wave; t < ntile; t += 4) {
+        acc c = {0, 0, 0, 0};
+        const int irow = 16 * t + li, i = min(irow, wq - 1);
+        const int kend = min(16 * t + 16, wq);
+        for (int kk0 = 0; kk0 < kend; kk0 += 64) {
+            T av[16], bv[16];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) c[t] = acc{0, 0, 0, 0};
-    for (int kk0 = 0; kk0 < kend; kk0 += 64) {
-        T av[4][16], bv[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int kk = kk0 + 4 * u + lk;
-            bv[u] = kk < kend ? ts[kk * kPairLd + li] : T(0);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int irow = 16 * (wave + 4 * t) + li;
-                const T d = Dq[min(irow, wq - 1) + (int64_t)min(kk, wq - 1) * wq];
-                av[t][u] = kk <= irow ? d : T(0);
+            for (int u = 0; u < 16; ++u) {
+                const int kk = kk0 + 4 * u + lk;
+                const T d = Dq[i + (int64_t)min(kk, wq - 1) * wq];
+                av[u] = kk <= irow ? d : T(0);
+                bv[u] = kk < kend ? ts[kk * kPairLd + li] : T(0);
             }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) c = PairMM<T>::mfma(av[u], bv[u], c);
         }
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) c[t] = PairMM<T>::mfma(av[t][u], bv[u], c[t]);
-    }
-    if (j0 + li < wp)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
+        if (j0 + li < wp)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = 16 * (wave + 4 * t) + PairMM<T>::row(v, lk);
-                if (r < wq) P[(int64_t)(j0 + li) * W + wp + r] = -c[t][v];
+                const int r = 16 * t + PairMM<T>::row(v, lk);
+                if (r < wq) P[(int64_t)(j0 + li) * W + wp + r] = -c[v];
             }
+    }
 }
 
 // ---- host launchers
