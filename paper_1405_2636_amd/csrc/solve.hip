@@ -242,6 +242,113 @@ __global__ void __launch_bounds__(256) bwd_off(SweepArgs a, const OffItem* items
     }
 }
 
+// ---- off-diagonal steps for blocks of NR = 4 or 8 right-hand sides, on
+// the matrix cores (v_mfma_f64_16x16x4f64: operand A lane l holds
+// A[l%16][l/16], operand B lane l holds B[l/16][l%16], result slot v of
+// lane l holds D[4v + l/16][l%16]); FP32 panels are converted, so the
+// arithmetic stays FP64.  With several right-hand sides the scalar kernels
+// spend a product and an LDS read per loaded entry and right-hand side:
+// they were bound by that, not by the panel bytes.
+typedef double sw_d4 __attribute__((ext_vector_type(4)));
+
+// forward: y[g(r)] -= (L z)[r] over the item's 64 rows and columns c0..c1.
+// Wave v takes a quarter of the columns, all four 16-row tiles (A = panel
+// rows, B = the staged z, right-hand sides past NR zero); the four waves'
+// partial sums meet in LDS.
+template <class T, int NR>
+__global__ void __launch_bounds__(256) fwd_off_mm(SweepArgs a, const OffItem* items)
+{
+    __shared__ double zk[256 * NR];
+    __shared__ double part[4 * 64 * NR];
+    const OffItem it = items[blockIdx.x];
+    const int f = it.f, c0 = it.cnr & 511, c1 = (it.cnr >> 9) & 511, nr = it.cnr >> 18;
+    const int64_t ld = it.ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int rb = blockIdx.y * NR, nv = min(NR, a.nrhs - rb);
+    const int qw = (((c1 - c0 + 3) >> 2) + 3) & ~3;   // a wave's columns, a multiple of 4
+    const int cb = c0 + wave * qw, ce = min(c1, cb + qw);
+    const T* L = static_cast<const T*>(a.panels) + it.pofs;
+    const T* Pd = static_cast<const T*>(a.panels) + (it.pofs - it.row0);   // d_c at c * (ld + 1) (L D L^T)
+    for (int idx = tid; idx < (c1 - c0) * NR; idx += 256) {
+        const int c = c0 + idx / NR, j = idx % NR;
+        zk[idx] = j < nv ? a.z[(int64_t)(rb + j) * a.n + f + c] * (a.ldlt ? (double)Pd[c * (ld + 1)] : 1.0) : 0.0;
+    }
+    __syncthreads();
+    sw_d4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = sw_d4{0, 0, 0, 0};
+    // (columns past ce read a clamped column and meet B = 0; rows past nr
+    // read a clamped row whose results are not stored)
+    for (int k0 = cb; k0 < ce; k0 += 16) {
+        T al[4][4];
+        double bz[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int c = k0 + 4 * s + lk;
+            const int cc = min(c, ce - 1);
+            bz[s] = (c < ce && li < NR) ? zk[(cc - c0) * NR + li] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) al[t][s] = L[min(16 * t + li, nr - 1) + (int64_t)cc * ld];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)al[t][s], bz[s], acc[t], 0, 0, 0);
+    }
+    if (li < NR)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) part[(wave * 64 + 16 * t + 4 * v + lk) * NR + li] = acc[t][v];
+    __syncthreads();
+    for (int idx = tid; idx < nr * NR; idx += 256) {
+        const int r = idx / NR, j = idx % NR;
+        if (j < nv) {
+            const double sum = (part[r * NR + j] + part[(64 + r) * NR + j]) +
+                               (part[(128 + r) * NR + j] + part[(192 + r) * NR + j]);
+            unsafeAtomicAdd(a.y + (int64_t)(rb + j) * a.n + a.rowg[it.gofs + r], -sum);
+        }
+    }
+}
+
+// backward: tacc[f + c] += (L^T x)[c] over the item's rows.  A = the staged
+// x (right-hand side by row, rows past nr zero), B = 16 panel columns; wave
+// v takes the column tiles c0 + 16 v, c0 + 16 (v + 4), ...
+template <class T, int NR>
+__global__ void __launch_bounds__(256) bwd_off_mm(SweepArgs a, const OffItem* items)
+{
+    __shared__ double xr[kChunk * NR];
+    const OffItem it = items[blockIdx.x];
+    const int f = it.f, c0 = it.cnr & 511, c1 = (it.cnr >> 9) & 511, nr = it.cnr >> 18;
+    const int64_t ld = it.ld;
+    const int32_t* g = a.rowg + it.gofs;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int rb = blockIdx.y * NR, nv = min(NR, a.nrhs - rb);
+    const T* L = static_cast<const T*>(a.panels_b) + it.pofs;
+    for (int idx = tid; idx < kChunk * NR; idx += 256) {
+        const int r = idx / NR, j = idx % NR;
+        xr[idx] = (r < nr && j < nv) ? a.x[(int64_t)(rb + j) * a.n + g[r]] : 0.0;
+    }
+    __syncthreads();
+    double ax[16];   // A[rhs = li][row = 4 s + lk]
+#pragma unroll
+    for (int s = 0; s < 16; ++s) ax[s] = li < NR ? xr[(4 * s + lk) * NR + li] : 0.0;
+    for (int cb = c0 + 16 * wave; cb < c1; cb += 64) {
+        const T* Lc = L + (int64_t)min(cb + li, c1 - 1) * ld;
+        T bl[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) bl[s] = Lc[min(4 * s + lk, nr - 1)];
+        sw_d4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[s], (double)bl[s], acc, 0, 0, 0);
+        if (cb + li < c1)
+#pragma unroll
+            for (int v = 0; v < NR / 4; ++v)
+                if (4 * v + lk < nv) unsafeAtomicAdd(a.tacc + (int64_t)(rb + 4 * v + lk) * a.n + f + cb + li, acc[v]);
+    }
+}
+
 // ---- backward, diagonal block: x_k = D^T (z_k - t_k); LANES lanes per
 // column c of D, lane q takes the rows p = c+q, c+q+LANES, ... (p >= w
 // clamped and multiplied by zero); the forward kernel's items, columns
@@ -747,6 +854,17 @@ hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count,
 hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
+    if (a.nrhs > 1) {   // blocks of 4 or 8 right-hand sides: the matrix-core form
+        const dim3 grid(count, (a.nrhs + (a.nrhs <= 4 ? 3 : 7)) / (a.nrhs <= 4 ? 4 : 8));
+        if (a.nrhs <= 4) {
+            if (a.f32) fwd_off_mm<float, 4><<<grid, 256, 0, s>>>(a, items);
+            else fwd_off_mm<double, 4><<<grid, 256, 0, s>>>(a, items);
+        } else {
+            if (a.f32) fwd_off_mm<float, 8><<<grid, 256, 0, s>>>(a, items);
+            else fwd_off_mm<double, 8><<<grid, 256, 0, s>>>(a, items);
+        }
+        return hipGetLastError();
+    }
     SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? fwd_off<float, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
                                              : fwd_off<double, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
     return hipGetLastError();
@@ -754,6 +872,17 @@ hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, h
 hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, bool tall, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
+    if (a.nrhs > 1) {   // blocks of 4 or 8 right-hand sides (64-row items): the matrix-core form
+        const dim3 grid(count, (a.nrhs + (a.nrhs <= 4 ? 3 : 7)) / (a.nrhs <= 4 ? 4 : 8));
+        if (a.nrhs <= 4) {
+            if (a.f32) bwd_off_mm<float, 4><<<grid, 256, 0, s>>>(a, items);
+            else bwd_off_mm<double, 4><<<grid, 256, 0, s>>>(a, items);
+        } else {
+            if (a.f32) bwd_off_mm<float, 8><<<grid, 256, 0, s>>>(a, items);
+            else bwd_off_mm<double, 8><<<grid, 256, 0, s>>>(a, items);
+        }
+        return hipGetLastError();
+    }
     if (tall) {
         SPX_NR_DISPATCH(nr_block(a.nrhs), (a.f32 ? bwd_off<float, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
                                                  : bwd_off<double, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
