@@ -6,11 +6,17 @@
 //   z_k = L_kk^{-1} y_k                   (diagonal rows split over workgroups)
 //   y[rows of k] -= L_k,off z_k           (64-row chunks, FP64 atomics)
 // Backward sweep, levels descending:
-//   t_k  = L_k,off^T x[rows of k]         (64-row chunks)
+//   t_k  = L_k,off^T x[rows of k]         (64- or 256-row chunks)
 //   x_k  = L_kk^{-T} (z_k - t_k)
 // Both use the inverse of each diagonal block kept by the factorization.
+// On the narrow levels two consecutive pieces p, q of a split supernode are
+// one block of the sweeps: the diagonal steps use the pair's inverse
+// (pair_inv, formed after each factorization), so p's rows facing q are left
+// out of its off-diagonal steps.  Every launch reads its work from a list of
+// self-contained items (DiagItem, OffItem) built once per analysis.
 // Several right-hand sides are handled in blocks of up to 8 per pass over
-// the panels (each loaded entry serves the whole block).
+// the panels (each loaded entry serves the whole block); with 4 or 8 the
+// off-diagonal steps are matrix-core products (fwd_off_mm, bwd_off_mm).
 // Column blocks of width <= 32 with at most 128 panel rows take both halves
 // of a step in one kernel per level, a group of 16 lanes per block
 // (fwd_small, bwd_small).
