@@ -6,8 +6,9 @@ factorization; p's rows facing q are left out of its off-diagonal step.
 Checked through an unrefined solve (no refinement step: every error of the
 pair's inverse shows in x) against the oracle's solve, x within 1e-10 of its
 largest entry in FP64 and 1e-4 in the FP32 modes (the FP32 factor's own
-error), for one, three and eight right-hand sides (the sweeps' blocks of 1,
-4 and 8), and through the level count: fewer levels than the unpaired
+error), for one, three, eight and thirteen right-hand sides (the sweeps'
+blocks of 1, 4 and 8, and two grid rows of 8 with a partial second one),
+and through the level count: fewer levels than the unpaired
 dependency levels, computed here from the oracle's update lists (for a
 single chain of pieces; elsewhere pairs off the longest path leave the
 count unchanged).
@@ -82,7 +83,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("nrhs", [1, 3, 8])
+@pytest.mark.parametrize("nrhs", [1, 3, 8, 13])
 @pytest.mark.parametrize("case", list(CASES))
 def test_paired_sweeps(orc, torch, case, nrhs):
     from paper_1405_2636_amd import Solver
