@@ -33,10 +33,10 @@ int sched_blocks_per_cu(bool f32, bool ldlt, bool lu);
 hipError_t launch_sched(const SchedArgs& a, bool f32, bool lu, int grid, hipStream_t s);
 hipError_t launch_update_bench(const SchedArgs& a, bool f32, bool ldl, const int4* tiles, int ntiles, int mbase,
                                int copies, hipStream_t s);
-hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s);
+hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count, int lanes, hipStream_t s);
 hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s);
 hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, bool tall, hipStream_t s);
-hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s);
+hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count, int lanes, hipStream_t s);
 hipError_t launch_pair_inv(const void* panels, void* dinv, bool f32, bool ldlt, const PairItem* items, int count,
                            int maxnb, hipStream_t s);
 hipError_t launch_fwd_small(const SweepArgs& a, const int32_t* cblks, int count, hipStream_t s);
@@ -109,7 +109,8 @@ struct Level {
     std::vector<int32_t> nsmall; // blocks of width <= 32 with at most 128 panel rows, per level
     std::vector<int32_t> dptr;   // diagonal items of level l: ditem[dptr[l]..dptr[l+1])
     std::vector<DiagItem> ditem;
-    std::vector<uint8_t> narrow; // level l's diagonal items are 16-row parts (16 lanes per row), else 64-row
+    std::vector<uint8_t> narrow; // level l holds fewer than 64 blocks (its sweep items are cut finer)
+    std::vector<uint8_t> dlanes; // lanes per row of level l's diagonal items (4, 16 or 32; 256 / lanes rows each)
     std::vector<int32_t> kptr;   // off-diagonal items of level l: chunk[kptr[l]..kptr[l+1])
     std::vector<OffItem> chunk;
     std::vector<int32_t> bptr;   // narrow levels: the backward sweep's own 256-row items, bchunk[bptr[l]..bptr[l+1])
@@ -643,12 +644,18 @@ void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::ve
     // diagonal items: 16-row parts on levels with fewer than kNarrowLevel
     // blocks (16 lanes per row: fewer dependent load rounds), else 64-row
     constexpr int32_t kNarrowLevel = 64;
+    // (levels holding a pair: 32 lanes, so that a row of the pair's 512-wide
+    // inverse takes one round of sixteen loads per lane instead of two)
     L.dptr.assign(nl + 1, 0);
     L.narrow.assign(nl, 0);
+    L.dlanes.assign(nl, 4);
     for (int32_t l = 0; l < nl; ++l) {
         const int32_t nb = L.cptr[l + 1] - L.cptr[l] - L.nsmall[l];
         L.narrow[l] = nb < kNarrowLevel ? 1 : 0;
-        const int32_t rows = L.narrow[l] ? 16 : 64;
+        bool has_pair = false;
+        for (int32_t q = L.cptr[l] + L.nsmall[l]; q < L.cptr[l + 1]; ++q) has_pair = has_pair || pofs[L.cblk[q]] >= 0;
+        L.dlanes[l] = !L.narrow[l] ? 4 : (has_pair ? 32 : 16);
+        const int32_t rows = 256 / L.dlanes[l];
         for (int32_t q = L.cptr[l] + L.nsmall[l]; q < L.cptr[l + 1]; ++q) {
             const int32_t k = L.cblk[q];
             const bool pr = pofs[k] >= 0;
@@ -823,7 +830,7 @@ void sweeps(spx_handle* h, const SweepBufs& w, int32_t nrhs, hipStream_t s)
         const int32_t* sm = h->lv_cblk.p + L.cptr[l];
         const int ns = L.nsmall[l];
         HIPCHK(launch_fwd_small(a, sm, ns, s));
-        HIPCHK(launch_fwd_diag(a, h->lv_ditem.p + L.dptr[l], L.dptr[l + 1] - L.dptr[l], L.narrow[l] != 0, s));
+        HIPCHK(launch_fwd_diag(a, h->lv_ditem.p + L.dptr[l], L.dptr[l + 1] - L.dptr[l], L.dlanes[l], s));
         HIPCHK(launch_fwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
     }
     HIPCHK(launch_fill_f64(w.tacc, static_cast<int64_t>(h->n) * nrhs, 0.0, s));
@@ -836,7 +843,7 @@ void sweeps(spx_handle* h, const SweepBufs& w, int32_t nrhs, hipStream_t s)
         if (L.narrow[l] && nrhs == 1)
             HIPCHK(launch_bwd_off(a, h->lv_bchunk.p + L.bptr[l], L.bptr[l + 1] - L.bptr[l], true, s));
         else HIPCHK(launch_bwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], false, s));
-        HIPCHK(launch_bwd_diag(a, h->lv_ditem.p + L.dptr[l], L.dptr[l + 1] - L.dptr[l], L.narrow[l] != 0, s));
+        HIPCHK(launch_bwd_diag(a, h->lv_ditem.p + L.dptr[l], L.dptr[l + 1] - L.dptr[l], L.dlanes[l], s));
         HIPCHK(launch_bwd_small(a, sm, ns, s));
     }
 }

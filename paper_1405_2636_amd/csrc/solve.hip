@@ -44,7 +44,7 @@ namespace spx {
 
 constexpr int kChunk = 64;     // off-diagonal rows per chunk of the level lists
 
-// sum over the LANES consecutive lanes of a group (LANES = 4 or 16)
+// sum over the LANES consecutive lanes of a group (LANES = 4, 16 or 32)
 template <int LANES>
 __device__ __forceinline__ double group_sum(double v)
 {
@@ -69,9 +69,9 @@ __device__ __forceinline__ double group_sum(double v)
 // column-major).  LANES lanes per row, one workgroup per item: the rows
 // r0 .. r0 + 256/LANES - 1 of one block; lane q of a row takes the
 // columns p = q, q+LANES, ..., sixteen loads at a time (p > row clamped and
-// multiplied by zero).  Narrow levels (few blocks) use 16 lanes: fewer
-// dependent load rounds; wide levels 4 (the items of a level are cut to
-// match).
+// multiplied by zero).  Narrow levels (few blocks) use 16 lanes, or 32 when
+// they hold a pair of pieces (a 512-wide inverse): fewer dependent load
+// rounds; wide levels 4 (the items of a level are cut to match).
 template <class T, int LANES, int NR>
 __global__ void __launch_bounds__(256) fwd_diag(SweepArgs a, const DiagItem* items)
 {
@@ -844,17 +844,17 @@ static int nr_block(int nrhs) { return nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : 8); }
         else { constexpr int NR = 8; CALL; } \
     } while (0)
 
-hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s)
+hipError_t launch_fwd_diag(const SweepArgs& a, const DiagItem* items, int count, int lanes, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     const int nrv = nr_block(a.nrhs);
-    if (narrow) {
-        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
-                                    : fwd_diag<double, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
-    } else {
-        SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
-                                    : fwd_diag<double, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
-    }
+    const dim3 grid(count, (a.nrhs + nrv - 1) / nrv);
+#define SPX_FD(L) SPX_NR_DISPATCH(nrv, (a.f32 ? fwd_diag<float, L, NR><<<grid, 256, 0, s>>>(a, items) \
+                                               : fwd_diag<double, L, NR><<<grid, 256, 0, s>>>(a, items)))
+    if (lanes == 32) SPX_FD(32);
+    else if (lanes == 16) SPX_FD(16);
+    else SPX_FD(4);
+#undef SPX_FD
     return hipGetLastError();
 }
 hipError_t launch_fwd_off(const SweepArgs& a, const OffItem* items, int count, hipStream_t s)
@@ -898,17 +898,17 @@ hipError_t launch_bwd_off(const SweepArgs& a, const OffItem* items, int count, b
     }
     return hipGetLastError();
 }
-hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count, bool narrow, hipStream_t s)
+hipError_t launch_bwd_diag(const SweepArgs& a, const DiagItem* items, int count, int lanes, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     const int nrv = nr_block(a.nrhs);
-    if (narrow) {
-        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
-                                    : bwd_diag<double, 16, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
-    } else {
-        SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)
-                                    : bwd_diag<double, 4, NR><<<dim3(count, (a.nrhs + NR - 1) / NR), 256, 0, s>>>(a, items)));
-    }
+    const dim3 grid(count, (a.nrhs + nrv - 1) / nrv);
+#define SPX_BD(L) SPX_NR_DISPATCH(nrv, (a.f32 ? bwd_diag<float, L, NR><<<grid, 256, 0, s>>>(a, items) \
+                                               : bwd_diag<double, L, NR><<<grid, 256, 0, s>>>(a, items)))
+    if (lanes == 32) SPX_BD(32);
+    else if (lanes == 16) SPX_BD(16);
+    else SPX_BD(4);
+#undef SPX_BD
     return hipGetLastError();
 }
 hipError_t launch_pair_inv(const void* panels, void* dinv, bool f32, bool ldlt, const PairItem* items, int count,
