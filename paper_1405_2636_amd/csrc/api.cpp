@@ -113,6 +113,8 @@ struct Level {
     std::vector<uint8_t> dlanes; // lanes per row of level l's diagonal items (4, 16 or 32; 256 / lanes rows each)
     std::vector<int32_t> kptr;   // off-diagonal items of level l: chunk[kptr[l]..kptr[l+1])
     std::vector<OffItem> chunk;
+    std::vector<int32_t> kptr1;  // one right-hand side: every chunk cut into 64-column items, chunk1[..]
+    std::vector<OffItem> chunk1;
     std::vector<int32_t> bptr;   // narrow levels: the backward sweep's own 256-row items, bchunk[bptr[l]..bptr[l+1])
     std::vector<OffItem> bchunk;
     std::vector<PairItem> pair;  // paired pieces (one unit of the sweeps each)
@@ -157,7 +159,7 @@ struct spx_handle {
     Level lv;
     DevBuf<int32_t> lv_cblk;
     DevBuf<DiagItem> lv_ditem;
-    DevBuf<OffItem> lv_chunk;
+    DevBuf<OffItem> lv_chunk, lv_chunk1;
     DevBuf<OffItem> lv_bchunk;
     DevBuf<PairItem> lv_pair;
     // numeric: FP64 panels and inverses, or their FP32 counterparts
@@ -671,9 +673,14 @@ void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::ve
     // into 64-column parts (as many as bring the level towards kOffTarget
     // workgroups): the top levels hold one or two column blocks, and one
     // workgroup per 64 rows would leave most compute units idle while each
-    // walks its columns serially.
+    // walks its columns serially.  One right-hand side takes its own list,
+    // every chunk in 64-column parts (each wave then walks 16 columns, one
+    // round of loads: 100^3 solve 3.43 -> 3.38 ms; with 8 right-hand sides,
+    // whose items do eight times the work per loaded entry, that list was
+    // slower, 6.71 -> 7.04 ms).
     constexpr int64_t kOffTarget = 1024;
     L.kptr.assign(nl + 1, 0);
+    L.kptr1.assign(nl + 1, 0);
     L.bptr.assign(nl + 1, 0);
     std::vector<int32_t> members;
     for (int32_t l = 0; l < nl; ++l) {
@@ -703,6 +710,16 @@ void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::ve
             }
         }
         L.kptr[l + 1] = static_cast<int32_t>(L.chunk.size());
+        for (int32_t k : members) {
+            const int32_t w = width(k);
+            for (int32_t r = first_row(k); r < P.stride[k]; r += 64) {
+                const int32_t nr = std::min(64, P.stride[k] - r);
+                for (int32_t c0 = 0; c0 < w; c0 += 64)
+                    L.chunk1.push_back(OffItem{P.panel_off[k] + r, rgo[k] + (r - w), P.stride[k], P.fcol[k], r,
+                                               c0 | (std::min(w, c0 + 64) << 9) | (nr << 18)});
+            }
+        }
+        L.kptr1[l + 1] = static_cast<int32_t>(L.chunk1.size());
         // the backward sweep on narrow levels: 256 rows by 16 columns
         if (L.narrow[l])
             for (int32_t k : members) {
@@ -719,6 +736,7 @@ void build_levels(spx_handle* h, const std::vector<int64_t>& doff, const std::ve
     h->lv_cblk.upload(L.cblk);
     h->lv_ditem.upload(L.ditem);
     h->lv_chunk.upload(L.chunk);
+    h->lv_chunk1.upload(L.chunk1);
     h->lv_bchunk.upload(L.bchunk);
     h->lv_pair.upload(L.pair);
 }
@@ -831,7 +849,8 @@ void sweeps(spx_handle* h, const SweepBufs& w, int32_t nrhs, hipStream_t s)
         const int ns = L.nsmall[l];
         HIPCHK(launch_fwd_small(a, sm, ns, s));
         HIPCHK(launch_fwd_diag(a, h->lv_ditem.p + L.dptr[l], L.dptr[l + 1] - L.dptr[l], L.dlanes[l], s));
-        HIPCHK(launch_fwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
+        if (nrhs == 1) HIPCHK(launch_fwd_off(a, h->lv_chunk1.p + L.kptr1[l], L.kptr1[l + 1] - L.kptr1[l], s));
+        else HIPCHK(launch_fwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], s));
     }
     HIPCHK(launch_fill_f64(w.tacc, static_cast<int64_t>(h->n) * nrhs, 0.0, s));
     for (int l = nl - 1; l >= 0; --l) {
@@ -842,6 +861,8 @@ void sweeps(spx_handle* h, const SweepBufs& w, int32_t nrhs, hipStream_t s)
         // than the atomics it saves)
         if (L.narrow[l] && nrhs == 1)
             HIPCHK(launch_bwd_off(a, h->lv_bchunk.p + L.bptr[l], L.bptr[l + 1] - L.bptr[l], true, s));
+        else if (nrhs == 1)
+            HIPCHK(launch_bwd_off(a, h->lv_chunk1.p + L.kptr1[l], L.kptr1[l + 1] - L.kptr1[l], false, s));
         else HIPCHK(launch_bwd_off(a, h->lv_chunk.p + L.kptr[l], L.kptr[l + 1] - L.kptr[l], false, s));
         HIPCHK(launch_bwd_diag(a, h->lv_ditem.p + L.dptr[l], L.dptr[l + 1] - L.dptr[l], L.dlanes[l], s));
         HIPCHK(launch_bwd_small(a, sm, ns, s));
